@@ -1,0 +1,956 @@
+/*
+ * CPU oracle for the Monte Carlo projection step of gDRR (Jia et al., "A GPU
+ * tool for efficient, accurate, and realistic simulation of cone beam CT
+ * projections", arXiv:1204.6367).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, double-precision
+ * restatement of what the method computes, used by the tests, by the smoke
+ * check and by the benchmark's CPU-baseline leg to judge the GPU library.  The
+ * product path never links, loads or calls it, and it shares no code, header
+ * or table with the GPU library: the two meet only in the seeded input arrays.
+ *
+ * What it follows:
+ *   Sec. 2.1  geometry (source S at SAD, angle phi; detector normal to OP at
+ *             AID, angle theta; (u,v) frame at P with v parallel to z), the
+ *             voxel phantom (material index + density), the mass attenuation
+ *             tables mu_k(i,E) (k = Rayleigh, Compton, photoelectric), the
+ *             spectrum phi(E) and fluence map w(u) as normalised pdfs, and the
+ *             detector response r(E).
+ *   Sec. 2.3  Eq. 1 (Beer-Lambert primary), evaluated here *exactly* for the
+ *             trilinear / voxel-constant density model as a check of the MC.
+ *   Sec. 2.4  the MC: one history at a time -- source photon from spectrum and
+ *             fluence map, Woodcock (delta) tracking, photoelectric absorption
+ *             terminates, Compton and Rayleigh angles from their differential
+ *             cross sections, escape -> geometric detector hit -> r(E) added
+ *             to the primary or the scatter counter by the scatter indicator;
+ *             density tri-linearly interpolated at the photon's position.
+ *   Sec. 2.6  tallies normalised per source photon.
+ * Readings where the paper is silent (conventions, the random-number layout,
+ * the samplers, the majorant) are the ones listed in the design notes and are
+ * restated beside the code that implements them.
+ *
+ * Everything is double precision.  Inputs arrive as float32 / uint8 arrays
+ * and are widened on read.  OpenMP splits the photon-index range into fixed
+ * chunks; per-thread tallies are reduced in thread order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_ME_C2_KEV 510.99895
+#define OR_HC_KEV_A 12.398419843
+#define OR_MAX_TRIES 256
+#define OR_MAX_STEPS (1 << 20)
+
+enum { OR_PRIMARY = 0, OR_SCATTER = 1, OR_ABSORBED = 2, OR_CUT = 3, OR_MISSED = 4, OR_LOST = 5 };
+
+/* Problem description (the oracle's own layout; plain host arrays). */
+typedef struct {
+    int32_t nx, ny, nz;
+    double dx, dy, dz;                 /* mm */
+    const float* density;              /* [nz][ny][nx] g/cm^3 */
+    const uint8_t* material;           /* [nz][ny][nx] */
+    int32_t n_mat, n_e;
+    double e0, de;                     /* energy grid E_j = e0 + j de, keV */
+    const float* mu;                   /* [n_mat][n_e][3] cm^2/g: Rayleigh, Compton, photo */
+    const float* response;             /* [n_e] keV, or NULL for r(E) = E */
+    double x0_rayleigh;                /* form-factor scale, 1/Angstrom */
+    double e_cut;                      /* keV */
+    int32_t n_spec;
+    const float* spec_e;               /* [n_spec] keV */
+    const float* spec_p;               /* [n_spec] */
+    const float* fluence;              /* [nv][nu] */
+    double sad, aid, phi, theta;       /* mm, rad */
+    int32_t nu, nv;
+    double du, dv;                     /* mm */
+} or_problem;
+
+/* ------------------------------------------------------------------------ */
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as   */
+/* easy as 1, 2, 3", SC'11): ten rounds of two 32x32->64 multiplies with the */
+/* round keys advanced by the Weyl constants between rounds.                 */
+/* ------------------------------------------------------------------------ */
+void or_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)x0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)x2;
+        uint32_t y0 = (uint32_t)(p1 >> 32) ^ x1 ^ k0;
+        uint32_t y1 = (uint32_t)p1;
+        uint32_t y2 = (uint32_t)(p0 >> 32) ^ x3 ^ k1;
+        uint32_t y3 = (uint32_t)p0;
+        x0 = y0; x1 = y1; x2 = y2; x3 = y3;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+/* Uniform in (0,1) from 23 random bits: odd multiples of 2^-24, exact in
+ * both float32 and float64. */
+static double u24(uint32_t x) { return ((double)(x >> 9) + 0.5) * (1.0 / 8388608.0); }
+
+/* Uniform in [0,1) from 53 random bits of two words, exact in float64. */
+static double u53(uint32_t a, uint32_t b)
+{
+    uint64_t k = ((uint64_t)a << 21) | (uint64_t)(b >> 11);
+    return (double)k * (1.0 / 9007199254740992.0);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sampling from a tabulated pdf: inverse CDF.  C_k = S_k / S_{n-1} with     */
+/* S_k the running sum (in index order) of the non-negative weights; the     */
+/* sampled index is the smallest k with u < C_k.                             */
+/* ------------------------------------------------------------------------ */
+static int build_cdf(const float* w, int n, double* cdf)
+{
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) {
+        double x = (double)w[k];
+        if (!(x >= 0.0) || isinf(x)) return -1;
+        s += x;
+        cdf[k] = s;
+    }
+    if (!(s > 0.0)) return -1;
+    for (int k = 0; k < n; ++k) cdf[k] = cdf[k] / s;
+    return 0;
+}
+
+static int cdf_search(const double* cdf, int n, double u)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = lo + (hi - lo) / 2;
+        if (u < cdf[mid]) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+/* Tests: sample indices for given uniforms. */
+int or_sample_cdf(const float* w, int32_t n, const double* u, int64_t m, int32_t* out)
+{
+    double* cdf = (double*)malloc(sizeof(double) * (size_t)n);
+    if (!cdf) return -1;
+    if (build_cdf(w, n, cdf)) { free(cdf); return -1; }
+    for (int64_t i = 0; i < m; ++i) out[i] = cdf_search(cdf, n, u[i]);
+    free(cdf);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Geometry, Sec. 2.1: the source S rotates in the xOy plane at distance SAD */
+/* with phi the angle from +x to SO; the detector is perpendicular to xOy    */
+/* and to OP, at distance AID, with theta the angle from SO to OP (counter-  */
+/* clockwise); (u, v) has its origin at P and v along +z; u = z x n.         */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    double S[3], P[3], n[3], eu[3], ev[3];
+    double lo[3], hi[3], vs[3];
+    int nvox[3];
+    double* cdf_e;
+    double* cdf_f;
+    const double* mbar;                /* [n_e - 1], 1/cm */
+    uint32_t key[2];
+    uint32_t job;
+    int interp;
+} or_ctx;
+
+static void setup_geometry(const or_problem* p, or_ctx* c)
+{
+    double cp = cos(p->phi), sp = sin(p->phi);
+    double cq = cos(p->phi + p->theta), sq = sin(p->phi + p->theta);
+    c->S[0] = -p->sad * cp; c->S[1] = -p->sad * sp; c->S[2] = 0.0;
+    c->n[0] = cq; c->n[1] = sq; c->n[2] = 0.0;
+    c->P[0] = p->aid * cq; c->P[1] = p->aid * sq; c->P[2] = 0.0;
+    c->eu[0] = -sq; c->eu[1] = cq; c->eu[2] = 0.0;
+    c->ev[0] = 0.0; c->ev[1] = 0.0; c->ev[2] = 1.0;
+    c->nvox[0] = p->nx; c->nvox[1] = p->ny; c->nvox[2] = p->nz;
+    c->vs[0] = p->dx; c->vs[1] = p->dy; c->vs[2] = p->dz;
+    for (int a = 0; a < 3; ++a) {
+        c->lo[a] = -0.5 * c->nvox[a] * c->vs[a];
+        c->hi[a] = 0.5 * c->nvox[a] * c->vs[a];
+    }
+}
+
+static double dot3(const double* a, const double* b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+/* Slab-method intersection of the ray x + t d (t >= 0) with the phantom box. */
+static int box_entry(const or_ctx* c, const double* x, const double* d, double* tin, double* tout)
+{
+    double t0 = 0.0, t1 = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0) {
+            if (x[a] < c->lo[a] || x[a] > c->hi[a]) return 0;
+            continue;
+        }
+        double ta = (c->lo[a] - x[a]) / d[a];
+        double tb = (c->hi[a] - x[a]) / d[a];
+        if (ta > tb) { double t = ta; ta = tb; tb = t; }
+        if (ta > t0) t0 = ta;
+        if (tb < t1) t1 = tb;
+    }
+    if (!(t0 < t1)) return 0;
+    *tin = t0; *tout = t1;
+    return 1;
+}
+
+/* Distance from a point inside the box to its boundary along d. */
+static double box_exit(const or_ctx* c, const double* x, const double* d)
+{
+    double t = INFINITY;
+    for (int a = 0; a < 3; ++a) {
+        double ta = INFINITY;
+        if (d[a] > 0.0) ta = (c->hi[a] - x[a]) / d[a];
+        else if (d[a] < 0.0) ta = (c->lo[a] - x[a]) / d[a];
+        if (ta < t) t = ta;
+    }
+    return t < 0.0 ? 0.0 : t;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Material tables, Sec. 2.1/2.3: mu(x,E) = rho(x) * sum_k mu_k(i(x), E).     */
+/* The tables are linear in E between grid points.                           */
+/* ------------------------------------------------------------------------ */
+static int e_interval(const or_problem* p, double E, double* f)
+{
+    double g = (E - p->e0) / p->de;
+    int j = (int)floor(g);
+    if (j < 0) j = 0;
+    if (j > p->n_e - 2) j = p->n_e - 2;
+    *f = g - (double)j;
+    return j;
+}
+
+static void xs_at(const or_problem* p, int m, double E, double mu3[3])
+{
+    double f;
+    int j = e_interval(p, E, &f);
+    const float* a = p->mu + ((size_t)m * p->n_e + j) * 3;
+    const float* b = a + 3;
+    for (int k = 0; k < 3; ++k) mu3[k] = (double)a[k] + f * ((double)b[k] - (double)a[k]);
+}
+
+static double response_at(const or_problem* p, double E)
+{
+    if (!p->response) return E;
+    double f;
+    int j = e_interval(p, E, &f);
+    return (double)p->response[j] + f * ((double)p->response[j + 1] - (double)p->response[j]);
+}
+
+static int clampi(int i, int lo, int hi) { return i < lo ? lo : (i > hi ? hi : i); }
+
+static size_t vidx(const or_problem* p, int ix, int iy, int iz)
+{
+    return ((size_t)iz * p->ny + iy) * p->nx + ix;
+}
+
+/* Containing voxel (clamped so rounding at the faces stays inside). */
+static size_t containing_voxel(const or_problem* p, const or_ctx* c, const double* x)
+{
+    int i[3];
+    for (int a = 0; a < 3; ++a)
+        i[a] = clampi((int)floor((x[a] - c->lo[a]) / c->vs[a]), 0, c->nvox[a] - 1);
+    return vidx(p, i[0], i[1], i[2]);
+}
+
+/* Trilinear stencil of Sec. 2.4: density on the lattice of voxel centres,
+ * clamped to the edge voxels outside the outermost centres.  Fills the eight
+ * corner voxel indices and weights; returns rho(x). */
+static double trilinear(const or_problem* p, const or_ctx* c, const double* x,
+                        size_t vox[8], double wt[8])
+{
+    int i0[3], i1[3];
+    double f[3];
+    for (int a = 0; a < 3; ++a) {
+        double g = (x[a] - c->lo[a]) / c->vs[a] - 0.5;
+        int k = (int)floor(g);
+        f[a] = g - (double)k;
+        i0[a] = clampi(k, 0, c->nvox[a] - 1);
+        i1[a] = clampi(k + 1, 0, c->nvox[a] - 1);
+    }
+    double rho = 0.0;
+    int n = 0;
+    for (int bz = 0; bz < 2; ++bz)
+        for (int by = 0; by < 2; ++by)
+            for (int bx = 0; bx < 2; ++bx) {
+                double w = (bx ? f[0] : 1.0 - f[0]) * (by ? f[1] : 1.0 - f[1]) * (bz ? f[2] : 1.0 - f[2]);
+                size_t v = vidx(p, bx ? i1[0] : i0[0], by ? i1[1] : i0[1], bz ? i1[2] : i0[2]);
+                vox[n] = v; wt[n] = w; ++n;
+                rho += w * (double)p->density[v];
+            }
+    return rho;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Woodcock majorant: for each energy interval [E_j, E_j+1), the largest     */
+/* attenuation any position can show, times (1 + 2^-20).  With interpolation */
+/* on, a position's density mixes the 2x2x2 centres around it, all inside    */
+/* the 3x3x3 neighbourhood of its containing voxel (whose material it takes),*/
+/* so rho_max(m) is the 3x3x3-neighbourhood maximum over voxels of m.        */
+/* ------------------------------------------------------------------------ */
+int or_majorant(const or_problem* p, int32_t interp, double* out)
+{
+    double rmax[256];
+    int present[256];
+    if (p->n_mat < 1 || p->n_mat > 256 || p->n_e < 2) return -1;
+    for (int m = 0; m < 256; ++m) { rmax[m] = 0.0; present[m] = 0; }
+    for (int iz = 0; iz < p->nz; ++iz)
+        for (int iy = 0; iy < p->ny; ++iy)
+            for (int ix = 0; ix < p->nx; ++ix) {
+                size_t v = vidx(p, ix, iy, iz);
+                int m = p->material[v];
+                if (m >= p->n_mat) return -1;
+                double r = (double)p->density[v];
+                if (!(r >= 0.0) || isinf(r)) return -1;
+                if (interp) {
+                    for (int dz = -1; dz <= 1; ++dz)
+                        for (int dy = -1; dy <= 1; ++dy)
+                            for (int dx = -1; dx <= 1; ++dx) {
+                                size_t w = vidx(p, clampi(ix + dx, 0, p->nx - 1),
+                                                clampi(iy + dy, 0, p->ny - 1),
+                                                clampi(iz + dz, 0, p->nz - 1));
+                                double q = (double)p->density[w];
+                                if (q > r) r = q;
+                            }
+                }
+                if (r > rmax[m]) rmax[m] = r;
+                present[m] = 1;
+            }
+    for (int j = 0; j < p->n_e - 1; ++j) {
+        double best = 0.0;
+        for (int m = 0; m < p->n_mat; ++m) {
+            if (!present[m]) continue;
+            const float* a = p->mu + ((size_t)m * p->n_e + j) * 3;
+            double t0 = (double)a[0] + (double)a[1] + (double)a[2];
+            double t1 = (double)a[3] + (double)a[4] + (double)a[5];
+            double t = rmax[m] * (t0 > t1 ? t0 : t1);
+            if (t > best) best = t;
+        }
+        out[j] = best * (1.0 + 1.0 / 1048576.0);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Random-number layout: block (photon i, job, step, sub) under key = seed.  */
+/* step 0 = source; step k >= 1 = k-th free flight; sub 0 = the flight's     */
+/* own four uniforms, sub 1 + t = the t-th try of an angular sampler.        */
+/* ------------------------------------------------------------------------ */
+static void rblock(const or_ctx* c, uint32_t i, uint32_t step, uint32_t sub, uint32_t x[4])
+{
+    uint32_t ctr[4] = { i, c->job, step, sub };
+    or_philox(ctr, c->key, x);
+}
+
+/* Compton scattering, free-electron Klein-Nishina.  With kappa = E/mc^2 and
+ * tau = E'/E in [tau0, 1], tau0 = 1/(1+2 kappa), the KN density in tau is
+ * proportional to (1/tau + tau)(1 - tau sin^2/(1+tau^2)).  It is sampled as a
+ * mixture of the densities 1/tau (weight ln(1/tau0)) and tau (weight
+ * (1-tau0^2)/2), then accepted with probability 1 - tau sin^2/(1+tau^2). */
+static void compton(const or_ctx* c, uint32_t i, uint32_t step, double E, double* tau_out, double* cos_out)
+{
+    double k = E / OR_ME_C2_KEV;
+    double tau0 = 1.0 / (1.0 + 2.0 * k);
+    double a1 = log(1.0 + 2.0 * k);
+    double a2 = 0.5 * (1.0 - tau0 * tau0);
+    for (uint32_t t = 0; t < OR_MAX_TRIES; ++t) {
+        uint32_t x[4];
+        rblock(c, i, step, 1 + t, x);
+        double b0 = u24(x[0]), b1 = u24(x[1]), b2 = u24(x[2]);
+        double tau;
+        if (b0 * (a1 + a2) < a1) tau = exp(-a1 * b1);
+        else tau = sqrt(tau0 * tau0 + (1.0 - tau0 * tau0) * b1);
+        double cost = 1.0 - (1.0 - tau) / (k * tau);
+        double sin2 = (1.0 - cost) * (1.0 + cost);
+        double g = 1.0 - tau * sin2 / (1.0 + tau * tau);
+        if (b2 <= g) { *tau_out = tau; *cos_out = cost; return; }
+    }
+    *tau_out = 1.0; *cos_out = 1.0;
+}
+
+/* Rayleigh scattering with form factor F(x) = Z exp(-x/x0), x = sin(theta/2)/
+ * lambda in [0, 1/lambda]: the density in x is proportional to
+ * (1 + cos^2) x exp(-2x/x0) with cos = 1 - 2 (lambda x)^2.  Above
+ * 1/lambda >= x0, x is drawn from Gamma(2, x0/2) and rejected beyond
+ * 1/lambda; below, x is drawn with density ~ x on [0, 1/lambda] and kept with
+ * probability exp(-2x/x0).  Either way it is then kept with probability
+ * (1 + cos^2)/2. */
+static double rayleigh(const or_ctx* c, uint32_t i, uint32_t step, double E, double x0)
+{
+    double xmax = E / OR_HC_KEV_A;
+    for (uint32_t t = 0; t < OR_MAX_TRIES; ++t) {
+        uint32_t x[4];
+        rblock(c, i, step, 1 + t, x);
+        double b0 = u24(x[0]), b1 = u24(x[1]), b2 = u24(x[2]);
+        double xx;
+        if (xmax >= x0) {
+            xx = -0.5 * x0 * log(b0 * b1);
+            if (xx > xmax) continue;
+        } else {
+            xx = xmax * sqrt(b0);
+            if (b1 > exp(-2.0 * xx / x0)) continue;
+        }
+        double r = xx / xmax;
+        double cost = 1.0 - 2.0 * r * r;
+        if (b2 <= 0.5 * (1.0 + cost * cost)) return cost;
+    }
+    return 1.0;
+}
+
+/* New direction at polar angle theta (cosine `cost`) and azimuth `ph` about
+ * d: d' = cos(theta) d + sin(theta) (cos(ph) e1 + sin(ph) e2) with (e1, e2, d)
+ * an orthonormal frame.  Away from the z axis e2 = (z x d)/|z x d| =
+ * (-dy, dx, 0)/r and e1 = e2 x d = (dx dz, dy dz, -r^2)/r, r = |(dx, dy)|;
+ * within 0.1 rad of it the frame is built on x instead: e2 = (x x d)/q =
+ * (0, -dz, dy)/q and e1 = e2 x d = (-q^2, dx dy, dx dz)/q, q = |(dy, dz)|.
+ * The result is renormalised. */
+void or_rotate(const double d[3], double cost, double ph, double out[3])
+{
+    double sint = sqrt(fmax(0.0, 1.0 - cost * cost));
+    double cph = cos(ph), sph = sin(ph);
+    double e1[3], e2[3];
+    double r = sqrt(d[0] * d[0] + d[1] * d[1]);
+    if (r > 0.1) {
+        e2[0] = -d[1] / r; e2[1] = d[0] / r; e2[2] = 0.0;
+        e1[0] = d[0] * d[2] / r; e1[1] = d[1] * d[2] / r; e1[2] = -r;
+    } else {
+        double q = sqrt(d[1] * d[1] + d[2] * d[2]);
+        e2[0] = 0.0; e2[1] = -d[2] / q; e2[2] = d[1] / q;
+        e1[0] = -q; e1[1] = d[0] * d[1] / q; e1[2] = d[0] * d[2] / q;
+    }
+    double o[3];
+    for (int a = 0; a < 3; ++a) o[a] = cost * d[a] + sint * (cph * e1[a] + sph * e2[a]);
+    double nrm = sqrt(dot3(o, o));
+    out[0] = o[0] / nrm; out[1] = o[1] / nrm; out[2] = o[2] / nrm;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One history, Sec. 2.4.                                                    */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int cls;
+    int pixel;
+    double e_src, e_final, recoil;
+    int steps, n_real, n_compton, n_rayleigh;
+} or_outcome;
+
+/* Visitor for tentative collisions inside the phantom (for the adjoint). */
+typedef struct {
+    double weight;          /* W of the history; 0 => no visit */
+    double* grad;           /* [nz][ny][nx] */
+} or_visit;
+
+static void visit(const or_problem* p, const or_ctx* c, or_visit* vis, const double* x,
+                  int real, double rho, double tot, double mbar)
+{
+    /* Score-function terms of delta tracking, the majorant held fixed:
+     * real:  d log(rho mu_k / mbar)       / d rho_v = w_v / rho
+     * null:  d log(1 - rho mu_tot / mbar) / d rho_v = -mu_tot w_v / (mbar - rho mu_tot) */
+    size_t vox[8];
+    double wt[8];
+    if (c->interp) {
+        trilinear(p, c, x, vox, wt);
+        for (int n = 0; n < 8; ++n) {
+            double s = real ? wt[n] / rho : -tot * wt[n] / (mbar - rho * tot);
+            vis->grad[vox[n]] += vis->weight * s;
+        }
+    } else {
+        size_t v = containing_voxel(p, c, x);
+        double s = real ? 1.0 / rho : -tot / (mbar - rho * tot);
+        vis->grad[v] += vis->weight * s;
+    }
+}
+
+static void history(const or_problem* p, const or_ctx* c, uint32_t i, or_outcome* o, or_visit* vis)
+{
+    uint32_t x[4];
+    rblock(c, i, 0, 0, x);
+    int ke = cdf_search(c->cdf_e, p->n_spec, u53(x[0], x[1]));
+    int kf = cdf_search(c->cdf_f, p->nu * p->nv, u53(x[2], x[3]));
+    int iu = kf % p->nu, iv = kf / p->nu;
+    rblock(c, i, 0, 1, x);
+    double ju = u24(x[0]), jv = u24(x[1]);
+    double E = (double)p->spec_e[ke];
+    o->e_src = E; o->recoil = 0.0;
+    o->steps = 0; o->n_real = 0; o->n_compton = 0; o->n_rayleigh = 0;
+
+    /* aim point D on the detector, uniform within the sampled pixel */
+    double uc = ((double)iu + ju - 0.5 * p->nu) * p->du;
+    double vc = ((double)iv + jv - 0.5 * p->nv) * p->dv;
+    double pos[3], dir[3];
+    for (int a = 0; a < 3; ++a) dir[a] = c->P[a] + uc * c->eu[a] + vc * c->ev[a] - c->S[a];
+    double nd = sqrt(dot3(dir, dir));
+    for (int a = 0; a < 3; ++a) { dir[a] /= nd; pos[a] = c->S[a]; }
+
+    int scattered = 0;
+    double tin, tout;
+    if (box_entry(c, pos, dir, &tin, &tout)) {
+        for (int a = 0; a < 3; ++a) pos[a] += tin * dir[a];
+        double trem = tout - tin;
+        for (uint32_t step = 1;; ++step) {
+            if (step > OR_MAX_STEPS) { o->cls = OR_LOST; o->pixel = -1; o->e_final = E; return; }
+            o->steps = (int)step;
+            rblock(c, i, step, 0, x);
+            double r0 = u24(x[0]), r1 = u24(x[1]), r2 = u24(x[2]), r3 = u24(x[3]);
+            double f;
+            int j = e_interval(p, E, &f);
+            double mbar = c->mbar[j];
+            double s = -log(r0) / (0.1 * mbar);              /* mm; mbar in 1/cm */
+            if (s >= trem) break;                             /* leaves the phantom */
+            for (int a = 0; a < 3; ++a) pos[a] += s * dir[a];
+            trem -= s;
+            size_t v = containing_voxel(p, c, pos);
+            int m = p->material[v];
+            double rho;
+            if (c->interp) { size_t vv[8]; double ww[8]; rho = trilinear(p, c, pos, vv, ww); }
+            else rho = (double)p->density[v];
+            double mu3[3];
+            xs_at(p, m, E, mu3);
+            double tot = mu3[0] + mu3[1] + mu3[2];
+            double mu = rho * tot;
+            int real = r1 * mbar < mu;
+            if (vis) visit(p, c, vis, pos, real, rho, tot, mbar);
+            if (!real) continue;                              /* null collision */
+            o->n_real++;
+            double sel = r2 * tot;
+            double cost;
+            if (sel < mu3[0]) {                               /* Rayleigh: E unchanged */
+                cost = rayleigh(c, i, step, E, p->x0_rayleigh);
+                o->n_rayleigh++;
+            } else if (sel < mu3[0] + mu3[1]) {               /* Compton */
+                double tau;
+                compton(c, i, step, E, &tau, &cost);
+                o->recoil += E - tau * E;
+                E = tau * E;
+                o->n_compton++;
+            } else {                                          /* photoelectric: history ends */
+                o->cls = OR_ABSORBED; o->pixel = -1; o->e_final = E;
+                return;
+            }
+            double nd2[3];
+            or_rotate(dir, cost, 2.0 * M_PI * r3, nd2);
+            dir[0] = nd2[0]; dir[1] = nd2[1]; dir[2] = nd2[2];
+            scattered = 1;
+            if (E < p->e_cut) { o->cls = OR_CUT; o->pixel = -1; o->e_final = E; return; }
+            trem = box_exit(c, pos, dir);
+        }
+    }
+    o->e_final = E;
+    if (!scattered) {                   /* straight line to the sampled aim point */
+        o->cls = OR_PRIMARY;
+        o->pixel = iv * p->nu + iu;
+        return;
+    }
+    /* vacuum outside the phantom: straight line to the detector plane */
+    double dn = dot3(dir, c->n);
+    if (dn > 0.0) {
+        double w[3];
+        for (int a = 0; a < 3; ++a) w[a] = c->P[a] - pos[a];
+        double t = dot3(w, c->n) / dn;
+        if (t >= 0.0) {
+            double h[3];
+            for (int a = 0; a < 3; ++a) h[a] = pos[a] + t * dir[a] - c->P[a];
+            double fu = dot3(h, c->eu) / p->du + 0.5 * p->nu;
+            double fv = dot3(h, c->ev) / p->dv + 0.5 * p->nv;
+            double ku = floor(fu), kv = floor(fv);
+            if (ku >= 0.0 && ku < p->nu && kv >= 0.0 && kv < p->nv) {
+                o->cls = OR_SCATTER;
+                o->pixel = (int)kv * p->nu + (int)ku;
+                return;
+            }
+        }
+    }
+    o->cls = OR_MISSED;
+    o->pixel = -1;
+}
+
+/* ------------------------------------------------------------------------ */
+static int validate(const or_problem* p)
+{
+    if (!p || p->nx < 1 || p->ny < 1 || p->nz < 1) return -1;
+    if (!(p->dx > 0 && p->dy > 0 && p->dz > 0)) return -1;
+    if (!p->density || !p->material || !p->mu || !p->spec_e || !p->spec_p || !p->fluence) return -1;
+    if (p->n_mat < 1 || p->n_mat > 256 || p->n_e < 2 || !(p->de > 0)) return -1;
+    if (p->n_spec < 1 || p->nu < 1 || p->nv < 1 || !(p->du > 0 && p->dv > 0)) return -1;
+    double emax = p->e0 + p->de * (p->n_e - 1);
+    for (int k = 0; k < p->n_spec; ++k)
+        if (!(p->spec_e[k] >= p->e0 && p->spec_e[k] <= emax)) return -1;
+    if (!(p->e_cut >= p->e0)) return -1;
+    /* the phantom must lie on the source side of the detector plane */
+    double rxy = sqrt(0.25 * (p->nx * p->dx) * (p->nx * p->dx) + 0.25 * (p->ny * p->dy) * (p->ny * p->dy));
+    if (!(rxy < p->aid) || !(rxy < p->sad)) return -1;
+    return 0;
+}
+
+static int make_ctx(const or_problem* p, uint64_t seed, uint32_t job, int interp,
+                    const double* mbar, or_ctx* c)
+{
+    memset(c, 0, sizeof(*c));
+    setup_geometry(p, c);
+    c->cdf_e = (double*)malloc(sizeof(double) * (size_t)p->n_spec);
+    c->cdf_f = (double*)malloc(sizeof(double) * (size_t)p->nu * p->nv);
+    if (!c->cdf_e || !c->cdf_f) return -1;
+    if (build_cdf(p->spec_p, p->n_spec, c->cdf_e)) return -1;
+    if (build_cdf(p->fluence, p->nu * p->nv, c->cdf_f)) return -1;
+    c->mbar = mbar;
+    c->key[0] = (uint32_t)seed;
+    c->key[1] = (uint32_t)(seed >> 32);
+    c->job = job;
+    c->interp = interp;
+    return 0;
+}
+
+static void free_ctx(or_ctx* c) { free(c->cdf_e); free(c->cdf_f); }
+
+#define OR_CHUNK 4096
+
+/* Type-specific scatter tally (Sec. 2.4 offers e.g. first-order Compton):
+ * mode 0 counts every scattered photon, mode 1 only photons scattered exactly
+ * once (Compton or Rayleigh), mode 2 only photons scattered exactly once by
+ * Compton.  The primary tally is the same in every mode. */
+static int counts_as_scatter(const or_outcome* o, int mode)
+{
+    if (mode == 1) return o->n_compton + o->n_rayleigh == 1;
+    if (mode == 2) return o->n_compton == 1 && o->n_rayleigh == 0;
+    return 1;
+}
+
+/*
+ * The MC projection: n photons with ids 0..n-1 of job `job` under `seed`.
+ * tally [4][nv][nu]: sum r(E), sum r(E)^2 over primary hits, then the same
+ * over scatter hits, each divided by n (per source photon).  Optional
+ * per-history outputs (any may be NULL): cls, pixel, e_final, steps,
+ * n_compton, n_rayleigh.  `mode` selects the scatter tally (above).  stats[12] (optional): totals of steps, real events,
+ * Compton, Rayleigh, histories per class [6], source energy, final energy of
+ * non-absorbed photons + absorbed energy, recoil energy.
+ * `mbar` NULL => the majorant is computed here.
+ */
+int or_mc_project(const or_problem* p, uint64_t seed, uint64_t n, uint32_t job, int32_t interp,
+                  int32_t mode, const double* mbar_in, double* tally, int8_t* cls, int32_t* pixel, double* e_final,
+                  int32_t* steps, int32_t* n_compton, int32_t* n_rayleigh, double* stats, int32_t nthreads)
+{
+    if (validate(p) || !tally || n > 0xFFFFFFFFull) return -1;
+    double* mb = NULL;
+    if (!mbar_in) {
+        mb = (double*)malloc(sizeof(double) * (size_t)(p->n_e - 1));
+        if (!mb || or_majorant(p, interp, mb)) { free(mb); return -1; }
+    }
+    or_ctx c;
+    if (make_ctx(p, seed, job, interp, mbar_in ? mbar_in : mb, &c)) { free_ctx(&c); free(mb); return -1; }
+    size_t npix = (size_t)p->nu * p->nv;
+    int nt = 1;
+#ifdef _OPENMP
+    nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+    double* part = (double*)calloc((size_t)nt * 4 * npix, sizeof(double));
+    double* st = (double*)calloc((size_t)nt * 16, sizeof(double));
+    if (!part || !st) { free(part); free(st); free_ctx(&c); free(mb); return -1; }
+    uint64_t nchunks = (n + OR_CHUNK - 1) / OR_CHUNK;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+    {
+        int t = 0;
+#ifdef _OPENMP
+        t = omp_get_thread_num();
+#endif
+        double* my = part + (size_t)t * 4 * npix;
+        double* ms = st + (size_t)t * 16;
+        for (uint64_t ch = (uint64_t)t; ch < nchunks; ch += (uint64_t)nt) {
+            uint64_t a = ch * OR_CHUNK, b = a + OR_CHUNK < n ? a + OR_CHUNK : n;
+            for (uint64_t i = a; i < b; ++i) {
+                or_outcome o;
+                history(p, &c, (uint32_t)i, &o, NULL);
+                if (o.cls == OR_PRIMARY || (o.cls == OR_SCATTER && counts_as_scatter(&o, mode))) {
+                    double r = response_at(p, o.e_final);
+                    size_t base = (o.cls == OR_PRIMARY ? 0 : 2) * npix + (size_t)o.pixel;
+                    my[base] += r;
+                    my[base + npix] += r * r;
+                }
+                if (cls) cls[i] = (int8_t)o.cls;
+                if (pixel) pixel[i] = o.pixel;
+                if (e_final) e_final[i] = o.e_final;
+                if (steps) steps[i] = o.steps;
+                if (n_compton) n_compton[i] = o.n_compton;
+                if (n_rayleigh) n_rayleigh[i] = o.n_rayleigh;
+                ms[0] += o.steps; ms[1] += o.n_real; ms[2] += o.n_compton; ms[3] += o.n_rayleigh;
+                ms[4 + o.cls] += 1.0;
+                ms[10] += o.e_src; ms[11] += o.e_final + o.recoil;
+            }
+        }
+    }
+    double inv = n ? 1.0 / (double)n : 0.0;
+    for (size_t k = 0; k < 4 * npix; ++k) {
+        double s = 0.0;
+        for (int t = 0; t < nt; ++t) s += part[(size_t)t * 4 * npix + k];
+        tally[k] = s * inv;
+    }
+    if (stats)
+        for (int k = 0; k < 12; ++k) {
+            double s = 0.0;
+            for (int t = 0; t < nt; ++t) s += st[t * 16 + k];
+            stats[k] = s;
+        }
+    free(part); free(st); free_ctx(&c); free(mb);
+    return 0;
+}
+
+/*
+ * Adjoint by path replay.  For a loss L(T) with adj = dL/dT over the primary
+ * and scatter tallies ([2][nv][nu]), adds to grad[nz][ny][nx] the estimate
+ *   dL/drho_v = (1/n) sum_i adj[c_i][p_i] r(E_i) sum_{events e of i} s_e(v)
+ * with the score-function terms s_e of the visitor above.  Each history is run
+ * once to find its outcome and, when its weight is non-zero, once more with
+ * the same random numbers to visit its collisions.  `mbar` must be the
+ * majorant of the forward run (it is held fixed under differentiation).
+ */
+int or_mc_backward(const or_problem* p, uint64_t seed, uint64_t n, uint32_t job, int32_t interp,
+                   int32_t mode, const double* mbar, const double* adj, double* grad, int32_t nthreads)
+{
+    if (validate(p) || !mbar || !adj || !grad || n > 0xFFFFFFFFull) return -1;
+    or_ctx c;
+    if (make_ctx(p, seed, job, interp, mbar, &c)) { free_ctx(&c); return -1; }
+    size_t npix = (size_t)p->nu * p->nv;
+    size_t nvox = (size_t)p->nx * p->ny * p->nz;
+    int nt = 1;
+#ifdef _OPENMP
+    nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+    double* part = (double*)calloc((size_t)nt * nvox, sizeof(double));
+    if (!part) { free_ctx(&c); return -1; }
+    uint64_t nchunks = (n + OR_CHUNK - 1) / OR_CHUNK;
+    double inv = n ? 1.0 / (double)n : 0.0;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(nt)
+#endif
+    {
+        int t = 0;
+#ifdef _OPENMP
+        t = omp_get_thread_num();
+#endif
+        or_visit vis;
+        vis.grad = part + (size_t)t * nvox;
+        for (uint64_t ch = (uint64_t)t; ch < nchunks; ch += (uint64_t)nt) {
+            uint64_t a = ch * OR_CHUNK, b = a + OR_CHUNK < n ? a + OR_CHUNK : n;
+            for (uint64_t i = a; i < b; ++i) {
+                or_outcome o;
+                history(p, &c, (uint32_t)i, &o, NULL);
+                if (o.cls != OR_PRIMARY && !(o.cls == OR_SCATTER && counts_as_scatter(&o, mode))) continue;
+                double w = adj[(o.cls == OR_PRIMARY ? 0 : 1) * npix + (size_t)o.pixel]
+                           * response_at(p, o.e_final) * inv;
+                if (w == 0.0) continue;
+                vis.weight = w;
+                history(p, &c, (uint32_t)i, &o, &vis);
+            }
+        }
+    }
+    for (size_t k = 0; k < nvox; ++k) {
+        double s = 0.0;
+        for (int t = 0; t < nt; ++t) s += part[(size_t)t * nvox + k];
+        grad[k] += s;
+    }
+    free(part); free_ctx(&c);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Eq. 1, evaluated exactly for the density model the MC samples.  Along a  */
+/* line, the containing voxel (hence the material) changes only at voxel     */
+/* faces and the trilinear cell (and the clamping) only at the planes of     */
+/* voxel centres; between consecutive such planes rho is a polynomial of     */
+/* degree <= 3 in the arc length, so two-point Gauss-Legendre integrates it  */
+/* exactly.  rho_int[m] receives the integral of rho over the pieces of      */
+/* material m (mm * g/cm^3), so that int mu dl = 0.1 sum_m mu_tot(m,E)       */
+/* rho_int[m] in dimensionless units.                                        */
+/* ------------------------------------------------------------------------ */
+static int cmp_double(const void* a, const void* b)
+{
+    double x = *(const double*)a, y = *(const double*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+int or_rho_integrals(const or_problem* p, int32_t interp, const double* a, const double* b, double* rho_int)
+{
+    or_ctx c;
+    memset(&c, 0, sizeof(c));
+    setup_geometry(p, &c);
+    c.interp = interp;
+    for (int m = 0; m < p->n_mat; ++m) rho_int[m] = 0.0;
+    double d[3];
+    for (int k = 0; k < 3; ++k) d[k] = b[k] - a[k];
+    double len = sqrt(dot3(d, d));
+    if (!(len > 0.0)) return 0;
+    for (int k = 0; k < 3; ++k) d[k] /= len;
+    double tin, tout;
+    if (!box_entry(&c, a, d, &tin, &tout)) return 0;
+    if (tout > len) tout = len;
+    if (!(tin < tout)) return 0;
+    int cap = 2 * (2 * (p->nx + p->ny + p->nz) + 3) + 2;
+    double* br = (double*)malloc(sizeof(double) * (size_t)cap);
+    if (!br) return -1;
+    int nb = 0;
+    br[nb++] = tin;
+    br[nb++] = tout;
+    for (int ax = 0; ax < 3; ++ax) {
+        if (d[ax] == 0.0) continue;
+        for (int h = 0; h <= 2 * c.nvox[ax]; ++h) {          /* faces and centres */
+            double plane = c.lo[ax] + 0.5 * h * c.vs[ax];
+            double t = (plane - a[ax]) / d[ax];
+            if (t > tin && t < tout) br[nb++] = t;
+        }
+    }
+    qsort(br, (size_t)nb, sizeof(double), cmp_double);
+    const double gq = 0.5 / sqrt(3.0);
+    for (int k = 0; k + 1 < nb; ++k) {
+        double t0 = br[k], t1 = br[k + 1];
+        if (!(t1 > t0)) continue;
+        double mid[3], x[3];
+        for (int q = 0; q < 3; ++q) mid[q] = a[q] + 0.5 * (t0 + t1) * d[q];
+        int m = p->material[containing_voxel(p, &c, mid)];
+        double acc = 0.0;
+        for (int g = -1; g <= 1; g += 2) {
+            double t = 0.5 * (t0 + t1) + g * gq * (t1 - t0);
+            for (int q = 0; q < 3; ++q) x[q] = a[q] + t * d[q];
+            if (interp) { size_t vv[8]; double ww[8]; acc += trilinear(p, &c, x, vv, ww); }
+            else acc += (double)p->density[containing_voxel(p, &c, x)];
+        }
+        rho_int[m] += 0.5 * (t1 - t0) * acc;
+    }
+    free(br);
+    return 0;
+}
+
+/*
+ * Expected primary tally E[P_hat] per pixel ([nv][nu], per source photon):
+ *   sum_j phi_j W_p r(E_j) <exp(-int mu dl)>_p
+ * where phi_j, W_p are the normalised spectrum and fluence weights and <.>_p
+ * averages over the pixel (the aim point is uniform inside it) with an
+ * nq x nq Gauss-Legendre rule.
+ */
+int or_primary_exact(const or_problem* p, int32_t interp, int32_t nq, double* out)
+{
+    if (validate(p) || nq < 1 || nq > 64) return -1;
+    or_ctx c;
+    memset(&c, 0, sizeof(c));
+    setup_geometry(p, &c);
+    /* Gauss-Legendre nodes/weights on [0,1] by Newton iteration on P_nq */
+    double gx[64], gw[64];
+    for (int k = 0; k < nq; ++k) {
+        double z = cos(M_PI * (k + 0.75) / (nq + 0.5));
+        for (int it = 0; it < 100; ++it) {
+            double p0 = 1.0, p1 = 0.0;
+            for (int l = 1; l <= nq; ++l) { double p2 = p1; p1 = p0; p0 = ((2 * l - 1) * z * p1 - (l - 1) * p2) / l; }
+            double dp = nq * (z * p0 - p1) / (z * z - 1.0);
+            double dz = p0 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-15) break;
+        }
+        double p0 = 1.0, p1 = 0.0;
+        for (int l = 1; l <= nq; ++l) { double p2 = p1; p1 = p0; p0 = ((2 * l - 1) * z * p1 - (l - 1) * p2) / l; }
+        double dp = nq * (z * p0 - p1) / (z * z - 1.0);
+        gx[k] = 0.5 * (1.0 - z);
+        gw[k] = 1.0 / ((1.0 - z * z) * dp * dp);
+    }
+    double sp = 0.0, sf = 0.0;
+    for (int k = 0; k < p->n_spec; ++k) sp += p->spec_p[k];
+    for (int k = 0; k < p->nu * p->nv; ++k) sf += p->fluence[k];
+    double* ri = (double*)malloc(sizeof(double) * (size_t)p->n_mat);
+    double* muj = (double*)malloc(sizeof(double) * (size_t)p->n_spec * p->n_mat);
+    if (!ri || !muj) { free(ri); free(muj); return -1; }
+    for (int k = 0; k < p->n_spec; ++k)
+        for (int m = 0; m < p->n_mat; ++m) {
+            double mu3[3];
+            xs_at(p, m, p->spec_e[k], mu3);
+            muj[(size_t)k * p->n_mat + m] = mu3[0] + mu3[1] + mu3[2];
+        }
+    for (int iv = 0; iv < p->nv; ++iv)
+        for (int iu = 0; iu < p->nu; ++iu) {
+            double acc = 0.0;
+            for (int qa = 0; qa < nq; ++qa)
+                for (int qb = 0; qb < nq; ++qb) {
+                    double uc = ((double)iu + gx[qa] - 0.5 * p->nu) * p->du;
+                    double vc = ((double)iv + gx[qb] - 0.5 * p->nv) * p->dv;
+                    double D[3];
+                    for (int q = 0; q < 3; ++q) D[q] = c.P[q] + uc * c.eu[q] + vc * c.ev[q];
+                    if (or_rho_integrals(p, interp, c.S, D, ri)) { free(ri); free(muj); return -1; }
+                    double e_sum = 0.0;
+                    for (int k = 0; k < p->n_spec; ++k) {
+                        double li = 0.0;
+                        for (int m = 0; m < p->n_mat; ++m) li += muj[(size_t)k * p->n_mat + m] * ri[m];
+                        e_sum += (p->spec_p[k] / sp) * response_at(p, p->spec_e[k]) * exp(-0.1 * li);
+                    }
+                    acc += gw[qa] * gw[qb] * e_sum;
+                }
+            out[iv * p->nu + iu] = (p->fluence[iv * p->nu + iu] / sf) * acc;
+        }
+    free(ri); free(muj);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Sampler access for the tests: n draws at energy E, photon ids 0..n-1,     */
+/* step 1, the same try layout as in transport.                              */
+/* ------------------------------------------------------------------------ */
+int or_sample_compton(double E, uint64_t seed, uint64_t n, double* cost, double* tau)
+{
+    or_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.key[0] = (uint32_t)seed; c.key[1] = (uint32_t)(seed >> 32);
+    for (uint64_t i = 0; i < n; ++i) compton(&c, (uint32_t)i, 1, E, &tau[i], &cost[i]);
+    return 0;
+}
+
+int or_sample_rayleigh(double E, double x0, uint64_t seed, uint64_t n, double* cost)
+{
+    or_ctx c;
+    memset(&c, 0, sizeof(c));
+    c.key[0] = (uint32_t)seed; c.key[1] = (uint32_t)(seed >> 32);
+    for (uint64_t i = 0; i < n; ++i) cost[i] = rayleigh(&c, (uint32_t)i, 1, E, x0);
+    return 0;
+}
+
+/* Geometry frame for the tests: S, P, n, eu, ev (15 doubles). */
+void or_geometry(const or_problem* p, double* out15)
+{
+    or_ctx c;
+    memset(&c, 0, sizeof(c));
+    setup_geometry(p, &c);
+    for (int k = 0; k < 3; ++k) {
+        out15[k] = c.S[k]; out15[3 + k] = c.P[k]; out15[6 + k] = c.n[k];
+        out15[9 + k] = c.eu[k]; out15[12 + k] = c.ev[k];
+    }
+}
+
+/* Trilinear density at points (tests). */
+int or_density_at(const or_problem* p, int32_t interp, const double* xyz, int64_t m, double* out)
+{
+    or_ctx c;
+    memset(&c, 0, sizeof(c));
+    setup_geometry(p, &c);
+    for (int64_t k = 0; k < m; ++k) {
+        const double* x = xyz + 3 * k;
+        if (interp) { size_t vv[8]; double ww[8]; out[k] = trilinear(p, &c, x, vv, ww); }
+        else out[k] = (double)p->density[containing_voxel(p, &c, x)];
+    }
+    return 0;
+}
+
+/* Batched form of or_rho_integrals: segments a -> b[k], k < m; out [m][n_mat]. */
+int or_rho_integrals_many(const or_problem* p, int32_t interp, const double* a, const double* b,
+                          int64_t m, double* out)
+{
+    int bad = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(static) reduction(|:bad)
+#endif
+    for (int64_t k = 0; k < m; ++k)
+        bad |= or_rho_integrals(p, interp, a, b + 3 * k, out + (size_t)k * p->n_mat) != 0;
+    return bad ? -1 : 0;
+}

@@ -1,0 +1,414 @@
+"""Pins of the oracle's transport against what the paper and the mathematics fix:
+Eq. 1 (Beer-Lambert primary) in closed form and by brute force, the
+geometry conventions of Sec. 2.1, the unbiasedness of Woodcock tracking for any
+majorant, the interpolation identity on homogeneous media, energy
+bookkeeping, the single-scatter integral and the symmetry of the sphere.
+CPU only."""
+import math
+
+import numpy as np
+import pytest
+from scipy import ndimage
+
+from paper_1204_6367_amd import workloads as W
+
+ME = 510.99895
+HC = 12.398419843
+
+
+def make(phantom, geom, spec=(np.array([60.0], np.float32), np.array([1.0], np.float32)),
+         fluence=None, response=None, phys_grid=W.EnergyGrid(), oracle_lib=None):
+    import oracle
+    mu = W.cross_section_table(phantom.materials, phys_grid)
+    if fluence is None:
+        fluence = W.fluence_map(geom)
+    return oracle.Problem(phantom.density, phantom.material, phantom.spacing_mm, mu,
+                          phys_grid.e0_kev, phys_grid.de_kev, spec[0], spec[1], fluence,
+                          geom.sad_mm, geom.aid_mm, geom.phi_rad, geom.theta_rad,
+                          geom.nu, geom.nv, geom.du_mm, geom.dv_mm, response=response)
+
+
+def zscores(t, t2, n, expect):
+    var = np.maximum(t2 - t * t, 0.0) / n
+    return (t - expect) / np.sqrt(np.maximum(var, 1e-300))
+
+
+def geo_frame(phi, theta, sad, aid):
+    """Sec. 2.1 in words: S on the -SO side at distance SAD with SO at angle phi
+    from +x; OP at angle theta from SO (counter-clockwise seen from +z); u along
+    z x n, v along z."""
+    so = np.array([math.cos(phi), math.sin(phi), 0.0])
+    n = np.array([math.cos(phi + theta), math.sin(phi + theta), 0.0])
+    S = -sad * so
+    P = aid * n
+    eu = np.cross([0.0, 0.0, 1.0], n)
+    return S, P, n, eu, np.array([0.0, 0.0, 1.0])
+
+
+def test_geometry_frame_follows_section_2_1(oracle_lib):
+    ph = W.box_phantom((4, 4, 4), (2.0, 2.0, 2.0))
+    for phi, theta in [(0.0, 0.0), (0.5 * math.pi, 0.0), (1.0, 0.3), (4.0, -0.2)]:
+        g = W.Geometry(phi_rad=phi, theta_rad=theta, nu=8, nv=6)
+        p = make(ph, g)
+        fr = oracle_lib.geometry(p)
+        S, P, n, eu, ev = geo_frame(phi, theta, g.sad_mm, g.aid_mm)
+        for k, v in dict(S=S, P=P, n=n, eu=eu, ev=ev).items():
+            assert np.allclose(fr[k], v, atol=1e-9), k
+        # |SO| = SAD, |OP| = AID, angle(SO, OP) = theta, v parallel to z
+        assert abs(np.linalg.norm(fr["S"]) - g.sad_mm) < 1e-9
+        assert abs(np.linalg.norm(fr["P"]) - g.aid_mm) < 1e-9
+        so = -fr["S"] / g.sad_mm
+        op = fr["P"] / g.aid_mm
+        assert abs(math.atan2(np.cross(so, op)[2], so @ op) - theta) < 1e-9
+
+
+@pytest.mark.parametrize("phi,obj,uv", [
+    (0.0, (0.0, 30.0, 20.0), (45.0, 30.0)),             # source at -x: +y -> +u
+    (0.5 * math.pi, (-30.0, 0.0, -20.0), (45.0, -30.0)), # source at -y: -x -> +u
+])
+def test_shadow_lands_where_the_geometry_says(oracle_lib, phi, obj, uv):
+    """A bone cube off the axis casts its shadow at magnification SDD/SAD."""
+    n, d = 40, 2.5
+    ph = W.box_phantom((n, n, n), (d, d, d), material="air", density=0.0)
+    ph = W.Phantom(ph.density, ph.material, ph.spacing_mm, ["air", "bone"])
+    c = ((np.arange(n) + 0.5) - n / 2) * d
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    cube = (abs(X - obj[0]) < 5) & (abs(Y - obj[1]) < 5) & (abs(Z - obj[2]) < 5)
+    ph.material[cube] = 1
+    ph.density[cube] = 1.85
+    g = W.Geometry(phi_rad=phi, nu=64, nv=48, du_mm=4.0, dv_mm=4.0)
+    p = make(ph, g)
+    prim = oracle_lib.primary_exact(p, interp=False, nq=2)
+    deficit = 1.0 - prim / (60.0 * W.fluence_map(g))          # 1 - transmission
+    assert deficit.max() > 0.3
+    uc = (np.arange(g.nu) + 0.5 - g.nu / 2) * g.du_mm
+    vc = (np.arange(g.nv) + 0.5 - g.nv / 2) * g.dv_mm
+    u = (deficit.sum(0) * uc).sum() / deficit.sum()
+    v = (deficit.sum(1) * vc).sum() / deficit.sum()
+    assert abs(u - uv[0]) < 1.0 and abs(v - uv[1]) < 1.0
+
+
+def box_chords(S, D, half):
+    """Chord length of segments S->D through the box |x_a| <= half_a (numpy)."""
+    d = D - S
+    L = np.linalg.norm(d, axis=-1)
+    d = d / L[..., None]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t1 = (-half - S) / d
+        t2 = (half - S) / d
+    tn = np.nanmax(np.minimum(t1, t2), axis=-1)
+    tf = np.nanmin(np.maximum(t1, t2), axis=-1)
+    tn = np.maximum(tn, 0.0)
+    tf = np.minimum(tf, L)
+    return np.maximum(tf - tn, 0.0)
+
+
+def beer_lambert_expectation(geom, half, mu_per_mm, fluence, nq=8):
+    S, P, n, eu, ev = geo_frame(geom.phi_rad, geom.theta_rad, geom.sad_mm, geom.aid_mm)
+    t, w = np.polynomial.legendre.leggauss(nq)
+    g = 0.5 * (t + 1)
+    w = w / 2
+    out = np.zeros((geom.nv, geom.nu))
+    for iv in range(geom.nv):
+        for iu in range(geom.nu):
+            uc = (iu + g[:, None] - geom.nu / 2) * geom.du_mm
+            vc = (iv + g[None, :] - geom.nv / 2) * geom.dv_mm
+            D = P + uc[..., None] * eu + vc[..., None] * ev
+            L = box_chords(S, D, half)
+            out[iv, iu] = (np.exp(-mu_per_mm * L) * w[:, None] * w[None, :]).sum()
+    f = fluence.astype(np.float64)
+    return out * f / f.sum()
+
+
+@pytest.mark.parametrize("e_kev", [60.0, 47.3])
+def test_beer_lambert_homogeneous_box(oracle_lib, e_kev):
+    """Eq. 1 for a homogeneous water box, mono-energetic: E[P_hat_p] =
+    W_p E <exp(-mu L)>_p, L the chord length; both the exact integrator and
+    the MC primary.  47.3 keV lies between table points (linear in E)."""
+    ph = W.box_phantom((10, 12, 8), (6.0, 5.0, 7.0), "water", 1.0)
+    g = W.Geometry(phi_rad=0.4, nu=16, nv=12, du_mm=8.0, dv_mm=8.0)
+    p = make(ph, g, spec=(np.array([e_kev], np.float32), np.array([1.0], np.float32)))
+    half = 0.5 * np.array([8 * 6.0, 12 * 5.0, 10 * 7.0])      # (nx dx, ny dy, nz dz)
+    tab = W.cross_section_table(["water"])[0].astype(np.float64).sum(-1)
+    mu = 0.1 * np.interp(float(np.float32(e_kev)), W.EnergyGrid().energies(), tab)   # 1/mm
+    want = float(np.float32(e_kev)) * beer_lambert_expectation(g, half, mu, p.fluence, nq=24)
+    exact = oracle_lib.primary_exact(p, interp=True, nq=24)
+    assert np.allclose(exact, want, rtol=1e-9, atol=0)
+    n = 2_000_000
+    r = oracle_lib.mc_project(p, seed=5, n=n)
+    z = zscores(r["tally"][0], r["tally"][1], n, want)
+    assert np.abs(z).max() < 4.5
+    assert abs((z**2).mean() - 1.0) < 0.35
+
+
+def random_phantom(shape, spacing, seed):
+    rng = np.random.default_rng(seed)
+    mats = ["air", "water", "bone"]
+    m = rng.integers(0, 3, shape).astype(np.uint8)
+    base = np.array([0.0012, 1.0, 1.85])
+    dens = (base[m] * rng.uniform(0.6, 1.4, shape)).astype(np.float32)
+    return W.Phantom(dens, m, spacing, mats)
+
+
+def brute_rho_integrals(ph, a, b, interp, npts=400000):
+    """Midpoint Riemann sum of rho along a->b, split by material, using
+    scipy.ndimage.map_coordinates for the trilinear lattice (mode 'nearest' =
+    clamp to the edge voxels)."""
+    nz, ny, nx = ph.density.shape
+    sp = np.array(ph.spacing_mm)
+    lo = -0.5 * np.array([nx, ny, nz]) * sp
+    t = (np.arange(npts) + 0.5) / npts
+    x = a[None, :] + t[:, None] * (b - a)[None, :]
+    g = (x - lo) / sp                                 # voxel units, (x, y, z)
+    inside = np.all((g >= 0) & (g < [nx, ny, nz]), axis=1)
+    x, g = x[inside], g[inside]
+    iv = np.floor(g).astype(int)
+    mat = ph.material[iv[:, 2], iv[:, 1], iv[:, 0]]
+    if interp:
+        coords = np.stack([g[:, 2] - 0.5, g[:, 1] - 0.5, g[:, 0] - 0.5])
+        rho = ndimage.map_coordinates(ph.density.astype(np.float64), coords, order=1, mode="nearest")
+    else:
+        rho = ph.density[iv[:, 2], iv[:, 1], iv[:, 0]].astype(np.float64)
+    dl = np.linalg.norm(b - a) / npts
+    return np.array([rho[mat == k].sum() * dl for k in range(len(ph.materials))])
+
+
+@pytest.mark.parametrize("interp", [True, False])
+def test_exact_line_integral_matches_brute_force(oracle_lib, interp):
+    ph = random_phantom((7, 6, 5), (4.0, 5.0, 6.0), seed=9)
+    g = W.Geometry(nu=8, nv=6)
+    p = make(ph, g)
+    rng = np.random.default_rng(10)
+    for _ in range(6):
+        a = rng.uniform(-40, 40, 3)
+        b = rng.uniform(-40, 40, 3)
+        a[rng.integers(3)] = -60.0                    # start outside the box
+        got = oracle_lib.rho_integrals(p, a, b, interp)
+        want = brute_rho_integrals(ph, a, b, interp)
+        assert np.allclose(got, want, rtol=2e-3, atol=2e-3)
+
+
+@pytest.mark.parametrize("interp", [True, False])
+def test_mc_primary_matches_exact_eq1(oracle_lib, interp):
+    """E[P_hat] of the MC equals Eq. 1 for the same density model, poly-energetic."""
+    ph = random_phantom((12, 12, 12), (5.0, 5.0, 5.0), seed=11)
+    g = W.Geometry(phi_rad=0.7, nu=16, nv=12, du_mm=8.0, dv_mm=8.0)
+    spec = (np.array([30.0, 45.5, 60.0, 80.0, 110.0], np.float32),
+            np.array([0.1, 0.3, 0.3, 0.2, 0.1], np.float32))
+    p = make(ph, g, spec=spec)
+    want = oracle_lib.primary_exact(p, interp=interp, nq=32)   # pixel average converged
+    n = 2_000_000
+    r = oracle_lib.mc_project(p, seed=3, n=n, interp=interp)
+    z = zscores(r["tally"][0], r["tally"][1], n, want)
+    assert np.abs(z).max() < 4.5
+    assert abs((z**2).mean() - 1.0) < 0.35
+
+
+def test_majorant_bounds_attenuation_everywhere(oracle_lib):
+    """mu(x, E) = rho(x) mu_tot(m(x), E) never exceeds the majorant of E's
+    interval, at random positions and energies, including a phantom whose
+    light high-Z voxels touch dense low-Z ones (the interpolated density of a
+    bone voxel then exceeds every bone voxel's own density)."""
+    rng = np.random.default_rng(31)
+    ph1 = random_phantom((6, 7, 8), (5.0, 5.0, 5.0), seed=12)
+    m2 = (rng.random((6, 7, 8)) < 0.5).astype(np.uint8)          # 0 water, 1 bone
+    d2 = np.where(m2 == 0, 3.0, 0.3).astype(np.float32)
+    ph2 = W.Phantom(d2, m2, (5.0, 5.0, 5.0), ["water", "bone"])
+    grid = W.EnergyGrid()
+    eg = grid.energies()
+    for ph in (ph1, ph2):
+        p = make(ph, W.Geometry(nu=8, nv=6))
+        tab = p.mu.astype(np.float64).sum(-1)                      # [m][E]
+        nz, ny, nx = ph.density.shape
+        sp = np.array(ph.spacing_mm)
+        ext = 0.5 * np.array([nx, ny, nz]) * sp
+        x = rng.uniform(-ext, ext, (20000, 3))
+        for interp in (True, False):
+            mb = oracle_lib.majorant(p, interp)
+            rho = oracle_lib.density_at(p, x, interp)
+            iv = np.clip(np.floor((x + ext) / sp).astype(int), 0, [nx - 1, ny - 1, nz - 1])
+            m = ph.material[iv[:, 2], iv[:, 1], iv[:, 0]]
+            e = rng.uniform(eg[0], eg[-1], len(x))
+            j = np.clip(np.floor((e - eg[0]) / grid.de_kev).astype(int), 0, len(eg) - 2)
+            mut = np.array([np.interp(e[k], eg, tab[m[k]]) for k in range(len(x))])
+            assert np.all(rho * mut <= mb[j])
+
+
+def test_mc_primary_unbiased_when_light_bone_touches_dense_water(oracle_lib):
+    rng = np.random.default_rng(32)
+    m2 = (rng.random((10, 10, 10)) < 0.5).astype(np.uint8)
+    d2 = np.where(m2 == 0, 1.5, 0.2).astype(np.float32)
+    ph = W.Phantom(d2, m2, (5.0, 5.0, 5.0), ["water", "bone"])
+    g = W.Geometry(phi_rad=0.2, nu=16, nv=12, du_mm=8.0, dv_mm=8.0)
+    p = make(ph, g)
+    want = oracle_lib.primary_exact(p, interp=True, nq=32)
+    n = 1_000_000
+    r = oracle_lib.mc_project(p, seed=8, n=n)
+    z = zscores(r["tally"][0], r["tally"][1], n, want)
+    assert np.abs(z).max() < 4.5
+    assert abs((z**2).mean() - 1.0) < 0.35
+
+
+def test_interpolation_changes_heterogeneous_primary(oracle_lib):
+    """The two density models differ on a heterogeneous phantom (power check)."""
+    ph = random_phantom((12, 12, 12), (5.0, 5.0, 5.0), seed=11)
+    g = W.Geometry(phi_rad=0.7, nu=16, nv=12, du_mm=8.0, dv_mm=8.0)
+    p = make(ph, g)
+    a = oracle_lib.primary_exact(p, interp=True, nq=4)
+    b = oracle_lib.primary_exact(p, interp=False, nq=4)
+    assert np.abs(a - b).max() > 0.01 * a.max()
+
+
+def test_woodcock_is_unbiased_for_any_majorant(oracle_lib):
+    """Doubling the majorant changes every path but not the expected tallies."""
+    pr = W.sphere_problem()
+    p = oracle_lib.Problem.from_workload(pr)
+    mb = oracle_lib.majorant(p)
+    n = 1_000_000
+    a = oracle_lib.mc_project(p, 1, n, majorant_tab=mb)
+    b = oracle_lib.mc_project(p, 2, n, majorant_tab=2.0 * mb)
+    assert b["stats"]["steps"] > 1.5 * a["stats"]["steps"]
+    for k in (0, 2):
+        ta, tb = a["tally"][k], b["tally"][k]
+        va = np.maximum(a["tally"][k + 1] - ta**2, 0) / n
+        vb = np.maximum(b["tally"][k + 1] - tb**2, 0) / n
+        # 8x8 pooled bins
+        pool = lambda x: x.reshape(6, 8, 8, 8).sum(axis=(1, 3))
+        z = (pool(ta) - pool(tb)) / np.sqrt(pool(va) + pool(vb))
+        assert np.abs(z).max() < 4.0
+        tot = (ta.sum() - tb.sum()) / math.sqrt(va.sum() + vb.sum())
+        assert abs(tot) < 4.0
+
+
+def test_interpolation_is_identity_on_homogeneous_medium(oracle_lib):
+    ph = W.box_phantom((9, 8, 7), (5.0, 5.0, 5.0), "water", 1.0)
+    g = W.Geometry(nu=16, nv=12, du_mm=8.0, dv_mm=8.0)
+    p = make(ph, g)
+    a = oracle_lib.mc_project(p, 4, 200000, interp=True)
+    b = oracle_lib.mc_project(p, 4, 200000, interp=False)
+    assert np.array_equal(a["tally"], b["tally"])
+
+
+def test_energy_bookkeeping_and_classes(oracle_lib):
+    pr = W.sphere_problem()
+    p = oracle_lib.Problem.from_workload(pr)
+    n = 200000
+    r = oracle_lib.mc_project(p, 1, n, trace=True)
+    st = r["stats"]
+    assert sum(st["classes"].values()) == n
+    assert abs(st["e_src"] - st["e_out"]) <= 1e-12 * st["e_src"]
+    assert st["e_src"] == 60.0 * n
+    # per-history trace agrees with the tally
+    npix = p.nu * p.nv
+    for cls, k in ((0, 0), (1, 2)):
+        sel = r["cls"] == cls
+        acc = np.bincount(r["pixel"][sel], weights=r["e_final"][sel], minlength=npix) / n
+        assert np.allclose(acc.reshape(p.nv, p.nu), r["tally"][k], rtol=1e-12, atol=1e-18)
+    # primaries keep their energy, scattered Compton photons lose some
+    assert np.all(r["e_final"][r["cls"] == 0] == 60.0)
+    sc = (r["cls"] == 1) & (r["n_compton"] > 0)
+    assert np.all(r["e_final"][sc] < 60.0)
+    assert np.all(r["e_final"][r["cls"] == 1] >= 60.0 / (1 + 2 * 60.0 / ME) ** r["n_compton"][r["cls"] == 1] - 1e-9)
+
+
+def test_sphere_symmetry(oracle_lib):
+    """The centred sphere and the centred source are symmetric under u -> -u and v -> -v."""
+    pr = W.sphere_problem()
+    p = oracle_lib.Problem.from_workload(pr)
+    n = 1_000_000
+    r = oracle_lib.mc_project(p, 7, n)
+    for k in (0, 2):
+        t, t2 = r["tally"][k], r["tally"][k + 1]
+        pool = lambda x: x.reshape(6, 8, 8, 8).sum(axis=(1, 3))
+        v = np.maximum(t2 - t * t, 0) / n
+        for flip in (lambda x: x[:, ::-1], lambda x: x[::-1, :]):
+            z = (pool(t) - pool(flip(t))) / np.sqrt(pool(v) + pool(flip(v)) + 1e-300)
+            assert np.abs(z).max() < 4.5
+
+
+# ---------------------------------------------------------------------------
+# Single scatter.  For a homogeneous box lit by a uniform field that covers its
+# shadow, the expected first-order scatter tally (photons scattered exactly
+# once, the paper's type-specific tally) is
+#   S1_q = int_box dV Phi(x) sum_{k=R,C} mu_k(E) int_q dA' cos(a')/|D'-x|^2
+#          p_k(cos t) T_out(x, D', E'_k) r(E'_k)
+# with Phi(x) = f |D-S|^2/cos(a) T_in(x, E) / |x-S|^2 the fluence per source
+# photon (f the aim-point density per area), p_k the angular pdf per sr.
+# ---------------------------------------------------------------------------
+def single_scatter_expectation(geom, half, table_grid, mu_tab, f_area, field_half, nvq=8, nq=4):
+    S, P, n, eu, ev = geo_frame(geom.phi_rad, geom.theta_rad, geom.sad_mm, geom.aid_mm)
+    E = 60.0
+    egrid = table_grid.energies()
+    mu_k = lambda e, k: 0.1 * np.interp(e, egrid, mu_tab[:, k].astype(np.float64))   # 1/mm
+    mu_t = lambda e: mu_k(e, 0) + mu_k(e, 1) + mu_k(e, 2)
+    kap = E / ME
+    kn = lambda c: (lambda Pq: Pq * Pq * (Pq + 1 / Pq - (1 - c * c)))(1 / (1 + kap * (1 - c)))
+    cg = np.linspace(-1, 1, 200001)
+    kn_norm = np.trapezoid(kn(cg), cg) * 2 * math.pi
+    lam = HC / E
+    ray = lambda c: (1 + c * c) * np.exp(-2 * np.sqrt(np.maximum(0, (1 - c) / 2)) / lam / W.RAYLEIGH_X0)
+    ray_norm = np.trapezoid(ray(cg), cg) * 2 * math.pi
+    tv, wv = np.polynomial.legendre.leggauss(nvq)
+    xs = [half[a] * tv for a in range(3)]
+    ws = [half[a] * wv for a in range(3)]
+    X, Y, Z = np.meshgrid(xs[0], xs[1], xs[2], indexing="ij")
+    WV = np.einsum("i,j,k->ijk", ws[0], ws[1], ws[2])
+    x = np.stack([X.ravel(), Y.ravel(), Z.ravel()], -1)             # [V,3]
+    wvol = WV.ravel()
+    # incoming: aim point D of the line S->x on the detector plane
+    dirin = x - S
+    rin = np.linalg.norm(dirin, axis=-1)
+    din = dirin / rin[:, None]
+    tD = ((P - S) @ n) / (din @ n)
+    D = S + tD[:, None] * din
+    uD, vD = (D - P) @ eu, (D - P) @ ev
+    assert np.all(np.abs(uD) < field_half) and np.all(np.abs(vD) < field_half)
+    cos_a = din @ n
+    p_omega = f_area * tD**2 / cos_a
+    Lin = box_chords(S, x, half)
+    phi = p_omega * np.exp(-mu_t(E) * Lin) / rin**2
+    tq, wq = np.polynomial.legendre.leggauss(nq)
+    gq, wq = 0.5 * (tq + 1), wq / 2
+    out = np.zeros((geom.nv, geom.nu))
+    for iv in range(geom.nv):
+        for iu in range(geom.nu):
+            uc = (iu + gq[:, None] - geom.nu / 2) * geom.du_mm
+            vc = (iv + gq[None, :] - geom.nv / 2) * geom.dv_mm
+            Dq = (P + uc[..., None] * eu + vc[..., None] * ev).reshape(-1, 3)      # [Q,3]
+            wa = (wq[:, None] * wq[None, :]).ravel() * geom.du_mm * geom.dv_mm
+            rel = Dq[None, :, :] - x[:, None, :]                                  # [V,Q,3]
+            r2 = (rel**2).sum(-1)
+            dout = rel / np.sqrt(r2)[..., None]
+            domega = (dout @ n) / r2 * wa[None, :]
+            c = np.einsum("vqk,vk->vq", dout, din)
+            # exit chord from x towards D'
+            Lout = box_chords(x[:, None, :] + 0 * rel, Dq[None, :, :] + 0 * rel, half)
+            e_c = E / (1 + kap * (1 - c))
+            comp = mu_k(E, 1) * kn(c) / kn_norm * np.exp(-mu_t(e_c) * Lout) * e_c
+            rayl = mu_k(E, 0) * ray(c) / ray_norm * np.exp(-mu_t(E) * Lout) * E
+            out[iv, iu] = (wvol[:, None] * phi[:, None] * domega * (comp + rayl)).sum()
+    return out
+
+
+def test_single_scatter_matches_integral(oracle_lib):
+    nvox, d = 8, 5.0
+    ph = W.box_phantom((nvox, nvox, nvox), (d, d, d), "water", 1.0)
+    g = W.Geometry(nu=16, nv=16, du_mm=40.0, dv_mm=40.0)
+    flu = np.zeros((16, 16), np.float32)
+    flu[7:9, 7:9] = 1.0                                     # 80 mm square field
+    grid = W.EnergyGrid()
+    p = make(ph, g, fluence=flu, phys_grid=grid)
+    half = np.full(3, 0.5 * nvox * d)
+    mu_tab = W.cross_section_table(["water"], grid)[0]
+    want = single_scatter_expectation(g, half, grid, mu_tab, 1.0 / (80.0 * 80.0), 40.0)
+    n = 4_000_000
+    r = oracle_lib.mc_project(p, seed=17, n=n, mode=1)
+    t, t2 = r["tally"][2], r["tally"][3]
+    z = zscores(t, t2, n, want)
+    assert np.abs(z).max() < 4.5
+    assert abs((z**2).mean() - 1.0) < 0.35
+    var_tot = np.maximum(t2 - t * t, 0).sum() / n
+    assert abs(t.sum() - want.sum()) < 4 * math.sqrt(var_tot) + 2e-3 * want.sum()
+    # the full scatter tally is larger (multiple scatter adds), so mode 1 is a real filter
+    r0 = oracle_lib.mc_project(p, seed=17, n=n, mode=0)
+    assert r0["tally"][2].sum() > 1.05 * t.sum()
