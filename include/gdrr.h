@@ -1,0 +1,225 @@
+/*
+ * gdrr.h -- C ABI of libgdrr, the MI355X (gfx950) Monte Carlo projection step
+ * of gDRR (Jia, Yan, Cervino, Folkerts, Jiang: "A GPU tool for efficient,
+ * accurate, and realistic simulation of cone beam CT projections",
+ * arXiv:1204.6367).
+ *
+ * The library computes Step 2 of the paper (Sec. 2.4): photon histories are
+ * generated from a spectrum and a fluence map (Sec. 2.1), tracked through a
+ * voxel phantom by Woodcock (delta) tracking with tri-linearly interpolated
+ * density, undergo photoelectric absorption, Compton (Klein-Nishina) and
+ * Rayleigh scattering, and, when they leave the phantom towards the detector,
+ * add r(E) to a primary or a scatter tally per pixel depending on whether they
+ * scattered.  Tallies are per source photon (Sec. 2.6).  It also offers the
+ * gradient of a loss of the tallies with respect to voxel densities (path
+ * replay of the same random numbers; not in the paper).
+ *
+ * Conventions (the paper leaves them open; these are the library's reading):
+ *  - lengths in mm, energies in keV, mass attenuation in cm^2/g, density in
+ *    g/cm^3;
+ *  - the phantom is centred on the isocentre O, x fastest: voxel (i,j,k) has
+ *    its centre at ((i + 1/2 - nx/2) dx, (j + 1/2 - ny/2) dy, (k + 1/2 - nz/2) dz)
+ *    and element k*ny*nx + j*nx + i;
+ *  - source S = -SAD (cos phi, sin phi, 0); detector normal
+ *    n = (cos(phi+theta), sin(phi+theta), 0); detector centre P = AID n;
+ *    u axis = z x n, v axis = z; pixel (iu, iv) covers
+ *    u in [(iu - nu/2) du, (iu + 1 - nu/2) du), likewise v; tallies are
+ *    [plane][nv][nu];
+ *  - the fluence map w(u) is given per detector pixel (an air-scan image);
+ *    the aim point is uniform inside the sampled pixel;
+ *  - the random numbers of photon i of job `job_id` under `seed` come from
+ *    Philox4x32-10 blocks with counter (i, job_id, step, sub) and key seed,
+ *    so results depend only on (seed, job_id, photon index) and the inputs.
+ *
+ * Memory: every array pointer inside the structs below, and every output
+ * array, is a DEVICE pointer owned by the caller; the struct pointers
+ * themselves are host pointers read during the call.  All calls are
+ * asynchronous on `stream` (a hipStream_t passed as void*; NULL = the null
+ * stream) and may be recorded into a HIP graph.  The library keeps no device
+ * memory between calls: scratch lives in the caller's workspace.
+ *
+ * Errors: functions return GDRR_OK (0) or a negative code; no exception
+ * crosses the ABI; gdrr_last_error() gives a message for the calling thread.
+ */
+#ifndef GDRR_H
+#define GDRR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GDRR_OK 0
+#define GDRR_EINVAL (-1)   /* invalid argument (message via gdrr_last_error) */
+#define GDRR_EHIP (-2)     /* HIP runtime / launch error */
+#define GDRR_ENOTSUP (-3)  /* valid but unsupported configuration */
+
+/* flags */
+#define GDRR_INTERP_DENSITY 1u     /* tri-linear density at the photon position (Sec. 2.4); else voxel-constant */
+#define GDRR_TALLY_SUMSQ 2u        /* also tally r(E)^2 (planes 1 and 3), for per-pixel variances */
+#define GDRR_ACCUMULATE 4u         /* add to the output tallies / gradient instead of overwriting them */
+#define GDRR_SCATTER_FIRST 8u      /* scatter tally counts only photons scattered exactly once (Sec. 2.4, type-specific tally) */
+#define GDRR_SCATTER_FIRST_COMPTON 16u /* ... only photons scattered exactly once, by Compton */
+
+#define GDRR_MAX_MATERIALS 16
+#define GDRR_MAX_VOLUMES 8
+#define GDRR_MAX_SOURCES 8
+
+/* Voxel phantom (Sec. 2.1): material index and density per voxel. */
+typedef struct gdrr_volume {
+    int32_t nx, ny, nz;
+    float dx_mm, dy_mm, dz_mm;
+    const float* density;      /* [nz][ny][nx] g/cm^3, finite and >= 0 */
+    const uint8_t* material;   /* [nz][ny][nx] indices < gdrr_physics.n_mat */
+} gdrr_volume;
+
+/* Mass attenuation tables mu_k(i, E) of Sec. 2.1 on the grid
+ * E_j = e0 + j de, j < n_e, linear in E between grid points; the detector
+ * response r(E) on the same grid. */
+typedef struct gdrr_physics {
+    int32_t n_mat, n_e;        /* 1 <= n_mat <= GDRR_MAX_MATERIALS, 2 <= n_e <= 1024 */
+    float e0_kev, de_kev;
+    const float* mu_mass;      /* [n_mat][n_e][3] cm^2/g: Rayleigh, Compton, photoelectric */
+    const float* response;     /* [n_e] keV deposited per photon of energy E_j, or NULL for r(E) = E;
+                                  values are clamped to [0, 1024] keV */
+    float rayleigh_x0_invA;    /* form factor F(x) = Z exp(-x/x0), x = sin(theta/2)/lambda, 1/Angstrom */
+    float e_cut_kev;           /* photons below this energy are absorbed locally; >= e0 */
+} gdrr_physics;
+
+/* Source of Sec. 2.1, defined after the bowtie: spectrum phi(E) and fluence
+ * map w(u); both are normalised by the library (weights need only be >= 0). */
+typedef struct gdrr_source {
+    int32_t n_spec;            /* 1 <= n_spec <= 4096 energy channels */
+    const float* spec_e_kev;   /* [n_spec] channel energies within the physics grid */
+    const float* spec_prob;    /* [n_spec] weights */
+    int32_t fu, fv;            /* fluence grid = the detector's pixel grid (fu = nu, fv = nv) */
+    const float* fluence;      /* [fv][fu] weights */
+} gdrr_source;
+
+/* Geometry of Sec. 2.1 (Fig. 1). */
+typedef struct gdrr_geometry {
+    float sad_mm, aid_mm;      /* source-axis and axis-imager distances */
+    float phi_rad, theta_rad;  /* gantry angle; imager angle from SO to OP */
+    int32_t nu, nv;            /* detector pixels */
+    float du_mm, dv_mm;
+} gdrr_geometry;
+
+/* One projection of a batch. */
+typedef struct gdrr_job {
+    int32_t volume;            /* index into the batch's volumes */
+    int32_t source;            /* index into the batch's sources */
+    gdrr_geometry geom;
+    uint64_t n_photons;        /* < 2^32 */
+    uint32_t job_id;           /* Philox counter word 1 */
+    uint32_t reserved;         /* must be 0 */
+    int64_t tally_offset;      /* element offset of this job's [4][nv][nu] block in `tallies` */
+} gdrr_job;
+
+/* Launch shape of the persistent kernel (0 = library default). */
+typedef struct gdrr_tuning {
+    int32_t block;             /* threads per workgroup: 64, 128, 256 or 512 */
+    int32_t blocks_per_cu;     /* workgroups per compute unit */
+    int32_t chunk;             /* photons handed to a wavefront at a time (multiple of 64) */
+    int32_t defer;             /* interactions/refills are served when >= defer lanes wait (1..64) */
+} gdrr_tuning;
+
+/*
+ * Woodcock majorant (the bound delta tracking needs, Sec. 2.4 [Woodcock]):
+ * out[j], j < n_e - 1, is the largest linear attenuation (1/cm) any position
+ * of `vol` can show for E in [E_j, E_j+1), times (1 + margin).  With
+ * GDRR_INTERP_DENSITY the density at a position mixes the voxel centres of
+ * the 3x3x3 neighbourhood of its containing voxel, whose material it takes,
+ * so each material's bound uses that neighbourhood's maximum density.
+ * margin >= 2^-20 keeps the bound valid under float32 rounding; the adjoint
+ * needs a larger one (0.05 - 0.2) for a bounded variance.
+ * Workspace: gdrr_majorant_workspace() bytes.
+ */
+int gdrr_majorant(const gdrr_volume* vol, const gdrr_physics* phys, uint32_t flags, float margin,
+                  float* out, void* workspace, size_t ws_bytes, void* stream);
+size_t gdrr_majorant_workspace(void);
+
+/*
+ * One projection (Sec. 2.4): n_photons histories, photon indices
+ * 0..n_photons-1 of job `job_id`.  `majorant` (device, [n_e-1], 1/cm) may be
+ * NULL: the library then computes it with margin 2^-20 into the workspace.
+ * tally [4][nv][nu] (double, per source photon): primary sum of r(E), its
+ * sum of squares, scatter sum of r(E), its sum of squares (the squares only
+ * with GDRR_TALLY_SUMSQ, else those planes are left untouched).
+ * Workspace: gdrr_mc_project_workspace() bytes.
+ */
+int gdrr_mc_project(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr_source* src,
+                    const gdrr_geometry* geom, const float* majorant, uint64_t seed,
+                    uint64_t n_photons, uint32_t job_id, uint32_t flags, double* tally,
+                    void* workspace, size_t ws_bytes, void* stream);
+size_t gdrr_mc_project_workspace(const gdrr_physics* phys, const gdrr_source* src,
+                                 const gdrr_geometry* geom);
+
+/*
+ * Batch: every job of `jobs` (host array) in one persistent launch, replayed
+ * from a cached HIP graph when called again with the same arguments.  Job k
+ * gives exactly the tallies gdrr_mc_project gives for its volume, source,
+ * geometry, photon count and job_id (bitwise).  All volumes share `phys`.
+ * `majorants` (device, [n_vols][n_e-1]) may be NULL (computed, margin 2^-20).
+ * `tallies` receives each job's [4][nv][nu] block at its tally_offset.
+ * `tune` may be NULL for the defaults.
+ */
+int gdrr_mc_project_batch(const gdrr_volume* vols, int32_t n_vols, const gdrr_physics* phys,
+                          const gdrr_source* srcs, int32_t n_srcs, const gdrr_job* jobs,
+                          int32_t n_jobs, const float* majorants, uint64_t seed, uint32_t flags,
+                          const gdrr_tuning* tune, double* tallies, void* workspace,
+                          size_t ws_bytes, void* stream);
+size_t gdrr_mc_project_batch_workspace(const gdrr_physics* phys, const gdrr_source* srcs,
+                                       int32_t n_srcs, const gdrr_job* jobs, int32_t n_jobs);
+
+/*
+ * Gradient of a loss of the tallies with respect to voxel density (not in the
+ * paper): with adj[k] = dL/dT for job k ([2][nv][nu] double: primary,
+ * scatter; device, at element offset 2*npix*k), adds to grad_density
+ * ([nz][ny][nx] double, device) of every job's volume the path-replay,
+ * score-function estimate
+ *   dL/drho_v = sum_jobs (1/N) sum_i adj[c_i][p_i] r(E_i) sum_{collisions e of i} s_e(v),
+ * s_e = w_v/rho for a real collision and -mu_tot w_v/(mbar - mu) for a null
+ * one (w_v the interpolation weight of voxel v), holding the majorant fixed.
+ * Each history is regenerated twice from its Philox counters (outcome, then
+ * collisions); nothing is stored per history.  `majorants` is required and
+ * must be the one the forward used; only jobs of volume `volume` are run.
+ * Workspace: gdrr_mc_project_batch_workspace() bytes.
+ */
+int gdrr_mc_backward(const gdrr_volume* vols, int32_t n_vols, const gdrr_physics* phys,
+                     const gdrr_source* srcs, int32_t n_srcs, const gdrr_job* jobs, int32_t n_jobs,
+                     int32_t volume, const float* majorants, uint64_t seed, uint32_t flags,
+                     const gdrr_tuning* tune, const double* adj, double* grad_density,
+                     void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Per-history outcomes of one projection (a diagnostic of the same transport
+ * code): class (0 primary hit, 1 scatter hit, 2 photoelectric, 3 energy cut,
+ * 4 missed the detector, 5 step limit), pixel (iv*nu+iu or -1), final energy,
+ * number of free flights, Compton and Rayleigh events.  Arrays are device
+ * arrays of n_photons elements; any may be NULL.
+ */
+int gdrr_mc_trace(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr_source* src,
+                  const gdrr_geometry* geom, const float* majorant, uint64_t seed,
+                  uint64_t n_photons, uint32_t job_id, uint32_t flags, int8_t* cls, int32_t* pixel,
+                  float* e_final, int32_t* steps, int32_t* n_compton, int32_t* n_rayleigh,
+                  void* workspace, size_t ws_bytes, void* stream);
+
+/* Default launch shape for this device (after gdrr_init). */
+int gdrr_default_tuning(gdrr_tuning* out);
+
+/* Optional: binds the library to the current device and reads its properties. */
+int gdrr_init(void);
+
+/* Message of the last error of the calling thread ("" if none). */
+const char* gdrr_last_error(void);
+
+/* Library version string. */
+const char* gdrr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GDRR_H */

@@ -67,6 +67,7 @@ def lib():
         L.or_mc_project.argtypes = [P, u64, u64, C.c_uint32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32]
         L.or_mc_backward.argtypes = [P, u64, u64, C.c_uint32, i32, i32, vp, vp, vp, i32]
         L.or_rho_integrals.argtypes = [P, i32, vp, vp, vp]
+        L.or_mc_histories.argtypes = [P, u64, C.c_uint32, i32, vp, vp, C.c_int64, vp, vp, vp, vp, vp, vp, i32]
         L.or_primary_exact.argtypes = [P, i32, i32, vp]
         L.or_rho_integrals_many.argtypes = [P, i32, vp, vp, C.c_int64, vp]
         L.or_sample_compton.argtypes = [C.c_double, u64, u64, vp, vp]
@@ -173,6 +174,22 @@ def mc_project(p: Problem, seed: int, n: int, job_id: int = 0, interp: bool = Tr
         e_src=stats[10], e_out=stats[11]))
     out.update(tr)
     return out
+
+
+def mc_histories(p: Problem, seed: int, ids, majorant_tab: np.ndarray, job_id: int = 0,
+                 interp: bool = True, nthreads: int = 0):
+    """Outcomes of the selected photon indices (same definition as mc_project's trace)."""
+    ids = np.ascontiguousarray(ids, np.uint32)
+    m = ids.shape[0]
+    tr = dict(cls=np.zeros(m, np.int8), pixel=np.zeros(m, np.int32), e_final=np.zeros(m, np.float64),
+              steps=np.zeros(m, np.int32), n_compton=np.zeros(m, np.int32), n_rayleigh=np.zeros(m, np.int32))
+    mb = np.ascontiguousarray(majorant_tab, np.float64)
+    rc = lib().or_mc_histories(p.ref, seed, job_id, int(interp), _ptr(mb), _ptr(ids), m, _ptr(tr["cls"]),
+                               _ptr(tr["pixel"]), _ptr(tr["e_final"]), _ptr(tr["steps"]),
+                               _ptr(tr["n_compton"]), _ptr(tr["n_rayleigh"]), nthreads)
+    if rc:
+        raise ValueError("oracle mc_histories: invalid input")
+    return tr
 
 
 def mc_backward(p: Problem, seed: int, n: int, adj: np.ndarray, majorant_tab: np.ndarray,

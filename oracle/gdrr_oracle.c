@@ -703,6 +703,40 @@ int or_mc_project(const or_problem* p, uint64_t seed, uint64_t n, uint32_t job, 
 }
 
 /*
+ * Selected histories: the outcome of photons ids[k] (k < m) of job `job`,
+ * exactly as or_mc_project computes them (for comparing sampled histories of
+ * runs too large to repeat on the CPU).
+ */
+int or_mc_histories(const or_problem* p, uint64_t seed, uint32_t job, int32_t interp, const double* mbar,
+                    const uint32_t* ids, int64_t m, int8_t* cls, int32_t* pixel, double* e_final,
+                    int32_t* steps, int32_t* n_compton, int32_t* n_rayleigh, int32_t nthreads)
+{
+    if (validate(p) || !mbar || !ids) return -1;
+    or_ctx c;
+    if (make_ctx(p, seed, job, interp, mbar, &c)) { free_ctx(&c); return -1; }
+    int nt = 1;
+#ifdef _OPENMP
+    nt = nthreads > 0 ? nthreads : omp_get_max_threads();
+#endif
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nt)
+#endif
+    for (int64_t k = 0; k < m; ++k) {
+        or_outcome o;
+        history(p, &c, ids[k], &o, NULL);
+        if (cls) cls[k] = (int8_t)o.cls;
+        if (pixel) pixel[k] = o.pixel;
+        if (e_final) e_final[k] = o.e_final;
+        if (steps) steps[k] = o.steps;
+        if (n_compton) n_compton[k] = o.n_compton;
+        if (n_rayleigh) n_rayleigh[k] = o.n_rayleigh;
+    }
+    (void)nt;
+    free_ctx(&c);
+    return 0;
+}
+
+/*
  * Adjoint by path replay.  For a loss L(T) with adj = dL/dT over the primary
  * and scatter tallies ([2][nv][nu]), adds to grad[nz][ny][nx] the estimate
  *   dL/drho_v = (1/n) sum_i adj[c_i][p_i] r(E_i) sum_{events e of i} s_e(v)

@@ -1,0 +1,297 @@
+"""Python binding of libgdrr: device containers for the inputs, thin
+wrappers over the C ABI, and the autograd Function.
+
+PyTorch provides device memory and the stream; every step of the projection
+(majorant, source tables, transport, scoring, finalisation, adjoint) runs in
+the HIP library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi
+
+INTERP_DENSITY = _abi.INTERP_DENSITY
+TALLY_SUMSQ = _abi.TALLY_SUMSQ
+ACCUMULATE = _abi.ACCUMULATE
+SCATTER_FIRST = _abi.SCATTER_FIRST
+SCATTER_FIRST_COMPTON = _abi.SCATTER_FIRST_COMPTON
+
+
+def _dev(device):
+    return torch.device(device if device is not None else "cuda")
+
+
+def _stream(stream) -> C.c_void_p:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _t(x, dtype, device):
+    if isinstance(x, torch.Tensor):
+        return x.to(device=device, dtype=dtype).contiguous()
+    return torch.as_tensor(np.ascontiguousarray(x), dtype=dtype, device=device).contiguous()
+
+
+class DeviceVolume:
+    """Voxel phantom on the device: density [nz][ny][nx] f32, material u8."""
+
+    def __init__(self, density, material, spacing_mm, device=None):
+        dev = _dev(device)
+        self.density = _t(density, torch.float32, dev)
+        self.material = _t(material, torch.uint8, dev)
+        assert self.density.shape == self.material.shape and self.density.dim() == 3
+        self.spacing_mm = tuple(float(s) for s in spacing_mm)
+
+    @property
+    def shape(self):
+        return tuple(self.density.shape)
+
+    def struct(self, density: Optional[torch.Tensor] = None) -> _abi.Volume:
+        d = self.density if density is None else density
+        nz, ny, nx = d.shape
+        return _abi.Volume(nx, ny, nz, *self.spacing_mm, d.data_ptr(), self.material.data_ptr())
+
+
+class DevicePhysics:
+    """Mass attenuation tables [n_mat][n_e][3] and optional response [n_e]."""
+
+    def __init__(self, mu_mass, e0_kev, de_kev, response=None, rayleigh_x0=0.35, e_cut_kev=1.0, device=None):
+        dev = _dev(device)
+        self.mu = _t(mu_mass, torch.float32, dev)
+        self.response = None if response is None else _t(response, torch.float32, dev)
+        self.e0, self.de = float(e0_kev), float(de_kev)
+        self.x0, self.e_cut = float(rayleigh_x0), float(e_cut_kev)
+
+    @property
+    def n_e(self):
+        return self.mu.shape[1]
+
+    def struct(self) -> _abi.Physics:
+        return _abi.Physics(self.mu.shape[0], self.mu.shape[1], self.e0, self.de, self.mu.data_ptr(),
+                            None if self.response is None else self.response.data_ptr(), self.x0, self.e_cut)
+
+
+class DeviceSource:
+    """Spectrum (energies, weights) and fluence map [nv][nu] weights."""
+
+    def __init__(self, spec_e, spec_p, fluence, device=None):
+        dev = _dev(device)
+        self.spec_e = _t(spec_e, torch.float32, dev)
+        self.spec_p = _t(spec_p, torch.float32, dev)
+        self.fluence = _t(fluence, torch.float32, dev)
+        assert self.fluence.dim() == 2
+
+    def struct(self) -> _abi.Source:
+        fv, fu = self.fluence.shape
+        return _abi.Source(self.spec_e.shape[0], self.spec_e.data_ptr(), self.spec_p.data_ptr(), fu, fv,
+                           self.fluence.data_ptr())
+
+
+def geometry_struct(g) -> _abi.Geometry:
+    """From any object with sad_mm, aid_mm, phi_rad, theta_rad, nu, nv, du_mm, dv_mm."""
+    return _abi.Geometry(g.sad_mm, g.aid_mm, g.phi_rad, g.theta_rad, g.nu, g.nv, g.du_mm, g.dv_mm)
+
+
+def upload(problem, device=None):
+    """Device copies of a workloads.Problem: (volume, physics, source)."""
+    ph, phys, src = problem.phantom, problem.physics, problem.source
+    vol = DeviceVolume(ph.density, ph.material, ph.spacing_mm, device)
+    dphys = DevicePhysics(phys.mu_mass, phys.grid.e0_kev, phys.grid.de_kev, phys.response,
+                          phys.rayleigh_x0, phys.e_cut_kev, device)
+    dsrc = DeviceSource(src.spec_e, src.spec_p, src.fluence, device)
+    return vol, dphys, dsrc
+
+
+def _flags(interp: bool, sumsq: bool, extra: int = 0) -> int:
+    return (INTERP_DENSITY if interp else 0) | (TALLY_SUMSQ if sumsq else 0) | extra
+
+
+def majorant(vol: DeviceVolume, phys: DevicePhysics, interp: bool = True, margin: float = 2.0**-20,
+             density: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    L = _abi.lib()
+    out = torch.empty(phys.n_e - 1, dtype=torch.float32, device=vol.density.device)
+    ws = torch.empty(int(L.gdrr_majorant_workspace()), dtype=torch.uint8, device=vol.density.device)
+    v, p = vol.struct(density), phys.struct()
+    _abi.check(L.gdrr_majorant(C.byref(v), C.byref(p), INTERP_DENSITY if interp else 0, margin,
+                               out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return out
+
+
+def project(vol: DeviceVolume, phys: DevicePhysics, src: DeviceSource, geom, n_photons: int, seed: int = 1,
+            job_id: int = 0, interp: bool = True, sumsq: bool = True, majorant_tab: Optional[torch.Tensor] = None,
+            flags: int = 0, out: Optional[torch.Tensor] = None, density: Optional[torch.Tensor] = None,
+            stream=None) -> torch.Tensor:
+    """One projection: tally [4][nv][nu] float64 (P, P^2, S, S^2 per source photon)."""
+    L = _abi.lib()
+    g = geometry_struct(geom)
+    v, p, s = vol.struct(density), phys.struct(), src.struct()
+    if out is None:
+        out = torch.zeros(4, geom.nv, geom.nu, dtype=torch.float64, device=vol.density.device)
+    nbytes = int(L.gdrr_mc_project_workspace(C.byref(p), C.byref(s), C.byref(g)))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=vol.density.device)
+    mb = None if majorant_tab is None else majorant_tab.data_ptr()
+    _abi.check(L.gdrr_mc_project(C.byref(v), C.byref(p), C.byref(s), C.byref(g), mb, seed, n_photons, job_id,
+                                 _flags(interp, sumsq, flags), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                 _stream(stream)))
+    return out
+
+
+def trace(vol: DeviceVolume, phys: DevicePhysics, src: DeviceSource, geom, n_photons: int, seed: int = 1,
+          job_id: int = 0, interp: bool = True, majorant_tab: Optional[torch.Tensor] = None,
+          stream=None) -> Dict[str, torch.Tensor]:
+    """Per-history outcomes (class, pixel, final energy, flights, Compton and Rayleigh counts)."""
+    L = _abi.lib()
+    dev = vol.density.device
+    out = dict(cls=torch.full((n_photons,), -1, dtype=torch.int8, device=dev),
+               pixel=torch.empty(n_photons, dtype=torch.int32, device=dev),
+               e_final=torch.empty(n_photons, dtype=torch.float32, device=dev),
+               steps=torch.empty(n_photons, dtype=torch.int32, device=dev),
+               n_compton=torch.empty(n_photons, dtype=torch.int32, device=dev),
+               n_rayleigh=torch.empty(n_photons, dtype=torch.int32, device=dev))
+    g = geometry_struct(geom)
+    v, p, s = vol.struct(), phys.struct(), src.struct()
+    nbytes = int(L.gdrr_mc_project_workspace(C.byref(p), C.byref(s), C.byref(g)))
+    ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
+    mb = None if majorant_tab is None else majorant_tab.data_ptr()
+    _abi.check(L.gdrr_mc_trace(C.byref(v), C.byref(p), C.byref(s), C.byref(g), mb, seed, n_photons, job_id,
+                               INTERP_DENSITY if interp else 0, out["cls"].data_ptr(), out["pixel"].data_ptr(),
+                               out["e_final"].data_ptr(), out["steps"].data_ptr(), out["n_compton"].data_ptr(),
+                               out["n_rayleigh"].data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return out
+
+
+class JobSpec:
+    """One projection of a batch."""
+
+    def __init__(self, geom, n_photons: int, job_id: int, volume: int = 0, source: int = 0):
+        self.geom, self.n_photons, self.job_id = geom, int(n_photons), int(job_id)
+        self.volume, self.source = int(volume), int(source)
+
+
+def _jobs_array(jobs: Sequence[JobSpec]):
+    arr = (_abi.Job * len(jobs))()
+    off = 0
+    for k, j in enumerate(jobs):
+        arr[k].volume, arr[k].source = j.volume, j.source
+        arr[k].geom = geometry_struct(j.geom)
+        arr[k].n_photons, arr[k].job_id, arr[k].reserved = j.n_photons, j.job_id, 0
+        arr[k].tally_offset = off
+        off += 4 * j.geom.nu * j.geom.nv
+    return arr, off
+
+
+def tuning_struct(tune) -> Optional[_abi.Tuning]:
+    if tune is None:
+        return None
+    if isinstance(tune, _abi.Tuning):
+        return tune
+    return _abi.Tuning(int(tune.get("block", 0)), int(tune.get("blocks_per_cu", 0)),
+                       int(tune.get("chunk", 0)), int(tune.get("defer", 0)))
+
+
+class Batch:
+    """Several volumes, sources and jobs in one persistent launch."""
+
+    def __init__(self, vols: List[DeviceVolume], phys: DevicePhysics, srcs: List[DeviceSource],
+                 jobs: Sequence[JobSpec]):
+        self.vols, self.phys, self.srcs, self.jobs = list(vols), phys, list(srcs), list(jobs)
+        self._jobs_c, self.tally_elems = _jobs_array(self.jobs)
+        self._ws = None
+
+    def _structs(self, densities=None):
+        n = len(self.vols)
+        va = (_abi.Volume * n)()
+        for k, v in enumerate(self.vols):
+            va[k] = v.struct(None if densities is None else densities[k])
+        sa = (_abi.Source * len(self.srcs))()
+        for k, s in enumerate(self.srcs):
+            sa[k] = s.struct()
+        return va, sa, self.phys.struct()
+
+    def workspace(self) -> torch.Tensor:
+        L = _abi.lib()
+        _, sa, p = self._structs()
+        nbytes = int(L.gdrr_mc_project_batch_workspace(C.byref(p), sa, len(self.srcs), self._jobs_c,
+                                                      len(self.jobs)))
+        if self._ws is None or self._ws.numel() < nbytes:
+            self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.vols[0].density.device)
+        return self._ws
+
+    def tally_views(self, tallies: torch.Tensor) -> List[torch.Tensor]:
+        out, off = [], 0
+        for j in self.jobs:
+            n = 4 * j.geom.nu * j.geom.nv
+            out.append(tallies[off:off + n].view(4, j.geom.nv, j.geom.nu))
+            off += n
+        return out
+
+    def majorants(self, interp: bool = True, margin: float = 2.0**-20, densities=None, stream=None):
+        ms = [majorant(v, self.phys, interp, margin, None if densities is None else densities[k], stream)
+              for k, v in enumerate(self.vols)]
+        return torch.stack(ms)
+
+    def project(self, seed: int = 1, interp: bool = True, sumsq: bool = True, flags: int = 0, tune=None,
+                majorants: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
+                densities=None, stream=None) -> torch.Tensor:
+        L = _abi.lib()
+        va, sa, p = self._structs(densities)
+        if out is None:
+            out = torch.zeros(self.tally_elems, dtype=torch.float64, device=self.vols[0].density.device)
+        ws = self.workspace()
+        t = tuning_struct(tune)
+        mb = None if majorants is None else majorants.contiguous().data_ptr()
+        _abi.check(L.gdrr_mc_project_batch(va, len(self.vols), C.byref(p), sa, len(self.srcs), self._jobs_c,
+                                           len(self.jobs), mb, seed, _flags(interp, sumsq, flags),
+                                           None if t is None else C.byref(t), out.data_ptr(), ws.data_ptr(),
+                                           ws.numel(), _stream(stream)))
+        return out
+
+    def backward(self, adj: torch.Tensor, majorants: torch.Tensor, volume: int = 0, seed: int = 1,
+                 interp: bool = True, flags: int = 0, tune=None, grad: Optional[torch.Tensor] = None,
+                 densities=None, stream=None) -> torch.Tensor:
+        """adj: [n_jobs][2][nv][nu] float64 (dL/dP, dL/dS per job); returns dL/drho of `volume`."""
+        L = _abi.lib()
+        va, sa, p = self._structs(densities)
+        v = self.vols[volume]
+        if grad is None:
+            grad = torch.zeros(v.shape, dtype=torch.float64, device=v.density.device)
+            flags |= ACCUMULATE
+        adj = adj.to(torch.float64).contiguous()
+        ws = self.workspace()
+        t = tuning_struct(tune)
+        _abi.check(L.gdrr_mc_backward(va, len(self.vols), C.byref(p), sa, len(self.srcs), self._jobs_c,
+                                      len(self.jobs), volume, majorants.contiguous().data_ptr(), seed,
+                                      _flags(interp, False, flags), None if t is None else C.byref(t),
+                                      adj.data_ptr(), grad.data_ptr(), ws.data_ptr(), ws.numel(),
+                                      _stream(stream)))
+        return grad
+
+
+class GdrrProject(torch.autograd.Function):
+    """(P_hat, S_hat) per job as a differentiable function of the density of
+    volume 0 of a Batch.  Backward replays the forward's histories (same seed
+    and majorant) and returns dL/drho from the score-function adjoint."""
+
+    @staticmethod
+    def forward(ctx, density: torch.Tensor, batch: Batch, seed: int, interp: bool, margin: float):
+        densities = [density.detach().contiguous()] + [v.density for v in batch.vols[1:]]
+        maj = batch.majorants(interp, margin, densities)
+        tallies = batch.project(seed=seed, interp=interp, sumsq=False, majorants=maj, densities=densities)
+        views = batch.tally_views(tallies)
+        ps = torch.stack([torch.stack([t[0], t[2]]) for t in views])      # [n_jobs][2][nv][nu]
+        ctx.batch, ctx.seed, ctx.interp = batch, seed, interp
+        ctx.save_for_backward(densities[0], maj)
+        return ps
+
+    @staticmethod
+    def backward(ctx, grad_ps: torch.Tensor):
+        density, maj = ctx.saved_tensors
+        densities = [density] + [v.density for v in ctx.batch.vols[1:]]
+        g = ctx.batch.backward(grad_ps.to(torch.float64).contiguous(), maj, volume=0, seed=ctx.seed,
+                               interp=ctx.interp, densities=densities)
+        return g.to(density.dtype), None, None, None, None

@@ -1,0 +1,661 @@
+// Host side of libgdrr: argument checks, workspace layout, launch plans,
+// the cached HIP graph of a batch, and the C ABI of include/gdrr.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "gdrr.h"
+#include "gdrr_kernels.h"
+
+using namespace gdrr;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+#define GDRR_HIP(call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) return fail(GDRR_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+// --------------------------------------------------------------------------
+// Device properties, read once per device.
+// --------------------------------------------------------------------------
+struct DevInfo {
+    int cus = 0;
+    size_t lds_max = 0;
+    bool ok = false;
+};
+
+std::mutex g_dev_mu;
+DevInfo g_dev[64];
+
+int device_info(DevInfo& out) {
+    int dev = 0;
+    GDRR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(GDRR_ENOTSUP, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (!g_dev[dev].ok) {
+        hipDeviceProp_t prop;
+        GDRR_HIP(hipGetDeviceProperties(&prop, dev));
+        g_dev[dev].cus = prop.multiProcessorCount;
+        g_dev[dev].lds_max = prop.sharedMemPerBlock;
+        g_dev[dev].ok = true;
+    }
+    out = g_dev[dev];
+    return GDRR_OK;
+}
+
+// --------------------------------------------------------------------------
+// Workspace carving: the same walk sizes the workspace (base == nullptr) and
+// lays it out.
+// --------------------------------------------------------------------------
+struct Carver {
+    char* base;
+    size_t off = 0;
+    explicit Carver(void* b) : base((char*)b) {}
+    template <class T>
+    T* take(size_t n) {
+        off = (off + 255) & ~(size_t)255;
+        T* p = base ? (T*)(base + off) : nullptr;
+        off += n * sizeof(T);
+        return p;
+    }
+};
+
+uint32_t guide_size(int n) {
+    uint32_t k = 1;
+    while ((int)k < n && k < (1u << 20)) k <<= 1;
+    return k;
+}
+
+// --------------------------------------------------------------------------
+// Argument checks.
+// --------------------------------------------------------------------------
+int check_volume(const gdrr_volume* v) {
+    if (!v) return fail(GDRR_EINVAL, "volume is NULL");
+    if (v->nx < 1 || v->ny < 1 || v->nz < 1) return fail(GDRR_EINVAL, "volume dimensions must be >= 1");
+    if ((long long)v->nx * v->ny * v->nz >= (1ll << 31)) return fail(GDRR_EINVAL, "volume has 2^31 voxels or more");
+    if (!(v->dx_mm > 0 && v->dy_mm > 0 && v->dz_mm > 0)) return fail(GDRR_EINVAL, "voxel sizes must be > 0");
+    if (!v->density || !v->material) return fail(GDRR_EINVAL, "volume density/material pointer is NULL");
+    return GDRR_OK;
+}
+
+int check_physics(const gdrr_physics* p) {
+    if (!p) return fail(GDRR_EINVAL, "physics is NULL");
+    if (p->n_mat < 1 || p->n_mat > GDRR_MAX_MATERIALS) return fail(GDRR_EINVAL, "n_mat must be in [1, 16]");
+    if (p->n_e < 2 || p->n_e > 1024) return fail(GDRR_EINVAL, "n_e must be in [2, 1024]");
+    if (!(p->de_kev > 0) || !(p->e0_kev > 0)) return fail(GDRR_EINVAL, "energy grid must have e0 > 0 and de > 0");
+    if (!p->mu_mass) return fail(GDRR_EINVAL, "mu_mass is NULL");
+    if (!(p->e_cut_kev >= p->e0_kev)) return fail(GDRR_EINVAL, "e_cut must be >= e0");
+    if (!(p->rayleigh_x0_invA > 0)) return fail(GDRR_EINVAL, "rayleigh x0 must be > 0");
+    return GDRR_OK;
+}
+
+int check_source(const gdrr_source* s) {
+    if (!s) return fail(GDRR_EINVAL, "source is NULL");
+    if (s->n_spec < 1 || s->n_spec > 4096) return fail(GDRR_EINVAL, "n_spec must be in [1, 4096]");
+    if (!s->spec_e_kev || !s->spec_prob || !s->fluence) return fail(GDRR_EINVAL, "source pointer is NULL");
+    if (s->fu < 1 || s->fv < 1 || (long long)s->fu * s->fv > (1ll << 24))
+        return fail(GDRR_EINVAL, "fluence grid must have 1 <= fu*fv <= 2^24");
+    return GDRR_OK;
+}
+
+int check_geometry(const gdrr_geometry* g, const gdrr_volume* v, const gdrr_source* s) {
+    if (!g) return fail(GDRR_EINVAL, "geometry is NULL");
+    if (!(g->sad_mm > 0 && g->aid_mm > 0)) return fail(GDRR_EINVAL, "SAD and AID must be > 0");
+    if (g->nu < 1 || g->nv < 1 || !(g->du_mm > 0 && g->dv_mm > 0)) return fail(GDRR_EINVAL, "bad detector grid");
+    if (!std::isfinite(g->phi_rad) || !std::isfinite(g->theta_rad)) return fail(GDRR_EINVAL, "angles must be finite");
+    if (s && (s->fu != g->nu || s->fv != g->nv))
+        return fail(GDRR_EINVAL, "the fluence grid must be the detector's pixel grid (fu = nu, fv = nv)");
+    if (v) {
+        const double hx = 0.5 * v->nx * v->dx_mm, hy = 0.5 * v->ny * v->dy_mm;
+        const double r = std::sqrt(hx * hx + hy * hy);
+        if (!(r < g->aid_mm) || !(r < g->sad_mm))
+            return fail(GDRR_EINVAL, "the phantom must lie between the source and the detector at every angle");
+    }
+    return GDRR_OK;
+}
+
+// --------------------------------------------------------------------------
+// Launch list: every kernel takes one parameter struct by value, so a launch
+// is (function, grid, block, LDS bytes, argument bytes).  The list runs either
+// directly or as a HIP graph.
+// --------------------------------------------------------------------------
+struct Launch {
+    const void* func;
+    dim3 grid, block;
+    size_t shmem;
+    std::vector<char> args;
+};
+
+template <class P>
+Launch make_launch(const void* f, dim3 g, dim3 b, size_t sh, const P& p) {
+    Launch L{f, g, b, sh, std::vector<char>(sizeof(P))};
+    std::memcpy(L.args.data(), &p, sizeof(P));
+    return L;
+}
+
+int run_direct(std::vector<Launch>& ls, hipStream_t st) {
+    for (auto& L : ls) {
+        void* a[1] = {L.args.data()};
+        GDRR_HIP(hipLaunchKernel(L.func, L.grid, L.block, a, L.shmem, st));
+    }
+    return GDRR_OK;
+}
+
+std::vector<char> launch_key(const std::vector<Launch>& ls) {
+    std::vector<char> k;
+    for (auto& L : ls) {
+        const char* f = (const char*)&L.func;
+        k.insert(k.end(), f, f + sizeof(L.func));
+        unsigned dims[7] = {L.grid.x, L.grid.y, L.grid.z, L.block.x, L.block.y, L.block.z, (unsigned)L.shmem};
+        k.insert(k.end(), (const char*)dims, (const char*)dims + sizeof(dims));
+        k.insert(k.end(), L.args.begin(), L.args.end());
+    }
+    return k;
+}
+
+struct GraphEntry {
+    int device = -1;
+    std::vector<char> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+std::mutex g_graph_mu;
+GraphEntry g_graphs[4];
+int g_graph_next = 0;
+
+int run_graph(std::vector<Launch>& ls, hipStream_t st) {
+    int dev = 0;
+    GDRR_HIP(hipGetDevice(&dev));
+    std::vector<char> key = launch_key(ls);
+    std::lock_guard<std::mutex> lk(g_graph_mu);
+    for (auto& e : g_graphs)
+        if (e.exec && e.device == dev && e.key == key) {
+            GDRR_HIP(hipGraphLaunch(e.exec, st));
+            return GDRR_OK;
+        }
+    GraphEntry& e = g_graphs[g_graph_next];
+    g_graph_next = (g_graph_next + 1) % 4;
+    if (e.exec) { (void)hipGraphExecDestroy(e.exec); e.exec = nullptr; }
+    if (e.graph) { (void)hipGraphDestroy(e.graph); e.graph = nullptr; }
+    GDRR_HIP(hipGraphCreate(&e.graph, 0));
+    hipGraphNode_t prev = nullptr;
+    for (auto& L : ls) {
+        hipKernelNodeParams kp{};
+        void* a[1] = {L.args.data()};
+        kp.func = const_cast<void*>(L.func);
+        kp.gridDim = L.grid;
+        kp.blockDim = L.block;
+        kp.sharedMemBytes = (unsigned)L.shmem;
+        kp.kernelParams = a;
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        GDRR_HIP(hipGraphAddKernelNode(&node, e.graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+        prev = node;
+    }
+    GDRR_HIP(hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0));
+    e.device = dev;
+    e.key = std::move(key);
+    GDRR_HIP(hipGraphLaunch(e.exec, st));
+    return GDRR_OK;
+}
+
+// --------------------------------------------------------------------------
+// A batch plan: host-side tables and the workspace layout.
+// --------------------------------------------------------------------------
+struct SrcArea {
+    double* spec_cdf;
+    uint32_t* spec_guide;
+    double* flu_cdf;
+    uint32_t* flu_guide;
+    uint32_t spec_k, flu_k;
+};
+
+struct Layout {
+    unsigned long long* counter;      // [8]: dispenser, error word
+    unsigned long long* chunk_prefix; // [n_jobs + 1]
+    DJob* jobs;                       // [n_jobs]
+    long long* out_off;               // [n_jobs]
+    float* majorants;                 // [n_vols][n_e - 1] (when computed)
+    unsigned int* rho_max;            // [n_vols][256]
+    unsigned int* present;            // [n_vols][256]
+    SrcArea src[GDRR_MAX_SOURCES];
+    unsigned long long* tally;        // fixed-point tallies
+    size_t tally_elems;
+    size_t bytes;
+};
+
+Layout carve(void* ws, const gdrr_physics* phys, const gdrr_source* srcs, int n_srcs, int n_jobs, int n_vols,
+             size_t tally_elems, bool need_majorant) {
+    Carver c(ws);
+    Layout L{};
+    L.counter = c.take<unsigned long long>(8);
+    L.chunk_prefix = c.take<unsigned long long>((size_t)n_jobs + 1);
+    L.jobs = c.take<DJob>((size_t)n_jobs);
+    L.out_off = c.take<long long>((size_t)n_jobs);
+    L.majorants = need_majorant ? c.take<float>((size_t)n_vols * (phys->n_e - 1)) : nullptr;
+    L.rho_max = c.take<unsigned int>((size_t)n_vols * 256);
+    L.present = c.take<unsigned int>((size_t)n_vols * 256);
+    for (int s = 0; s < n_srcs; ++s) {
+        const int npix = srcs[s].fu * srcs[s].fv;
+        L.src[s].spec_k = guide_size(srcs[s].n_spec);
+        L.src[s].flu_k = guide_size(npix);
+        L.src[s].spec_cdf = c.take<double>((size_t)srcs[s].n_spec);
+        L.src[s].spec_guide = c.take<uint32_t>(L.src[s].spec_k);
+        L.src[s].flu_cdf = c.take<double>((size_t)npix);
+        L.src[s].flu_guide = c.take<uint32_t>(L.src[s].flu_k);
+    }
+    L.tally = c.take<unsigned long long>(tally_elems);
+    L.tally_elems = tally_elems;
+    L.bytes = c.off + 256;
+    return L;
+}
+
+size_t tally_elems_of(const gdrr_job* jobs, int n_jobs, const gdrr_source* srcs) {
+    size_t e = 0;
+    for (int k = 0; k < n_jobs; ++k) e += 4 * (size_t)jobs[k].geom.nu * jobs[k].geom.nv;
+    (void)srcs;
+    return e;
+}
+
+struct Batch {
+    const gdrr_volume* vols;
+    int n_vols;
+    const gdrr_physics* phys;
+    const gdrr_source* srcs;
+    int n_srcs;
+    const gdrr_job* jobs;
+    int n_jobs;
+    const float* majorants;     // caller's, or null
+    uint64_t seed;
+    uint32_t flags;
+    const gdrr_tuning* tune;
+    int mode;                   // kModeForward / kModeTrace / kModeBackward
+    int only_volume;            // backward: jobs of this volume only (-1 = all)
+    double* out;                // forward: caller tallies
+    const double* adj;          // backward
+    double* grad;               // backward
+    int8_t* t_cls; int32_t* t_pixel; float* t_e; int32_t* t_steps; int32_t* t_nc; int32_t* t_nr;
+    bool use_graph;
+};
+
+thread_local std::vector<char> g_staging;
+
+int check_batch(const Batch& B) {
+    if (B.n_vols < 1 || B.n_vols > GDRR_MAX_VOLUMES) return fail(GDRR_EINVAL, "n_vols must be in [1, 8]");
+    if (B.n_srcs < 1 || B.n_srcs > GDRR_MAX_SOURCES) return fail(GDRR_EINVAL, "n_srcs must be in [1, 8]");
+    if (B.n_jobs < 1 || B.n_jobs > (1 << 20)) return fail(GDRR_EINVAL, "n_jobs must be in [1, 2^20]");
+    if (!B.vols || !B.srcs || !B.jobs) return fail(GDRR_EINVAL, "NULL array argument");
+    int rc;
+    if ((rc = check_physics(B.phys))) return rc;
+    for (int v = 0; v < B.n_vols; ++v)
+        if ((rc = check_volume(&B.vols[v]))) return rc;
+    for (int s = 0; s < B.n_srcs; ++s)
+        if ((rc = check_source(&B.srcs[s]))) return rc;
+    for (int k = 0; k < B.n_jobs; ++k) {
+        const gdrr_job& J = B.jobs[k];
+        if (J.volume < 0 || J.volume >= B.n_vols) return fail(GDRR_EINVAL, "job volume index out of range");
+        if (J.source < 0 || J.source >= B.n_srcs) return fail(GDRR_EINVAL, "job source index out of range");
+        if (J.n_photons >= (1ull << 32)) return fail(GDRR_EINVAL, "2^32 or more photons in one job");
+        if (J.reserved != 0) return fail(GDRR_EINVAL, "gdrr_job.reserved must be 0");
+        if (J.tally_offset < 0) return fail(GDRR_EINVAL, "negative tally offset");
+        if ((rc = check_geometry(&J.geom, &B.vols[J.volume], &B.srcs[J.source]))) return rc;
+    }
+    if (B.tune) {
+        const gdrr_tuning& t = *B.tune;
+        if (t.block && (t.block % 64 || t.block < 64 || t.block > 1024)) return fail(GDRR_EINVAL, "tune.block must be a multiple of 64 in [64, 1024]");
+        if (t.chunk && (t.chunk % 64 || t.chunk < 64)) return fail(GDRR_EINVAL, "tune.chunk must be a positive multiple of 64");
+        if (t.defer < 0 || t.defer > 64) return fail(GDRR_EINVAL, "tune.defer must be in [0, 64]");
+        if (t.blocks_per_cu < 0 || t.blocks_per_cu > 64) return fail(GDRR_EINVAL, "tune.blocks_per_cu must be in [0, 64]");
+    }
+    return GDRR_OK;
+}
+
+template <int MODE>
+const void* mc_func() { return reinterpret_cast<const void*>(&mc_kernel<MODE>); }
+
+int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
+    int rc = check_batch(B);
+    if (rc) return rc;
+    const gdrr_physics* phys = B.phys;
+    const bool need_maj = B.majorants == nullptr;
+    const Layout L0 = carve(nullptr, phys, B.srcs, B.n_srcs, B.n_jobs, B.n_vols,
+                            tally_elems_of(B.jobs, B.n_jobs, B.srcs), need_maj);
+    if (!ws || ws_bytes < L0.bytes)
+        return fail(GDRR_EINVAL, "workspace too small: need " + std::to_string(L0.bytes) + " bytes");
+    DevInfo dev;
+    if ((rc = device_info(dev))) return rc;
+    char* wsa = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    const Layout L = carve(wsa, phys, B.srcs, B.n_srcs, B.n_jobs, B.n_vols, L0.tally_elems, need_maj);
+    const bool interp = (B.flags & GDRR_INTERP_DENSITY) != 0;
+
+    // ---- host tables: jobs, chunk prefix, output offsets ----
+    gdrr_tuning tune{};
+    if (B.tune) tune = *B.tune;
+    unsigned long long total_photons = 0;
+    for (int k = 0; k < B.n_jobs; ++k)
+        if (B.only_volume < 0 || B.jobs[k].volume == B.only_volume) total_photons += B.jobs[k].n_photons;
+    const int block = tune.block ? tune.block : 256;
+    const size_t lds = lds_bytes(phys->n_mat, phys->n_e, B.n_vols, phys->response != nullptr);
+    if (lds > dev.lds_max) return fail(GDRR_ENOTSUP, "tables exceed the LDS of a workgroup");
+    int per_cu = tune.blocks_per_cu;
+    if (!per_cu) {
+        const void* f = B.mode == kModeForward ? mc_func<kModeForward>()
+                      : B.mode == kModeTrace ? mc_func<kModeTrace>() : mc_func<kModeBackward>();
+        int nb = 0;
+        GDRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, block, lds));
+        per_cu = std::max(nb, 1);
+    }
+    const unsigned grid = (unsigned)(dev.cus * per_cu);
+    const unsigned long long waves = (unsigned long long)grid * (block / 64);
+    int chunk = tune.chunk;
+    if (!chunk) {
+        unsigned long long c = total_photons / (waves * 8ull);
+        c = std::max<unsigned long long>(64, std::min<unsigned long long>(4096, c));
+        chunk = (int)(c / 64 * 64);
+    }
+    const int defer = tune.defer ? tune.defer : 8;
+
+    const size_t n_jobs = (size_t)B.n_jobs;
+    const size_t job_bytes = sizeof(unsigned long long) * (n_jobs + 1);
+    std::vector<unsigned long long> prefix(n_jobs + 1);
+    std::vector<DJob> dj(n_jobs);
+    std::vector<long long> out_off(n_jobs);
+    unsigned long long chunks = 0;
+    size_t toff = 0;
+    for (size_t k = 0; k < n_jobs; ++k) {
+        const gdrr_job& J = B.jobs[k];
+        const gdrr_geometry& g = J.geom;
+        const double phi = g.phi_rad, th = g.theta_rad;
+        const double cq = std::cos(phi + th), sq = std::sin(phi + th);
+        DJob d{};
+        d.Sx = (float)(-g.sad_mm * std::cos(phi));
+        d.Sy = (float)(-g.sad_mm * std::sin(phi));
+        d.Sz = 0.0f;
+        d.Px = (float)(g.aid_mm * cq);
+        d.Py = (float)(g.aid_mm * sq);
+        d.Pz = 0.0f;
+        d.nx = (float)cq; d.ny = (float)sq; d.nz = 0.0f;
+        d.ux = (float)(-sq); d.uy = (float)cq; d.uz = 0.0f;
+        d.du = g.du_mm; d.dv = g.dv_mm;
+        d.idu = (float)(1.0 / g.du_mm); d.idv = (float)(1.0 / g.dv_mm);
+        d.nu = g.nu; d.nv = g.nv;
+        d.src = J.source; d.vol = J.volume;
+        d.job_id = J.job_id;
+        const bool run = B.only_volume < 0 || J.volume == B.only_volume;
+        const unsigned long long n = run ? J.n_photons : 0ull;
+        d.n_lo = (uint32_t)J.n_photons;
+        d.n_hi = (uint32_t)(J.n_photons >> 32);
+        d.index = (uint32_t)k;
+        d.tally_off = (long long)toff;
+        d.adj_off = (long long)(2 * (size_t)g.nu * g.nv * k);
+        toff += 4 * (size_t)g.nu * g.nv;
+        dj[k] = d;
+        out_off[k] = J.tally_offset;
+        prefix[k] = chunks;
+        chunks += (n + (unsigned long long)chunk - 1) / (unsigned long long)chunk;
+    }
+    prefix[n_jobs] = chunks;
+
+    // The volume order of the dispenser: jobs are taken in array order; a
+    // wavefront drains before it changes phantom, so callers group jobs by volume.
+    g_staging.resize(job_bytes + sizeof(DJob) * n_jobs + sizeof(long long) * n_jobs + 1024);
+    char* hs = g_staging.data();
+    std::memcpy(hs, prefix.data(), job_bytes);
+    GDRR_HIP(hipMemcpyAsync(L.chunk_prefix, hs, job_bytes, hipMemcpyHostToDevice, st));
+    std::memcpy(hs + job_bytes, dj.data(), sizeof(DJob) * n_jobs);
+    GDRR_HIP(hipMemcpyAsync(L.jobs, hs + job_bytes, sizeof(DJob) * n_jobs, hipMemcpyHostToDevice, st));
+    std::memcpy(hs + job_bytes + sizeof(DJob) * n_jobs, out_off.data(), sizeof(long long) * n_jobs);
+    GDRR_HIP(hipMemcpyAsync(L.out_off, hs + job_bytes + sizeof(DJob) * n_jobs, sizeof(long long) * n_jobs,
+                            hipMemcpyHostToDevice, st));
+
+    std::vector<Launch> ls;
+    // ---- clear counters, tallies and the majorant scratch ----
+    {
+        FillParams f{L.counter, 8};
+        ls.push_back(make_launch((const void*)&fill_zero_kernel, dim3(1), dim3(256), 0, f));
+        FillParams t{L.tally, (long long)L.tally_elems};
+        ls.push_back(make_launch((const void*)&fill_zero_kernel, dim3(std::max<unsigned>(1, std::min<size_t>(4096, (L.tally_elems + 255) / 256))), dim3(256), 0, t));
+        FillParams r{(unsigned long long*)L.rho_max, (long long)B.n_vols * 128};   // 256 u32 per volume
+        ls.push_back(make_launch((const void*)&fill_zero_kernel, dim3(4), dim3(256), 0, r));
+        FillParams p{(unsigned long long*)L.present, (long long)B.n_vols * 128};
+        ls.push_back(make_launch((const void*)&fill_zero_kernel, dim3(4), dim3(256), 0, p));
+    }
+    // ---- majorants ----
+    const float* maj = B.majorants;
+    if (need_maj) {
+        for (int v = 0; v < B.n_vols; ++v) {
+            const gdrr_volume& V = B.vols[v];
+            MajParams m{V.density, V.material, V.nx, V.ny, V.nz, interp ? 1 : 0, L.rho_max + 256 * v,
+                        L.present + 256 * v, (unsigned int*)(L.counter + 1)};
+            const long long nvox = (long long)V.nx * V.ny * V.nz;
+            const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>(dev.cus * 8, (nvox + 255) / 256));
+            ls.push_back(make_launch((const void*)&rho_max_kernel, dim3(g), dim3(256), 0, m));
+            MajFinParams fp{L.rho_max + 256 * v, L.present + 256 * v, phys->mu_mass, phys->n_mat, phys->n_e,
+                            1.0 + (double)(1.0f / 1048576.0f), L.majorants + (size_t)v * (phys->n_e - 1),
+                            (unsigned int*)(L.counter + 1)};
+            ls.push_back(make_launch((const void*)&majorant_kernel, dim3((phys->n_e + 254) / 256), dim3(256), 0, fp));
+        }
+        maj = L.majorants;
+    }
+    // ---- sources: CDFs and guide tables ----
+    for (int s = 0; s < B.n_srcs; ++s) {
+        const gdrr_source& S = B.srcs[s];
+        const SrcArea& A = L.src[s];
+        SrcPrepParams sp{S.spec_prob, S.n_spec, A.spec_cdf, A.spec_guide, (int)A.spec_k, (unsigned int*)(L.counter + 1)};
+        ls.push_back(make_launch((const void*)&cdf_kernel, dim3(1), dim3(64), 0, sp));
+        ls.push_back(make_launch((const void*)&guide_kernel, dim3((A.spec_k + 255) / 256), dim3(256), 0, sp));
+        SrcPrepParams fp{S.fluence, S.fu * S.fv, A.flu_cdf, A.flu_guide, (int)A.flu_k, (unsigned int*)(L.counter + 1)};
+        ls.push_back(make_launch((const void*)&cdf_kernel, dim3(1), dim3(64), 0, fp));
+        ls.push_back(make_launch((const void*)&guide_kernel, dim3((A.flu_k + 255) / 256), dim3(256), 0, fp));
+    }
+    // ---- the persistent transport kernel ----
+    KParams kp{};
+    for (int v = 0; v < B.n_vols; ++v) {
+        const gdrr_volume& V = B.vols[v];
+        DVolume& d = kp.vol[v];
+        d.density = V.density;
+        d.material = V.material;
+        d.nx = V.nx; d.ny = V.ny; d.nz = V.nz; d.nxy = V.nx * V.ny;
+        d.lox = (float)(-0.5 * V.nx * V.dx_mm); d.hix = -d.lox;
+        d.loy = (float)(-0.5 * V.ny * V.dy_mm); d.hiy = -d.loy;
+        d.loz = (float)(-0.5 * V.nz * V.dz_mm); d.hiz = -d.loz;
+        d.idx = (float)(1.0 / V.dx_mm); d.idy = (float)(1.0 / V.dy_mm); d.idz = (float)(1.0 / V.dz_mm);
+        d.lds_majorant = v * (phys->n_e - 1);
+    }
+    for (int s = 0; s < B.n_srcs; ++s) {
+        DSource& d = kp.src[s];
+        d.spec_e = B.srcs[s].spec_e_kev;
+        d.spec_cdf = L.src[s].spec_cdf;
+        d.spec_guide = L.src[s].spec_guide;
+        d.flu_cdf = L.src[s].flu_cdf;
+        d.flu_guide = L.src[s].flu_guide;
+        d.n_spec = B.srcs[s].n_spec;
+        d.spec_k = (int)L.src[s].spec_k;
+        d.npix = B.srcs[s].fu * B.srcs[s].fv;
+        d.flu_k = (int)L.src[s].flu_k;
+    }
+    kp.jobs = L.jobs;
+    kp.chunk_prefix = L.chunk_prefix;
+    kp.counter = L.counter;
+    kp.tally = L.tally;
+    kp.mu_mass = phys->mu_mass;
+    kp.response = phys->response;
+    kp.majorants = maj;
+    kp.total_chunks = chunks;
+    kp.n_jobs = B.n_jobs;
+    kp.n_vols = B.n_vols;
+    kp.n_mat = phys->n_mat;
+    kp.n_e = phys->n_e;
+    kp.e0 = phys->e0_kev;
+    kp.inv_de = (float)(1.0 / phys->de_kev);
+    kp.e_max = (float)(phys->e0_kev + (double)phys->de_kev * (phys->n_e - 1));
+    kp.e_cut = phys->e_cut_kev;
+    kp.x0 = phys->rayleigh_x0_invA;
+    kp.k0 = (uint32_t)B.seed;
+    kp.k1 = (uint32_t)(B.seed >> 32);
+    kp.flags = B.flags;
+    kp.chunk = chunk;
+    kp.defer = defer;
+    kp.t_cls = B.t_cls; kp.t_pixel = B.t_pixel; kp.t_e = B.t_e;
+    kp.t_steps = B.t_steps; kp.t_nc = B.t_nc; kp.t_nr = B.t_nr;
+    kp.adj = B.adj;
+    kp.grad = B.grad;
+    const void* mf = B.mode == kModeForward ? mc_func<kModeForward>()
+                   : B.mode == kModeTrace ? mc_func<kModeTrace>() : mc_func<kModeBackward>();
+    if (chunks > 0) ls.push_back(make_launch(mf, dim3(grid), dim3(block), lds, kp));
+    // ---- finalize ----
+    if (B.mode == kModeForward) {
+        int maxpix = 1;
+        for (int k = 0; k < B.n_jobs; ++k) maxpix = std::max(maxpix, B.jobs[k].geom.nu * B.jobs[k].geom.nv);
+        FinParams fp{L.jobs, B.n_jobs, L.tally, B.out, L.out_off, B.flags};
+        ls.push_back(make_launch((const void*)&finalize_kernel,
+                                 dim3((unsigned)std::min(1024, (4 * maxpix + 255) / 256), (unsigned)B.n_jobs), dim3(256), 0, fp));
+    }
+    return B.use_graph ? run_graph(ls, st) : run_direct(ls, st);
+}
+
+size_t batch_bytes(const gdrr_physics* phys, const gdrr_source* srcs, int n_srcs, const gdrr_job* jobs, int n_jobs,
+                   int n_vols, bool need_maj) {
+    if (!phys || !srcs || !jobs || n_srcs < 1 || n_srcs > GDRR_MAX_SOURCES || n_jobs < 1 || n_vols < 1) return 0;
+    return carve(nullptr, phys, srcs, n_srcs, n_jobs, n_vols, tally_elems_of(jobs, n_jobs, srcs), need_maj).bytes + 256;
+}
+
+gdrr_job single_job(const gdrr_geometry* geom, uint64_t n, uint32_t job_id) {
+    gdrr_job j{};
+    j.volume = 0;
+    j.source = 0;
+    j.geom = *geom;
+    j.n_photons = n;
+    j.job_id = job_id;
+    j.tally_offset = 0;
+    return j;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gdrr_last_error(void) { return g_err.c_str(); }
+
+const char* gdrr_version(void) { return "gdrr-mi355x 0.1"; }
+
+int gdrr_init(void) {
+    DevInfo d;
+    return device_info(d);
+}
+
+int gdrr_default_tuning(gdrr_tuning* out) {
+    if (!out) return fail(GDRR_EINVAL, "out is NULL");
+    out->block = 256;
+    out->blocks_per_cu = 0;
+    out->chunk = 0;
+    out->defer = 8;
+    return GDRR_OK;
+}
+
+size_t gdrr_majorant_workspace(void) { return 4096; }
+
+int gdrr_majorant(const gdrr_volume* vol, const gdrr_physics* phys, uint32_t flags, float margin, float* out,
+                  void* workspace, size_t ws_bytes, void* stream) {
+    int rc;
+    if ((rc = check_volume(vol)) || (rc = check_physics(phys))) return rc;
+    if (!out) return fail(GDRR_EINVAL, "out is NULL");
+    if (!(margin >= 0.0f) || !std::isfinite(margin)) return fail(GDRR_EINVAL, "margin must be finite and >= 0");
+    if (!workspace || ws_bytes < gdrr_majorant_workspace()) return fail(GDRR_EINVAL, "workspace too small");
+    DevInfo dev;
+    if ((rc = device_info(dev))) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    unsigned int* rmax = (unsigned int*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    unsigned int* pres = rmax + 256;
+    unsigned int* err = pres + 256;
+    std::vector<Launch> ls;
+    FillParams f{(unsigned long long*)rmax, 257};
+    ls.push_back(make_launch((const void*)&fill_zero_kernel, dim3(2), dim3(256), 0, f));
+    MajParams m{vol->density, vol->material, vol->nx, vol->ny, vol->nz, (flags & GDRR_INTERP_DENSITY) ? 1 : 0,
+                rmax, pres, err};
+    const long long nvox = (long long)vol->nx * vol->ny * vol->nz;
+    const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>(dev.cus * 8, (nvox + 255) / 256));
+    ls.push_back(make_launch((const void*)&rho_max_kernel, dim3(g), dim3(256), 0, m));
+    MajFinParams fp{rmax, pres, phys->mu_mass, phys->n_mat, phys->n_e, 1.0 + (double)margin, out, err};
+    ls.push_back(make_launch((const void*)&majorant_kernel, dim3((phys->n_e + 254) / 256), dim3(256), 0, fp));
+    return run_direct(ls, st);
+}
+
+size_t gdrr_mc_project_workspace(const gdrr_physics* phys, const gdrr_source* src, const gdrr_geometry* geom) {
+    if (!geom) return 0;
+    gdrr_job j = single_job(geom, 0, 0);
+    return batch_bytes(phys, src, 1, &j, 1, 1, true);
+}
+
+int gdrr_mc_project(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr_source* src,
+                    const gdrr_geometry* geom, const float* majorant, uint64_t seed, uint64_t n_photons,
+                    uint32_t job_id, uint32_t flags, double* tally, void* workspace, size_t ws_bytes,
+                    void* stream) {
+    if (!geom) return fail(GDRR_EINVAL, "geometry is NULL");
+    if (!tally) return fail(GDRR_EINVAL, "tally is NULL");
+    gdrr_job j = single_job(geom, n_photons, job_id);
+    Batch B{vol, 1, phys, src, 1, &j, 1, majorant, seed, flags, nullptr, kModeForward, -1, tally,
+            nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, false};
+    return run_batch(B, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+size_t gdrr_mc_project_batch_workspace(const gdrr_physics* phys, const gdrr_source* srcs, int32_t n_srcs,
+                                       const gdrr_job* jobs, int32_t n_jobs) {
+    return batch_bytes(phys, srcs, n_srcs, jobs, n_jobs, GDRR_MAX_VOLUMES, true);
+}
+
+int gdrr_mc_project_batch(const gdrr_volume* vols, int32_t n_vols, const gdrr_physics* phys,
+                          const gdrr_source* srcs, int32_t n_srcs, const gdrr_job* jobs, int32_t n_jobs,
+                          const float* majorants, uint64_t seed, uint32_t flags, const gdrr_tuning* tune,
+                          double* tallies, void* workspace, size_t ws_bytes, void* stream) {
+    if (!tallies) return fail(GDRR_EINVAL, "tallies is NULL");
+    Batch B{vols, n_vols, phys, srcs, n_srcs, jobs, n_jobs, majorants, seed, flags, tune, kModeForward, -1,
+            tallies, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, true};
+    return run_batch(B, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+int gdrr_mc_backward(const gdrr_volume* vols, int32_t n_vols, const gdrr_physics* phys, const gdrr_source* srcs,
+                     int32_t n_srcs, const gdrr_job* jobs, int32_t n_jobs, int32_t volume, const float* majorants,
+                     uint64_t seed, uint32_t flags, const gdrr_tuning* tune, const double* adj,
+                     double* grad_density, void* workspace, size_t ws_bytes, void* stream) {
+    if (!majorants) return fail(GDRR_EINVAL, "the adjoint needs the forward's majorants");
+    if (!adj || !grad_density) return fail(GDRR_EINVAL, "adj / grad_density is NULL");
+    if (volume < 0 || volume >= n_vols) return fail(GDRR_EINVAL, "volume index out of range");
+    if (!(flags & GDRR_ACCUMULATE)) {
+        const gdrr_volume& V = vols[volume];
+        GradClearParams g{grad_density, (long long)V.nx * V.ny * V.nz};
+        void* a[1] = {&g};
+        GDRR_HIP(hipLaunchKernel((const void*)&grad_zero_kernel, dim3(1024), dim3(256), a, 0, (hipStream_t)stream));
+    }
+    Batch B{vols, n_vols, phys, srcs, n_srcs, jobs, n_jobs, majorants, seed, flags, tune, kModeBackward, volume,
+            nullptr, adj, grad_density, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, false};
+    return run_batch(B, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+int gdrr_mc_trace(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr_source* src,
+                  const gdrr_geometry* geom, const float* majorant, uint64_t seed, uint64_t n_photons,
+                  uint32_t job_id, uint32_t flags, int8_t* cls, int32_t* pixel, float* e_final, int32_t* steps,
+                  int32_t* n_compton, int32_t* n_rayleigh, void* workspace, size_t ws_bytes, void* stream) {
+    if (!geom) return fail(GDRR_EINVAL, "geometry is NULL");
+    gdrr_job j = single_job(geom, n_photons, job_id);
+    Batch B{vol, 1, phys, src, 1, &j, 1, majorant, seed, flags, nullptr, kModeTrace, -1, nullptr, nullptr,
+            nullptr, cls, pixel, e_final, steps, n_compton, n_rayleigh, false};
+    return run_batch(B, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+}  // extern "C"

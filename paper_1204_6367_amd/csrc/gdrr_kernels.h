@@ -1,0 +1,623 @@
+// Kernels of the gfx950 Monte Carlo projection step (Step 2 of gDRR,
+// Sec. 2.4 of arXiv:1204.6367) and their launch parameters.
+//
+// One wavefront lane carries one photon history at a time.  Lanes live for
+// the whole launch (a persistent grid): a lane whose history ends takes the
+// next photon index of its wavefront's chunk, and wavefronts take chunks of
+// (job, photon range) from one atomic dispenser, so all the angles and
+// phantoms of a batch run in the same launch.  Each loop iteration has three
+// phases -- refill (start new histories), flight (one Woodcock step of every
+// flying lane) and collision (interaction sampling) -- and the two rare ones
+// run only when at least `defer` lanes wait for them, so that the
+// wavefront's SIMD lanes mostly execute the same free-flight code.
+#pragma once
+
+#include "gdrr_device.h"
+
+namespace gdrr {
+
+enum : int { kDead = 0, kFly = 1, kColl = 2 };
+enum : int { kModeForward = 0, kModeTrace = 1, kModeBackward = 2 };
+
+constexpr int kMaxVol = 8;
+constexpr int kMaxSrc = 8;
+
+struct KParams {
+    DVolume vol[kMaxVol];
+    DSource src[kMaxSrc];
+    const DJob* jobs;
+    const unsigned long long* chunk_prefix;   // [n_jobs + 1]: first chunk of each job
+    unsigned long long* counter;              // [0] chunk dispenser
+    unsigned long long* tally;                // fixed-point tallies
+    const float* mu_mass;                     // [n_mat][n_e][3]
+    const float* response;                    // [n_e] or null
+    const float* majorants;                   // [n_vols][n_e - 1], 1/cm
+    unsigned long long total_chunks;
+    int n_jobs, n_vols, n_mat, n_e;
+    float e0, inv_de, e_max, e_cut, x0;
+    uint32_t k0, k1;
+    uint32_t flags;
+    int chunk, defer;
+    // diagnostics (trace mode)
+    int8_t* t_cls;
+    int32_t* t_pixel;
+    float* t_e;
+    int32_t* t_steps;
+    int32_t* t_nc;
+    int32_t* t_nr;
+    // adjoint (backward mode)
+    const double* adj;
+    double* grad;
+};
+
+__host__ __device__ inline size_t lds_bytes(int n_mat, int n_e, int n_vols, bool resp) {
+    return (size_t)n_mat * n_e * 16 + (size_t)n_mat * n_e * 8 + (size_t)n_vols * (n_e - 1) * 8 +
+           (resp ? (size_t)n_e * 8 : 0);
+}
+
+struct Tables {
+    const float4* rc;     // [m][j] (R_j, R_j+1 - R_j, C_j, C_j+1 - C_j)
+    const float2* tot;    // [m][j] (tot_j, tot_j+1 - tot_j)
+    const float2* maj;    // [v][j] (mbar, mean free path per unit of -ln u, mm)
+    const float2* resp;   // [j] (r_j, r_j+1 - r_j)
+};
+
+// Energy-interval cache of a photon: interval index, fraction, majorant, mfp.
+struct ECache {
+    int j;
+    float f, mbar, mfp;
+};
+
+__device__ __forceinline__ ECache energy_cache(const KParams& P, const Tables& T, int vol_off, float E) {
+    const float g = (E - P.e0) * P.inv_de;
+    int j = (int)floorf(g);
+    j = j < 0 ? 0 : (j > P.n_e - 2 ? P.n_e - 2 : j);
+    const float2 m = T.maj[vol_off + j];
+    return ECache{j, g - (float)j, m.x, m.y};
+}
+
+// Density at x (tri-linear on the voxel-centre lattice, clamped to the edge
+// voxels; or the containing voxel's), the containing voxel's material, and --
+// for the adjoint -- the eight corner voxels and weights.
+template <bool WANT_STENCIL>
+__device__ __forceinline__ float density_at(const DVolume& V, bool interp, float px, float py, float pz,
+                                            int& mat, int* vox, float* wt) {
+    const float gx = (px - V.lox) * V.idx, gy = (py - V.loy) * V.idy, gz = (pz - V.loz) * V.idz;
+    int cx = (int)floorf(gx), cy = (int)floorf(gy), cz = (int)floorf(gz);
+    cx = min(max(cx, 0), V.nx - 1);
+    cy = min(max(cy, 0), V.ny - 1);
+    cz = min(max(cz, 0), V.nz - 1);
+    const int cvox = cz * V.nxy + cy * V.nx + cx;
+    mat = V.material[cvox];
+    if (!interp) {
+        if (WANT_STENCIL) { vox[0] = cvox; wt[0] = 1.0f; }
+        return V.density[cvox];
+    }
+    const float hx = gx - 0.5f, hy = gy - 0.5f, hz = gz - 0.5f;
+    const float fx0 = floorf(hx), fy0 = floorf(hy), fz0 = floorf(hz);
+    const float fx = hx - fx0, fy = hy - fy0, fz = hz - fz0;
+    const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
+    const int x0 = min(max(ix, 0), V.nx - 1), x1 = min(max(ix + 1, 0), V.nx - 1);
+    const int y0 = min(max(iy, 0), V.ny - 1) * V.nx, y1 = min(max(iy + 1, 0), V.ny - 1) * V.nx;
+    const int z0 = min(max(iz, 0), V.nz - 1) * V.nxy, z1 = min(max(iz + 1, 0), V.nz - 1) * V.nxy;
+    const float* __restrict__ d = V.density;
+    const float c000 = d[z0 + y0 + x0], c001 = d[z0 + y0 + x1];
+    const float c010 = d[z0 + y1 + x0], c011 = d[z0 + y1 + x1];
+    const float c100 = d[z1 + y0 + x0], c101 = d[z1 + y0 + x1];
+    const float c110 = d[z1 + y1 + x0], c111 = d[z1 + y1 + x1];
+    const float a00 = c000 + fx * (c001 - c000), a01 = c010 + fx * (c011 - c010);
+    const float a10 = c100 + fx * (c101 - c100), a11 = c110 + fx * (c111 - c110);
+    const float b0 = a00 + fy * (a01 - a00), b1 = a10 + fy * (a11 - a10);
+    if (WANT_STENCIL) {
+        const float gx0 = 1.0f - fx, gy0 = 1.0f - fy, gz0 = 1.0f - fz;
+        vox[0] = z0 + y0 + x0; wt[0] = gx0 * gy0 * gz0;
+        vox[1] = z0 + y0 + x1; wt[1] = fx * gy0 * gz0;
+        vox[2] = z0 + y1 + x0; wt[2] = gx0 * fy * gz0;
+        vox[3] = z0 + y1 + x1; wt[3] = fx * fy * gz0;
+        vox[4] = z1 + y0 + x0; wt[4] = gx0 * gy0 * fz;
+        vox[5] = z1 + y0 + x1; wt[5] = fx * gy0 * fz;
+        vox[6] = z1 + y1 + x0; wt[6] = gx0 * fy * fz;
+        vox[7] = z1 + y1 + x1; wt[7] = fx * fy * fz;
+    }
+    return b0 + fz * (b1 - b0);
+}
+
+__device__ __forceinline__ float response_at(const KParams& P, const Tables& T, const ECache& ec, float E) {
+    if (!P.response) return E;
+    const float2 r = T.resp[ec.j];
+    return r.x + ec.f * r.y;
+}
+
+// Per-lane photon state.
+struct Photon {
+    float px, py, pz, dx, dy, dz, E, trem;
+    uint32_t pid, step, jid;   // photon index, free flights so far, Philox job word
+    int job;                   // index into the job table
+    int pix0;                  // sampled aim pixel (the pixel of a primary)
+    uint32_t nsc;              // Compton count | Rayleigh count << 16
+    int st;
+    bool passb;                // adjoint: second (visiting) pass
+    ECache ec;
+    float pu2, pu3;            // pending collision: type and azimuth uniforms
+    int pm;                    // pending collision: material
+    float w;                   // adjoint weight of the history
+};
+
+// Source photon (Sec. 2.1/2.4): energy channel and aim pixel by inverse CDF,
+// aim point uniform inside the pixel, straight line from S to the phantom.
+// Returns true if the photon enters the phantom; otherwise it reaches its
+// aim pixel unscattered.
+__device__ __forceinline__ bool start_photon(const KParams& P, const Tables& T, const DVolume& V, int vol_off,
+                                             Photon& ph) {
+    const DJob& J = P.jobs[ph.job];
+    const DSource& S = P.src[J.src];
+    const Block b0 = philox(ph.pid, ph.jid, 0u, 0u, P.k0, P.k1);
+    const Block b1 = philox(ph.pid, ph.jid, 0u, 1u, P.k0, P.k1);
+    const int ke = sample_cdf(S.spec_cdf, S.spec_guide, S.n_spec, S.spec_k, u53(b0.x, b0.y));
+    const int kf = sample_cdf(S.flu_cdf, S.flu_guide, S.npix, S.flu_k, u53(b0.z, b0.w));
+    const int iv = kf / J.nu, iu = kf - iv * J.nu;
+    const float uc = ((float)iu + u24(b1.x) - 0.5f * (float)J.nu) * J.du;
+    const float vc = ((float)iv + u24(b1.y) - 0.5f * (float)J.nv) * J.dv;
+    float dx = J.Px + uc * J.ux - J.Sx;
+    float dy = J.Py + uc * J.uy - J.Sy;
+    float dz = J.Pz + uc * J.uz + vc - J.Sz;
+    const float inv = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
+    dx *= inv; dy *= inv; dz *= inv;
+    ph.dx = dx; ph.dy = dy; ph.dz = dz;
+    ph.E = fminf(fmaxf(S.spec_e[ke], P.e0), P.e_max);
+    ph.ec = energy_cache(P, T, vol_off, ph.E);
+    ph.step = 0;
+    ph.nsc = 0;
+    ph.pix0 = kf;
+    float tin, tout;
+    if (box_entry(V, J.Sx, J.Sy, J.Sz, dx, dy, dz, tin, tout)) {
+        ph.px = J.Sx + tin * dx;
+        ph.py = J.Sy + tin * dy;
+        ph.pz = J.Sz + tin * dz;
+        ph.trem = tout - tin;
+        return true;
+    }
+    return false;
+}
+
+// Detector hit of a photon leaving the phantom: the primary pixel for an
+// unscattered photon, else the intersection of its line with the detector
+// plane (half-open pixels).  Returns the class (primary / scatter / missed).
+__device__ __forceinline__ int detector_pixel(const DJob& J, const Photon& ph, int& pixel) {
+    if (ph.nsc == 0) { pixel = ph.pix0; return kPrimary; }
+    const float dn = ph.dx * J.nx + ph.dy * J.ny + ph.dz * J.nz;
+    pixel = -1;
+    if (!(dn > 0.0f)) return kMissed;
+    const float t = ((J.Px - ph.px) * J.nx + (J.Py - ph.py) * J.ny + (J.Pz - ph.pz) * J.nz) / dn;
+    if (!(t >= 0.0f)) return kMissed;
+    const float hx = ph.px + t * ph.dx - J.Px, hy = ph.py + t * ph.dy - J.Py, hz = ph.pz + t * ph.dz - J.Pz;
+    const float fu = (hx * J.ux + hy * J.uy + hz * J.uz) * J.idu + 0.5f * (float)J.nu;
+    const float fv = hz * J.idv + 0.5f * (float)J.nv;
+    const float ku = floorf(fu), kv = floorf(fv);
+    if (ku >= 0.0f && ku < (float)J.nu && kv >= 0.0f && kv < (float)J.nv) {
+        pixel = (int)kv * J.nu + (int)ku;
+        return kScatter;
+    }
+    return kMissed;
+}
+
+__device__ __forceinline__ bool counts_as_scatter(uint32_t flags, uint32_t nsc) {
+    const uint32_t nc = nsc & 0xFFFFu, nr = nsc >> 16;
+    if (flags & 16u) return nc == 1 && nr == 0;
+    if (flags & 8u) return nc + nr == 1;
+    return true;
+}
+
+__device__ __forceinline__ void tally_add(const KParams& P, const DJob& J, int cls, int pixel, float r) {
+    const int npix = J.nu * J.nv;
+    unsigned long long* t = P.tally + J.tally_off + (cls == kPrimary ? 0 : 2 * npix) + pixel;
+    const double rd = (double)r;
+    atomicAdd(t, (unsigned long long)__double2ll_rn(rd * kQ1));
+    if (P.flags & 2u) atomicAdd(t + npix, (unsigned long long)__double2ll_rn(rd * rd * kQ2));
+}
+
+template <int MODE>
+__device__ __forceinline__ void trace_out(const KParams& P, const Photon& ph, int cls, int pixel) {
+    if (MODE != kModeTrace) return;
+    const uint32_t i = ph.pid;
+    if (P.t_cls) P.t_cls[i] = (int8_t)cls;
+    if (P.t_pixel) P.t_pixel[i] = pixel;
+    if (P.t_e) P.t_e[i] = ph.E;
+    if (P.t_steps) P.t_steps[i] = (int32_t)ph.step;
+    if (P.t_nc) P.t_nc[i] = (int32_t)(ph.nsc & 0xFFFFu);
+    if (P.t_nr) P.t_nr[i] = (int32_t)(ph.nsc >> 16);
+}
+
+// The end of a history: score it (forward), record it (trace) or turn it
+// into the adjoint's visiting pass (backward).
+template <int MODE>
+__device__ __forceinline__ void finish(const KParams& P, const Tables& T, const DVolume& V, int vol_off,
+                                      Photon& ph, int cls, int pixel) {
+    const DJob& J = P.jobs[ph.job];
+    const bool counted = cls == kPrimary || (cls == kScatter && counts_as_scatter(P.flags, ph.nsc));
+    if (MODE == kModeTrace) trace_out<MODE>(P, ph, cls, pixel);
+    if (MODE == kModeForward) {
+        if (counted) tally_add(P, J, cls, pixel, fminf(fmaxf(response_at(P, T, ph.ec, ph.E), 0.0f), kMaxResponse));
+        ph.st = kDead;
+        return;
+    }
+    if (MODE == kModeBackward && !ph.passb && counted) {
+        const double n = (double)J.n_lo + 4294967296.0 * (double)J.n_hi;
+        const int npix = J.nu * J.nv;
+        const double a = P.adj[J.adj_off + (cls == kPrimary ? 0 : npix) + pixel];
+        const float r = fminf(fmaxf(response_at(P, T, ph.ec, ph.E), 0.0f), kMaxResponse);
+        const float w = (float)(a * (double)r / n);
+        if (w != 0.0f) {
+            ph.w = w;
+            ph.passb = true;
+            ph.st = start_photon(P, T, V, vol_off, ph) ? kFly : kDead;
+            return;
+        }
+    }
+    ph.st = kDead;
+}
+
+// Score-function terms of one tentative collision (adjoint, second pass).
+__device__ __forceinline__ void visit(const KParams& P, const DVolume& V, bool interp, const Photon& ph,
+                                      bool real, float rho, float tot, float mbar) {
+    int vox[8];
+    float wt[8];
+    int m;
+    density_at<true>(V, interp, ph.px, ph.py, ph.pz, m, vox, wt);
+    const int n = interp ? 8 : 1;
+    const float base = real ? 1.0f / rho : -tot / (mbar - rho * tot);
+    for (int k = 0; k < n; ++k) {
+        const float s = base * wt[k];
+        if (s != 0.0f) unsafeAtomicAdd(P.grad + vox[k], (double)ph.w * (double)s);
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
+    extern __shared__ float4 lds[];
+    // ---- stage the per-launch tables in LDS ----
+    float4* s_rc = lds;
+    float2* s_tot = reinterpret_cast<float2*>(s_rc + P.n_mat * P.n_e);
+    float2* s_maj = s_tot + P.n_mat * P.n_e;
+    float2* s_resp = s_maj + P.n_vols * (P.n_e - 1);
+    for (int i = threadIdx.x; i < P.n_mat * P.n_e; i += blockDim.x) {
+        const int j = i % P.n_e;
+        const float* a = P.mu_mass + (size_t)i * 3;
+        const float* b = j + 1 < P.n_e ? a + 3 : a;
+        const float r0 = a[0], c0 = a[1], p0 = a[2], r1 = b[0], c1 = b[1], p1 = b[2];
+        s_rc[i] = make_float4(r0, r1 - r0, c0, c1 - c0);
+        const float t0 = r0 + c0 + p0, t1 = r1 + c1 + p1;
+        s_tot[i] = make_float2(t0, t1 - t0);
+    }
+    for (int i = threadIdx.x; i < P.n_vols * (P.n_e - 1); i += blockDim.x) {
+        const float mb = P.majorants[i];
+        s_maj[i] = make_float2(mb, mb > 0.0f ? 1.0f / (0.1f * mb) : INFINITY);
+    }
+    if (P.response)
+        for (int i = threadIdx.x; i < P.n_e; i += blockDim.x) {
+            const float r0 = P.response[i], r1 = P.response[i + 1 < P.n_e ? i + 1 : i];
+            s_resp[i] = make_float2(r0, r1 - r0);
+        }
+    __syncthreads();
+    const Tables T{s_rc, s_tot, s_maj, s_resp};
+    const bool interp = (P.flags & 1u) != 0;
+    const int lane = __lane_id();
+    const uint64_t lt = (1ull << lane) - 1ull;
+
+    Photon ph;
+    ph.st = kDead;
+    ph.passb = false;
+    ph.w = 0.0f;
+    ph.job = 0;
+    ph.pid = 0;
+    ph.jid = 0;
+    ph.nsc = 0;
+    ph.pu2 = ph.pu3 = 0.0f;
+    ph.pm = 0;
+
+    // wavefront-uniform dispenser state
+    int w_vol = -1, w_job = 0, w_hold = 0, w_done = 0;
+    uint32_t w_next = 0, w_end = 0;
+
+    for (;;) {
+        const uint64_t dead = __ballot(ph.st == kDead);
+        const int n_dead = __popcll(dead);
+        const int n_coll = __popcll(__ballot(ph.st == kColl));
+        const int n_fly = 64 - n_dead - n_coll;
+
+        // ---- refill ----
+        if (w_hold && n_dead == 64) {       // drained: switch to the held chunk's phantom
+            w_vol = __builtin_amdgcn_readfirstlane(P.jobs[w_job].vol);
+            w_hold = 0;
+        }
+        if (!w_done && !w_hold && n_dead > 0 && (n_dead >= P.defer || n_fly == 0)) {
+            if (w_next >= w_end) {
+                unsigned long long c = 0;
+                if (lane == 0) c = atomicAdd(P.counter, 1ull);
+                c = __shfl(c, 0);
+                if (c >= P.total_chunks) {
+                    w_done = 1;
+                } else {
+                    int lo = 0, hi = P.n_jobs - 1;          // last job whose first chunk <= c
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (P.chunk_prefix[mid] <= c) lo = mid; else hi = mid - 1;
+                    }
+                    w_job = __builtin_amdgcn_readfirstlane(lo);
+                    const DJob& J = P.jobs[w_job];
+                    const unsigned long long nph = (unsigned long long)J.n_lo | ((unsigned long long)J.n_hi << 32);
+                    const unsigned long long first = (c - P.chunk_prefix[w_job]) * (unsigned long long)P.chunk;
+                    const unsigned long long last = first + (unsigned long long)P.chunk < nph ? first + P.chunk : nph;
+                    w_next = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)first);
+                    w_end = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)last);
+                    const int v = __builtin_amdgcn_readfirstlane(J.vol);
+                    if (v != w_vol) {
+                        if (n_dead == 64) w_vol = v; else w_hold = 1;
+                    }
+                }
+            }
+            if (!w_done && !w_hold) {
+                const uint32_t avail = w_end - w_next;
+                const uint32_t rank = (uint32_t)__popcll(dead & lt);
+                if (ph.st == kDead && rank < avail) {
+                    ph.pid = w_next + rank;
+                    ph.job = w_job;
+                    ph.jid = P.jobs[w_job].job_id;
+                    ph.passb = false;
+                    const DVolume& V = P.vol[w_vol];
+                    const int vo = V.lds_majorant;
+                    if (start_photon(P, T, V, vo, ph)) ph.st = kFly;
+                    else finish<MODE>(P, T, V, vo, ph, kPrimary, ph.pix0);
+                }
+                w_next += (uint32_t)n_dead < avail ? (uint32_t)n_dead : avail;
+            }
+        }
+        if (w_done && n_dead == 64) break;
+        if (w_vol < 0) continue;
+        const DVolume& V = P.vol[w_vol];
+        const int vo = V.lds_majorant;
+
+        // ---- flight: one Woodcock step (Sec. 2.4) ----
+        if (ph.st == kFly && ph.step >= kMaxSteps) {          // step limit: the history is lost
+            if (MODE == kModeTrace) trace_out<MODE>(P, ph, kLost, -1);
+            ph.st = kDead;
+        }
+        if (ph.st == kFly) {
+            ph.step += 1;
+            const Block b = philox(ph.pid, ph.jid, ph.step, 0u, P.k0, P.k1);
+            const float s = -fast_log(u24(b.x)) * ph.ec.mfp;
+            if (!(s < ph.trem)) {
+                int pixel;
+                const int cls = detector_pixel(P.jobs[ph.job], ph, pixel);
+                finish<MODE>(P, T, V, vo, ph, cls, pixel);
+            } else {
+                ph.px += s * ph.dx;
+                ph.py += s * ph.dy;
+                ph.pz += s * ph.dz;
+                ph.trem -= s;
+                int m;
+                const float rho = density_at<false>(V, interp, ph.px, ph.py, ph.pz, m, nullptr, nullptr);
+                m = m < P.n_mat ? m : P.n_mat - 1;
+                const float2 tt = T.tot[m * P.n_e + ph.ec.j];
+                const float tot = tt.x + ph.ec.f * tt.y;
+                const bool real = u24(b.y) * ph.ec.mbar < rho * tot;
+                if (MODE == kModeBackward && ph.passb) visit(P, V, interp, ph, real, rho, tot, ph.ec.mbar);
+                if (real) {
+                    ph.st = kColl;
+                    ph.pu2 = u24(b.z);
+                    ph.pu3 = u24(b.w);
+                    ph.pm = m;
+                }
+            }
+        }
+
+        // ---- collision: interaction type and sampling ----
+        const int n_coll2 = __popcll(__ballot(ph.st == kColl));
+        const int n_fly2 = __popcll(__ballot(ph.st == kFly));
+        if (n_coll2 > 0 && (n_coll2 >= P.defer || n_fly2 == 0 || w_done || w_hold)) {
+            if (ph.st == kColl) {
+                const int m = ph.pm;
+                const float4 rc = T.rc[m * P.n_e + ph.ec.j];
+                const float2 tt = T.tot[m * P.n_e + ph.ec.j];
+                const float R = rc.x + ph.ec.f * rc.y;
+                const float C = rc.z + ph.ec.f * rc.w;
+                const float sel = ph.pu2 * (tt.x + ph.ec.f * tt.y);
+                float ct;
+                bool alive = true;
+                if (sel < R) {
+                    ct = rayleigh(ph.pid, ph.jid, ph.step, P.k0, P.k1, ph.E, P.x0);
+                    ph.nsc += 1u << 16;
+                } else if (sel < R + C) {
+                    ct = compton(ph.pid, ph.jid, ph.step, P.k0, P.k1, ph.E);
+                    ph.nsc += 1u;
+                    ph.ec = energy_cache(P, T, vo, ph.E);
+                } else {
+                    ct = 1.0f;
+                    alive = false;
+                    if (MODE == kModeTrace) trace_out<MODE>(P, ph, kAbsorbed, -1);
+                    ph.st = kDead;
+                }
+                if (alive) {
+                    rotate(ph.dx, ph.dy, ph.dz, ct, ph.pu3);
+                    if (ph.E < P.e_cut) {
+                        if (MODE == kModeTrace) trace_out<MODE>(P, ph, kCut, -1);
+                        ph.st = kDead;
+                    } else {
+                        ph.trem = box_exit(V, ph.px, ph.py, ph.pz, ph.dx, ph.dy, ph.dz);
+                        ph.st = kFly;
+                    }
+                }
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Majorant: per-material maximum density (over the 3x3x3 neighbourhood with
+// interpolation), then per energy interval the maximum over materials.
+// ---------------------------------------------------------------------------
+struct MajParams {
+    const float* density;
+    const uint8_t* material;
+    int nx, ny, nz;
+    int interp;
+    unsigned int* rho_max;       // [256] float bits, zeroed
+    unsigned int* present;       // [256], zeroed
+    unsigned int* error;         // error word
+};
+
+__global__ __launch_bounds__(256) void rho_max_kernel(MajParams M) {
+    __shared__ unsigned int s_max[256];
+    __shared__ unsigned int s_pres[256];
+    s_max[threadIdx.x] = 0u;
+    s_pres[threadIdx.x] = 0u;
+    __syncthreads();
+    const long long n = (long long)M.nx * M.ny * M.nz;
+    const long long nxy = (long long)M.nx * M.ny;
+    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < n;
+         v += (long long)gridDim.x * blockDim.x) {
+        const int m = M.material[v];
+        float r = M.density[v];
+        if (!(r >= 0.0f) || isinf(r)) { atomicOr(M.error, 1u); r = 0.0f; }
+        if (M.interp) {
+            const int z = (int)(v / nxy), y = (int)((v / M.nx) % M.ny), x = (int)(v % M.nx);
+            for (int dz = -1; dz <= 1; ++dz) {
+                const int zz = min(max(z + dz, 0), M.nz - 1);
+                for (int dy = -1; dy <= 1; ++dy) {
+                    const int yy = min(max(y + dy, 0), M.ny - 1);
+                    const float* row = M.density + (long long)zz * nxy + (long long)yy * M.nx;
+                    for (int dx = -1; dx <= 1; ++dx) {
+                        const float q = row[min(max(x + dx, 0), M.nx - 1)];
+                        r = q > r ? q : r;
+                    }
+                }
+            }
+        }
+        atomicMax(&s_max[m], __float_as_uint(r));
+        s_pres[m] = 1u;
+    }
+    __syncthreads();
+    if (s_pres[threadIdx.x]) {
+        atomicMax(&M.rho_max[threadIdx.x], s_max[threadIdx.x]);
+        atomicOr(&M.present[threadIdx.x], 1u);
+    }
+}
+
+struct MajFinParams {
+    const unsigned int* rho_max;
+    const unsigned int* present;
+    const float* mu_mass;
+    int n_mat, n_e;
+    double scale;              // 1 + margin
+    float* out;                // [n_e - 1]
+    unsigned int* error;
+};
+
+__global__ __launch_bounds__(256) void majorant_kernel(MajFinParams F) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < F.n_e - 1; j += gridDim.x * blockDim.x) {
+        double best = 0.0;
+        for (int m = 0; m < F.n_mat; ++m) {
+            if (!F.present[m]) continue;
+            const float* a = F.mu_mass + ((size_t)m * F.n_e + j) * 3;
+            const double t0 = (double)a[0] + (double)a[1] + (double)a[2];
+            const double t1 = (double)a[3] + (double)a[4] + (double)a[5];
+            const double t = (double)__uint_as_float(F.rho_max[m]) * (t0 > t1 ? t0 : t1);
+            best = t > best ? t : best;
+        }
+        F.out[j] = __double2float_ru(best * F.scale);
+    }
+    if (blockIdx.x == 0 && threadIdx.x < 256 - F.n_mat && F.present[F.n_mat + threadIdx.x])
+        atomicOr(F.error, 2u);   // material index out of range
+}
+
+// ---------------------------------------------------------------------------
+// Source preparation: normalised CDFs (running float64 sum in index order,
+// divided by the total) and guide tables.
+// ---------------------------------------------------------------------------
+struct SrcPrepParams {
+    const float* w;
+    int n;
+    double* cdf;
+    uint32_t* guide;
+    int k;
+    unsigned int* error;
+};
+
+__global__ __launch_bounds__(256) void cdf_kernel(SrcPrepParams S) {
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        int bad = 0;
+        for (int i = 0; i < S.n; ++i) {
+            const double x = (double)S.w[i];
+            if (!(x >= 0.0) || isinf(x)) bad = 1;
+            s += x;
+            S.cdf[i] = s;
+        }
+        if (!(s > 0.0)) bad = 1;
+        if (bad) atomicOr(S.error, 4u);
+        for (int i = 0; i < S.n; ++i) S.cdf[i] = S.cdf[i] / s;
+    }
+}
+
+__global__ __launch_bounds__(256) void guide_kernel(SrcPrepParams S) {
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < S.k; g += gridDim.x * blockDim.x) {
+        const double t = (double)g / (double)S.k;
+        int lo = 0, hi = S.n - 1;                 // smallest i with cdf[i] > t
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (S.cdf[mid] > t) hi = mid; else lo = mid + 1;
+        }
+        S.guide[g] = (uint32_t)lo;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Clear and finalize.
+// ---------------------------------------------------------------------------
+struct FillParams {
+    unsigned long long* p;
+    long long n;
+};
+
+__global__ __launch_bounds__(256) void fill_zero_kernel(FillParams F) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < F.n; i += (long long)gridDim.x * blockDim.x)
+        F.p[i] = 0ull;
+}
+
+struct FinParams {
+    const DJob* jobs;
+    int n_jobs;
+    const unsigned long long* tally;
+    double* out;
+    const long long* out_off;   // [n_jobs] double element offsets in `out`
+    uint32_t flags;
+};
+
+__global__ __launch_bounds__(256) void finalize_kernel(FinParams F) {
+    const int k = blockIdx.y;
+    const DJob& J = F.jobs[k];
+    const int npix = J.nu * J.nv;
+    const double n = (double)J.n_lo + 4294967296.0 * (double)J.n_hi;
+    const double inv = n > 0.0 ? 1.0 / n : 0.0;
+    const bool sumsq = (F.flags & 2u) != 0, acc = (F.flags & 4u) != 0;
+    double* out = F.out + F.out_off[k];
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 4 * npix; i += gridDim.x * blockDim.x) {
+        const int plane = i / npix;
+        if ((plane & 1) && !sumsq) continue;
+        const double q = (plane & 1) ? kQ2 : kQ1;
+        const double v = (double)F.tally[J.tally_off + i] / q * inv;
+        out[i] = acc ? out[i] + v : v;
+    }
+}
+
+struct GradClearParams {
+    double* p;
+    long long n;
+};
+
+__global__ __launch_bounds__(256) void grad_zero_kernel(GradClearParams G) {
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < G.n; i += (long long)gridDim.x * blockDim.x)
+        G.p[i] = 0.0;
+}
+
+}  // namespace gdrr
