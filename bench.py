@@ -1,0 +1,314 @@
+"""Benchmark of the gfx950 Monte Carlo projection step.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c4]
+
+One step runs every stage of the hot path over one batch of synthetic input:
+majorants, source tables, the persistent batched transport kernel with its
+scoring and finalisation, and (for workloads with a loss) the path-replay
+adjoint.  Inputs are resident in HBM before the timed region.  Prints ONE
+JSON line with the whole-step histories/s, the roofline of the transport
+kernel (timed with HIP events on its own stream, inside the library) and the
+CPU oracle timed on a bounded sample of the same workload.
+
+Workloads (synthetic, seeded; sizes of the paper's CBCT setting):
+  c1  one projection: 256x256x160 ellipsoid phantom, 120 kVp + bowtie, 1e8 photons
+  c2  360 angles of the c1 phantom, 1e7 photons each, one persistent launch
+  c3  adjoint: 128x128x96 phantom, 1e7 photons, loss 0.5 ||S - S*||^2
+  c4  three phantoms (512^2x256, 256^2x160, 128^2x64) at 60/120/360 angles,
+      1e8/3e7/1e7 photons per angle, then the adjoint of the second phantom
+      at 30 of its angles
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "photon histories/sec (fwd, batched angles) + adjoint histories/sec, 1×MI355X"
+
+# MI355X peaks used for the roofline fractions
+HBM_PEAK_GBS = 8000.0
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # 32-bit VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
+
+# Work model of one history (algorithmic units; see the design notes):
+# 32-bit VALU issue slots (quarter-rate integer multiplies and transcendentals
+# count 4) and bytes the algorithm must gather.
+SLOTS_PHILOX = 10 * (4 * 4 + 2)          # 2 mul_hi + 2 mul_lo (quarter rate) + 2 xor3 per round
+SLOTS_FLIGHT_IN = SLOTS_PHILOX + 6 + 7 + 4 + 64 + 7     # uniforms, -ln u, move, trilinear, lookup+accept
+SLOTS_FLIGHT_OUT = SLOTS_PHILOX + 6 + 7 + 30           # the escaping flight: detector intersection
+SLOTS_TRY = SLOTS_PHILOX + 9 + 30                      # one angular-sampler try
+SLOTS_COLLISION = 6 + 55 + 40 + 10                     # type select, rotation, box exit, energy cache
+SLOTS_SOURCE = 2 * SLOTS_PHILOX + 40 + 34 + 45         # two blocks, CDFs (fp64), aim point, box entry
+BYTES_FLIGHT_IN = 8 * 4 + 1                            # eight density corners + the material byte
+BYTES_SOURCE = 2 * (2 * 8 + 4) + 4                     # CDF + guide reads for energy and pixel, energy
+BYTES_SCORE = 8                                        # one fixed-point atomic
+
+
+def work_per_history(stats, n):
+    """Average algorithmic VALU slots and bytes per history from oracle counts."""
+    h = float(n)
+    entered = h * 1.0
+    flights = stats["steps"] / h
+    real = stats["real"] / h
+    tries = stats["tries"] / h
+    scatter_events = (stats["compton"] + stats["rayleigh"]) / h
+    scored = (stats["classes"]["primary"] + stats["classes"]["scatter"]) / h
+    # every history that entered the phantom ends its last flight by escaping
+    # (or is absorbed/cut at a collision); in-box flights = flights - escapes
+    escapes = (stats["classes"]["primary"] + stats["classes"]["scatter"] + stats["classes"]["missed"]) / h
+    inbox = max(flights - escapes, 0.0)
+    slots = (inbox * SLOTS_FLIGHT_IN + escapes * SLOTS_FLIGHT_OUT + tries * SLOTS_TRY
+             + real * 6 + scatter_events * (SLOTS_COLLISION - 6) + SLOTS_SOURCE)
+    nbytes = inbox * BYTES_FLIGHT_IN + BYTES_SOURCE + scored * BYTES_SCORE
+    return dict(slots=slots, bytes=nbytes, flights=flights, inbox_flights=inbox, real=real, tries=tries)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ---------------------------------------------------------------------------
+# workloads
+# ---------------------------------------------------------------------------
+def build_workload(name, api, W, torch):
+    """Returns dict(step=callable, fwd_histories, adj_histories, oracle_sample=callable, info)."""
+    if name in ("c1", "c2"):
+        prob = W.pelvis_problem(100_000_000)
+        vol, phys, src = api.upload(prob)
+        if name == "c1":
+            jobs = [api.JobSpec(prob.geom, 100_000_000, 0)]
+        else:
+            jobs = [api.JobSpec(prob.geom.replace(phi_rad=float(a)), 10_000_000, k)
+                    for k, a in enumerate(np.deg2rad(np.arange(360.0)))]
+        batch = api.Batch([vol], phys, [src], jobs)
+        tallies = torch.zeros(batch.tally_elems, dtype=torch.float64, device="cuda")
+        fwd = sum(j.n_photons for j in jobs)
+
+        def step():
+            maj = batch.majorants(True)
+            batch.project(seed=1, majorants=maj, out=tallies)
+            return [api.last_kernel_ms()]
+
+        samples = [(prob, float(jobs[k].geom.phi_rad), jobs[k].job_id) for k in (0, len(jobs) // 2)]
+        return dict(step=step, fwd=fwd, adj=0, samples=samples, adjoint=None,
+                    config=dict(workload=name, phantom="256x256x160 @1.95x1.95x2.5mm ellipsoids",
+                                angles=len(jobs), photons_per_angle=jobs[0].n_photons,
+                                detector="256x192 @1.552mm", spectrum="120 kVp Kramers + 2.5 mm Al, bowtie 30 mm Al"))
+    if name in ("c3", "c4"):
+        if name == "c3":
+            prob, target = W.adjoint_problem(10_000_000)
+            phantoms = [(prob.phantom, target)]
+            plan = [(0, 1, 10_000_000)]                      # (volume, n_angles, photons)
+            adj_vol, adj_jobs_every = 0, 1
+        else:
+            phantoms = []
+            plan = []
+            for v, (shape, sp, seed, n_ang, nph) in enumerate(W.MULTI_PHANTOMS):
+                t = time.time()
+                ph = W.ellipsoid_phantom(shape, sp, seed)
+                log(f"phantom {v} {shape} built in {time.time() - t:.1f}s")
+                phantoms.append((ph, W.perturb_density(ph, seed + 100) if v == 1 else None))
+                plan.append((v, n_ang, nph))
+            adj_vol, adj_jobs_every = 1, 4
+        geom = W.Geometry(**W.PELVIS_DET)
+        srcw = W.pelvis_source(geom)
+        physw = W.physics_for(phantoms[0][0])
+        vols = [api.DeviceVolume(ph.density, ph.material, ph.spacing_mm) for ph, _ in phantoms]
+        dphys = api.DevicePhysics(physw.mu_mass, physw.grid.e0_kev, physw.grid.de_kev)
+        dsrc = api.DeviceSource(srcw.spec_e, srcw.spec_p, srcw.fluence)
+        jobs, adj_idx = [], []
+        jid = 0
+        for v, n_ang, nph in plan:
+            for a in range(n_ang):
+                phi = 2.0 * math.pi * a / n_ang
+                if v == adj_vol and a % adj_jobs_every == 0:
+                    adj_idx.append(len(jobs))
+                jobs.append(api.JobSpec(geom.replace(phi_rad=phi), nph, jid, volume=v))
+                jid += 1
+        batch = api.Batch(vols, dphys, [dsrc], jobs)
+        adj_batch = api.Batch(vols, dphys, [dsrc], [jobs[k] for k in adj_idx])
+        margins = [0.1 if v == adj_vol else 2.0**-20 for v in range(len(vols))]
+        # target tallies S* of the perturbed phantom (Philox seed 2), not timed
+        tgt_vol = api.DeviceVolume(phantoms[adj_vol][1].density, phantoms[adj_vol][1].material,
+                                   phantoms[adj_vol][1].spacing_mm)
+        tvols = list(vols)
+        tvols[adj_vol] = tgt_vol
+        tb = api.Batch(tvols, dphys, [dsrc], [jobs[k] for k in adj_idx])
+        t_tally = tb.project(seed=2, sumsq=False)
+        s_target = torch.stack([t[2] for t in tb.tally_views(t_tally)])
+        tallies = torch.zeros(batch.tally_elems, dtype=torch.float64, device="cuda")
+        grad = torch.zeros(vols[adj_vol].shape, dtype=torch.float64, device="cuda")
+        fwd = sum(j.n_photons for j in jobs)
+        adjh = sum(jobs[k].n_photons for k in adj_idx)
+        state = {}
+
+        def step():
+            maj = torch.stack([api.majorant(v, dphys, True, margins[k]) for k, v in enumerate(vols)])
+            batch.project(seed=1, sumsq=False, majorants=maj, out=tallies)
+            ms_f = api.last_kernel_ms()
+            views = batch.tally_views(tallies)
+            s_now = torch.stack([views[k][2] for k in adj_idx])
+            adj = torch.zeros(len(adj_idx), 2, geom.nv, geom.nu, dtype=torch.float64, device="cuda")
+            adj[:, 1] = s_now - s_target                       # d(0.5||S - S*||^2)/dS
+            adj_batch.backward(adj, maj, volume=adj_vol, seed=1, grad=grad)
+            ms_b = api.last_kernel_ms()
+            state["loss"] = 0.5 * float(((s_now - s_target) ** 2).sum())
+            return [ms_f, ms_b]
+
+        samples = []
+        for v, n_ang, nph in plan:
+            k = next(i for i, j in enumerate(jobs) if j.volume == v)
+            ph = phantoms[v][0]
+            samples.append((W.Problem(ph, physw, srcw, jobs[k].geom, nph), float(jobs[k].geom.phi_rad),
+                            jobs[k].job_id))
+        adjoint = dict(problem=W.Problem(phantoms[adj_vol][0], physw, srcw, jobs[adj_idx[0]].geom, 1),
+                       job_id=jobs[adj_idx[0]].job_id, margin=0.1)
+        cfg = dict(workload=name, angles=len(jobs), adjoint_angles=len(adj_idx),
+                   detector="256x192 @1.552mm", spectrum="120 kVp Kramers + 2.5 mm Al, bowtie 30 mm Al",
+                   phantoms=[f"{'x'.join(map(str, ph.shape[::-1]))} @{ph.spacing_mm[0]}mm" for ph, _ in phantoms],
+                   photons_per_angle=[p[2] for p in plan])
+        return dict(step=step, fwd=fwd, adj=adjh, samples=samples, adjoint=adjoint, config=cfg)
+    raise SystemExit(f"unknown workload {name}")
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the oracle as it stands, on a bounded sample
+# ---------------------------------------------------------------------------
+def cpu_baseline(wl, budget_s=20.0):
+    import oracle
+    oracle.build(force=False)
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    stats_acc = None
+    done, spent = 0, 0.0
+    per = max(1, len(wl["samples"]))
+    for prob, phi, jid in wl["samples"]:
+        p = oracle.Problem.from_workload(prob, phi_rad=phi)
+        n = 20000
+        while True:                                  # grow the sample until ~budget/per seconds
+            t = time.time()
+            r = oracle.mc_project(p, 1, n, job_id=jid, nthreads=nthreads)
+            dt = time.time() - t
+            if dt > budget_s / per / 4 or n >= 1 << 24:
+                break
+            n *= 4
+        done += n
+        spent += dt
+        st = r["stats"]
+        if stats_acc is None:
+            stats_acc = {k: (dict(v) if isinstance(v, dict) else v) for k, v in st.items()}
+        else:
+            for k, v in st.items():
+                if isinstance(v, dict):
+                    for kk, vv in v.items():
+                        stats_acc[k][kk] += vv
+                else:
+                    stats_acc[k] += v
+    fwd_rate = done / spent
+    out = dict(fwd_rate=fwd_rate, fwd_sample=done, stats=stats_acc, threads=nthreads)
+    if wl["adjoint"] is not None:
+        a = wl["adjoint"]
+        p = oracle.Problem.from_workload(a["problem"])
+        mb = oracle.majorant(p) * (1.0 + a["margin"])
+        adj = np.zeros((2, p.nv, p.nu))
+        adj[1] = 1.0
+        n = 20000
+        while True:
+            t = time.time()
+            oracle.mc_backward(p, 1, n, adj, mb, job_id=a["job_id"], nthreads=nthreads)
+            dt = time.time() - t
+            if dt > budget_s / 4 / 4 or n >= 1 << 24:
+                break
+            n *= 4
+        out.update(adj_rate=n / dt, adj_sample=n)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per transport launch")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path shards by job "
+              f"across GPUs with no exchange; see the design notes)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    from paper_1204_6367_amd import api, workloads as W
+    api.enable_timing(True)
+    t = time.time()
+    wl = build_workload(args.workload, api, W, torch)
+    torch.cuda.synchronize()
+    log(f"setup {time.time() - t:.1f}s; fwd histories/step {wl['fwd']:.3g}, adjoint {wl['adj']:.3g}")
+    for i in range(args.warmup):
+        wl["step"]()
+        log(f"warmup {i} done")
+    torch.cuda.synchronize()
+    kms = []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        kms.append(wl["step"]())
+        log(f"step {i} done: kernel ms {kms[-1]}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    hist_step = wl["fwd"] + wl["adj"]
+    value = hist_step * args.steps / (t1 - t0)
+    fwd_ms = float(np.mean([k[0] for k in kms]))
+    adj_ms = float(np.mean([k[1] for k in kms])) if wl["adj"] else None
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
+    roof = None
+    extra = {}
+    if cpu is not None:
+        w = work_per_history(cpu["stats"], cpu["fwd_sample"])
+        slots = w["slots"] * wl["fwd"]
+        nbytes = w["bytes"] * wl["fwd"]
+        alu_ach = slots / (fwd_ms * 1e-3) / 1e12
+        hbm_ach = nbytes / (fwd_ms * 1e-3) / 1e9
+        traffic = None
+        if args.traffic and os.path.exists(args.traffic):
+            traffic = json.load(open(args.traffic)).get(args.workload)
+        alu = dict(bound="alu", achieved=round(alu_ach, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Tops/s",
+                   frac=round(alu_ach / ALU_PEAK_TOPS, 4), traffic=traffic)
+        hbm = dict(bound="hbm", achieved=round(hbm_ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                   frac=round(hbm_ach / HBM_PEAK_GBS, 4), traffic=traffic)
+        roof = alu if alu["frac"] >= hbm["frac"] else hbm
+        extra["roofline_other"] = hbm if roof is alu else alu
+        extra["work_per_history"] = {k: round(v, 3) for k, v in w.items()}
+        cores = cpu["threads"]
+        if wl["adj"]:
+            cval = hist_step / (wl["fwd"] / cpu["fwd_rate"] + wl["adj"] / cpu["adj_rate"])
+            sample = (f"{cpu['fwd_sample']} forward histories over {len(wl['samples'])} jobs + "
+                      f"{cpu['adj_sample']} adjoint histories of the same workload")
+        else:
+            cval = cpu["fwd_rate"]
+            sample = f"{cpu['fwd_sample']} forward histories over {len(wl['samples'])} jobs of the same workload"
+        cpu = dict(value=round(cval, 1), unit="histories/s", cores=cores, kind="oracle", sample=sample)
+    line = dict(metric=METRIC, value=round(value, 1), unit="histories/s", n_gpus=1, steps=args.steps,
+                warmup=args.warmup, ms_per_step=round(ms_step, 2), higher_is_better=True, scaling="weak",
+                vs_baseline=None, dtype="f32", data="synthetic",
+                config=wl["config"], roofline=roof, cpu_baseline=cpu,
+                fwd_histories_per_s=round(wl["fwd"] / (fwd_ms * 1e-3), 1),
+                adj_histories_per_s=round(wl["adj"] / (adj_ms * 1e-3), 1) if adj_ms else None,
+                transport_kernel_ms=round(fwd_ms, 3), adjoint_kernel_ms=round(adj_ms, 3) if adj_ms else None,
+                **extra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -206,6 +206,16 @@ int gdrr_mc_trace(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr_s
                   float* e_final, int32_t* steps, int32_t* n_compton, int32_t* n_rayleigh,
                   void* workspace, size_t ws_bytes, void* stream);
 
+/*
+ * Timing hook (autotuner, benchmarks): while enabled, the transport kernel of
+ * every call is bracketed by HIP events recorded on the call's stream (also
+ * inside a batch's cached graph); gdrr_last_kernel_ms waits for the most
+ * recent bracket of the current device and returns its duration in ms.
+ * Concurrent calls on one device share the bracket.
+ */
+int gdrr_enable_timing(int enable);
+int gdrr_last_kernel_ms(float* ms);
+
 /* Default launch shape for this device (after gdrr_init). */
 int gdrr_default_tuning(gdrr_tuning* out);
 

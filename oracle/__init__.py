@@ -64,6 +64,7 @@ def lib():
         L.or_philox.argtypes = [vp, vp, vp]
         L.or_philox.restype = None
         L.or_majorant.argtypes = [P, i32, vp]
+        L.or_majorant_margin.argtypes = [P, i32, C.c_double, vp]
         L.or_mc_project.argtypes = [P, u64, u64, C.c_uint32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, i32]
         L.or_mc_backward.argtypes = [P, u64, u64, C.c_uint32, i32, i32, vp, vp, vp, i32]
         L.or_rho_integrals.argtypes = [P, i32, vp, vp, vp]
@@ -143,9 +144,9 @@ def philox(ctr, key) -> np.ndarray:
     return out
 
 
-def majorant(p: Problem, interp: bool = True) -> np.ndarray:
+def majorant(p: Problem, interp: bool = True, margin: float = 2.0**-20) -> np.ndarray:
     out = np.zeros(p.mu.shape[1] - 1, np.float64)
-    if lib().or_majorant(p.ref, int(interp), _ptr(out)):
+    if lib().or_majorant_margin(p.ref, int(interp), float(margin), _ptr(out)):
         raise ValueError("oracle majorant: invalid input")
     return out
 
@@ -155,7 +156,7 @@ def mc_project(p: Problem, seed: int, n: int, job_id: int = 0, interp: bool = Tr
                nthreads: int = 0):
     """Returns dict(tally=[4][nv][nu], stats=..., and per-history arrays if trace)."""
     tally = np.zeros((4, p.nv, p.nu), np.float64)
-    stats = np.zeros(12, np.float64)
+    stats = np.zeros(13, np.float64)
     tr = {}
     if trace:
         tr = dict(cls=np.zeros(n, np.int8), pixel=np.zeros(n, np.int32),
@@ -171,7 +172,7 @@ def mc_project(p: Problem, seed: int, n: int, job_id: int = 0, interp: bool = Tr
     out = dict(tally=tally, stats=dict(
         steps=stats[0], real=stats[1], compton=stats[2], rayleigh=stats[3],
         classes={CLASS_NAMES[k]: stats[4 + k] for k in range(6)},
-        e_src=stats[10], e_out=stats[11]))
+        e_src=stats[10], e_out=stats[11], tries=stats[12]))
     out.update(tr)
     return out
 

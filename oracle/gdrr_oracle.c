@@ -295,7 +295,17 @@ static double trilinear(const or_problem* p, const or_ctx* c, const double* x,
 /* the 3x3x3 neighbourhood of its containing voxel (whose material it takes),*/
 /* so rho_max(m) is the 3x3x3-neighbourhood maximum over voxels of m.        */
 /* ------------------------------------------------------------------------ */
+int or_majorant_margin(const or_problem* p, int32_t interp, double margin, double* out);
+
 int or_majorant(const or_problem* p, int32_t interp, double* out)
+{
+    return or_majorant_margin(p, interp, 1.0 / 1048576.0, out);
+}
+
+/* The same bound times (1 + margin) instead of (1 + 2^-20): any margin keeps
+ * delta tracking unbiased; the adjoint's null-collision terms need a
+ * margin well above zero for a finite variance. */
+int or_majorant_margin(const or_problem* p, int32_t interp, double margin, double* out)
 {
     double rmax[256];
     int present[256];
@@ -333,7 +343,7 @@ int or_majorant(const or_problem* p, int32_t interp, double* out)
             double t = rmax[m] * (t0 > t1 ? t0 : t1);
             if (t > best) best = t;
         }
-        out[j] = best * (1.0 + 1.0 / 1048576.0);
+        out[j] = best * (1.0 + margin);
     }
     return 0;
 }
@@ -354,7 +364,8 @@ static void rblock(const or_ctx* c, uint32_t i, uint32_t step, uint32_t sub, uin
  * proportional to (1/tau + tau)(1 - tau sin^2/(1+tau^2)).  It is sampled as a
  * mixture of the densities 1/tau (weight ln(1/tau0)) and tau (weight
  * (1-tau0^2)/2), then accepted with probability 1 - tau sin^2/(1+tau^2). */
-static void compton(const or_ctx* c, uint32_t i, uint32_t step, double E, double* tau_out, double* cos_out)
+static void compton(const or_ctx* c, uint32_t i, uint32_t step, double E, double* tau_out, double* cos_out,
+                    int* tries)
 {
     double k = E / OR_ME_C2_KEV;
     double tau0 = 1.0 / (1.0 + 2.0 * k);
@@ -370,6 +381,7 @@ static void compton(const or_ctx* c, uint32_t i, uint32_t step, double E, double
         double cost = 1.0 - (1.0 - tau) / (k * tau);
         double sin2 = (1.0 - cost) * (1.0 + cost);
         double g = 1.0 - tau * sin2 / (1.0 + tau * tau);
+        ++*tries;
         if (b2 <= g) { *tau_out = tau; *cos_out = cost; return; }
     }
     *tau_out = 1.0; *cos_out = 1.0;
@@ -382,7 +394,7 @@ static void compton(const or_ctx* c, uint32_t i, uint32_t step, double E, double
  * 1/lambda; below, x is drawn with density ~ x on [0, 1/lambda] and kept with
  * probability exp(-2x/x0).  Either way it is then kept with probability
  * (1 + cos^2)/2. */
-static double rayleigh(const or_ctx* c, uint32_t i, uint32_t step, double E, double x0)
+static double rayleigh(const or_ctx* c, uint32_t i, uint32_t step, double E, double x0, int* tries)
 {
     double xmax = E / OR_HC_KEV_A;
     for (uint32_t t = 0; t < OR_MAX_TRIES; ++t) {
@@ -390,6 +402,7 @@ static double rayleigh(const or_ctx* c, uint32_t i, uint32_t step, double E, dou
         rblock(c, i, step, 1 + t, x);
         double b0 = u24(x[0]), b1 = u24(x[1]), b2 = u24(x[2]);
         double xx;
+        ++*tries;
         if (xmax >= x0) {
             xx = -0.5 * x0 * log(b0 * b1);
             if (xx > xmax) continue;
@@ -438,7 +451,7 @@ typedef struct {
     int cls;
     int pixel;
     double e_src, e_final, recoil;
-    int steps, n_real, n_compton, n_rayleigh;
+    int steps, n_real, n_compton, n_rayleigh, tries;
 } or_outcome;
 
 /* Visitor for tentative collisions inside the phantom (for the adjoint). */
@@ -479,7 +492,7 @@ static void history(const or_problem* p, const or_ctx* c, uint32_t i, or_outcome
     double ju = u24(x[0]), jv = u24(x[1]);
     double E = (double)p->spec_e[ke];
     o->e_src = E; o->recoil = 0.0;
-    o->steps = 0; o->n_real = 0; o->n_compton = 0; o->n_rayleigh = 0;
+    o->steps = 0; o->n_real = 0; o->n_compton = 0; o->n_rayleigh = 0; o->tries = 0;
 
     /* aim point D on the detector, uniform within the sampled pixel */
     double uc = ((double)iu + ju - 0.5 * p->nu) * p->du;
@@ -522,11 +535,11 @@ static void history(const or_problem* p, const or_ctx* c, uint32_t i, or_outcome
             double sel = r2 * tot;
             double cost;
             if (sel < mu3[0]) {                               /* Rayleigh: E unchanged */
-                cost = rayleigh(c, i, step, E, p->x0_rayleigh);
+                cost = rayleigh(c, i, step, E, p->x0_rayleigh, &o->tries);
                 o->n_rayleigh++;
             } else if (sel < mu3[0] + mu3[1]) {               /* Compton */
                 double tau;
-                compton(c, i, step, E, &tau, &cost);
+                compton(c, i, step, E, &tau, &cost, &o->tries);
                 o->recoil += E - tau * E;
                 E = tau * E;
                 o->n_compton++;
@@ -627,9 +640,9 @@ static int counts_as_scatter(const or_outcome* o, int mode)
  * tally [4][nv][nu]: sum r(E), sum r(E)^2 over primary hits, then the same
  * over scatter hits, each divided by n (per source photon).  Optional
  * per-history outputs (any may be NULL): cls, pixel, e_final, steps,
- * n_compton, n_rayleigh.  `mode` selects the scatter tally (above).  stats[12] (optional): totals of steps, real events,
- * Compton, Rayleigh, histories per class [6], source energy, final energy of
- * non-absorbed photons + absorbed energy, recoil energy.
+ * n_compton, n_rayleigh.  `mode` selects the scatter tally (above).  stats[13] (optional): totals of steps, real events,
+ * Compton, Rayleigh, histories per class [6], source energy, final energy plus
+ * recoil energy, angular-sampler tries.
  * `mbar` NULL => the majorant is computed here.
  */
 int or_mc_project(const or_problem* p, uint64_t seed, uint64_t n, uint32_t job, int32_t interp,
@@ -683,6 +696,7 @@ int or_mc_project(const or_problem* p, uint64_t seed, uint64_t n, uint32_t job, 
                 ms[0] += o.steps; ms[1] += o.n_real; ms[2] += o.n_compton; ms[3] += o.n_rayleigh;
                 ms[4 + o.cls] += 1.0;
                 ms[10] += o.e_src; ms[11] += o.e_final + o.recoil;
+                ms[12] += o.tries;
             }
         }
     }
@@ -693,7 +707,7 @@ int or_mc_project(const or_problem* p, uint64_t seed, uint64_t n, uint32_t job, 
         tally[k] = s * inv;
     }
     if (stats)
-        for (int k = 0; k < 12; ++k) {
+        for (int k = 0; k < 13; ++k) {
             double s = 0.0;
             for (int t = 0; t < nt; ++t) s += st[t * 16 + k];
             stats[k] = s;
@@ -937,7 +951,8 @@ int or_sample_compton(double E, uint64_t seed, uint64_t n, double* cost, double*
     or_ctx c;
     memset(&c, 0, sizeof(c));
     c.key[0] = (uint32_t)seed; c.key[1] = (uint32_t)(seed >> 32);
-    for (uint64_t i = 0; i < n; ++i) compton(&c, (uint32_t)i, 1, E, &tau[i], &cost[i]);
+    int tries = 0;
+    for (uint64_t i = 0; i < n; ++i) compton(&c, (uint32_t)i, 1, E, &tau[i], &cost[i], &tries);
     return 0;
 }
 
@@ -946,7 +961,8 @@ int or_sample_rayleigh(double E, double x0, uint64_t seed, uint64_t n, double* c
     or_ctx c;
     memset(&c, 0, sizeof(c));
     c.key[0] = (uint32_t)seed; c.key[1] = (uint32_t)(seed >> 32);
-    for (uint64_t i = 0; i < n; ++i) cost[i] = rayleigh(&c, (uint32_t)i, 1, E, x0);
+    int tries = 0;
+    for (uint64_t i = 0; i < n; ++i) cost[i] = rayleigh(&c, (uint32_t)i, 1, E, x0, &tries);
     return 0;
 }
 

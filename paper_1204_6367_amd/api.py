@@ -165,6 +165,18 @@ def trace(vol: DeviceVolume, phys: DevicePhysics, src: DeviceSource, geom, n_pho
     return out
 
 
+def enable_timing(on: bool = True):
+    """Bracket every transport-kernel launch with HIP events on its stream."""
+    _abi.check(_abi.lib().gdrr_enable_timing(1 if on else 0))
+
+
+def last_kernel_ms() -> float:
+    """Duration of the most recent bracketed transport kernel (waits for it)."""
+    ms = C.c_float(0.0)
+    _abi.check(_abi.lib().gdrr_last_kernel_ms(C.byref(ms)))
+    return float(ms.value)
+
+
 class JobSpec:
     """One projection of a batch."""
 

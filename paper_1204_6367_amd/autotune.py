@@ -1,0 +1,77 @@
+"""Launch-shape autotuner for the persistent transport kernel.
+
+Times candidate (block, defer, chunk) shapes on a reduced copy of a batch
+(same phantoms, sources and angles, a fraction of the photons) with the
+library's kernel timing hook, and caches the fastest per workload class in a
+JSON file.  Tallies do not depend on the shape (integer tallies keyed by
+photon index), so tuning never changes results.
+"""
+from __future__ import annotations
+
+import json
+import os
+from typing import Dict, Iterable, List, Optional
+
+from . import api
+
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
+
+CANDIDATES: List[Dict[str, int]] = [
+    dict(block=b, defer=d, chunk=0, blocks_per_cu=0)
+    for b in (256, 512, 1024) for d in (1, 4, 8, 16, 32)
+]
+
+
+def workload_key(batch: "api.Batch") -> str:
+    vols = ";".join("x".join(map(str, v.shape)) for v in batch.vols)
+    dets = sorted({(j.geom.nu, j.geom.nv) for j in batch.jobs})
+    return f"vols={vols}|det={dets}|jobs={len(batch.jobs)}"
+
+
+def _reduced(batch: "api.Batch", fraction: float, min_photons: int) -> "api.Batch":
+    jobs = [api.JobSpec(j.geom, max(min_photons, int(j.n_photons * fraction)), j.job_id, j.volume, j.source)
+            for j in batch.jobs]
+    return api.Batch(batch.vols, batch.phys, batch.srcs, jobs)
+
+
+def autotune(batch: "api.Batch", candidates: Optional[Iterable[Dict[str, int]]] = None,
+             fraction: float = 0.05, min_photons: int = 100_000, repeats: int = 2,
+             cache: Optional[str] = DEFAULT_CACHE, force: bool = False, interp: bool = True) -> Dict[str, int]:
+    """Returns the fastest tuning dict for `batch` (cached by workload class)."""
+    key = workload_key(batch)
+    table = {}
+    if cache and os.path.exists(cache):
+        try:
+            table = json.load(open(cache))
+        except (OSError, ValueError):
+            table = {}
+    if not force and key in table:
+        return dict(table[key]["tuning"])
+    small = _reduced(batch, fraction, min_photons)
+    maj = small.majorants(interp)
+    api.enable_timing(True)
+    results = []
+    for cand in (candidates or CANDIDATES):
+        try:
+            small.project(seed=1, interp=interp, sumsq=False, majorants=maj, tune=cand)   # warm-up / graph build
+            ms = min(_timed(small, maj, cand, interp) for _ in range(repeats))
+        except api._abi.GdrrError:
+            continue
+        results.append((ms, cand))
+    if not results:
+        raise RuntimeError("no candidate launch shape ran")
+    results.sort(key=lambda r: r[0])
+    best_ms, best = results[0]
+    if cache:
+        table[key] = dict(tuning=best, ms=best_ms, photons=sum(j.n_photons for j in small.jobs),
+                          all=[dict(ms=m, **c) for m, c in results])
+        tmp = cache + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1)
+        os.replace(tmp, cache)
+    return dict(best)
+
+
+def _timed(batch, maj, cand, interp) -> float:
+    batch.project(seed=1, interp=interp, sumsq=False, majorants=maj, tune=cand)
+    return api.last_kernel_ms()

@@ -129,6 +129,29 @@ int check_geometry(const gdrr_geometry* g, const gdrr_volume* v, const gdrr_sour
 }
 
 // --------------------------------------------------------------------------
+// Timing hook: HIP events around the transport kernel, on the call's stream.
+// --------------------------------------------------------------------------
+struct TimeEvents {
+    hipEvent_t a = nullptr, b = nullptr;
+    bool recorded = false;
+};
+
+std::mutex g_time_mu;
+bool g_timing = false;
+TimeEvents g_tev[64];
+
+int timing_events(TimeEvents** out) {
+    int dev = 0;
+    GDRR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(GDRR_ENOTSUP, "device index out of range");
+    TimeEvents& t = g_tev[dev];
+    if (!t.a) GDRR_HIP(hipEventCreate(&t.a));
+    if (!t.b) GDRR_HIP(hipEventCreate(&t.b));
+    *out = &t;
+    return GDRR_OK;
+}
+
+// --------------------------------------------------------------------------
 // Launch list: every kernel takes one parameter struct by value, so a launch
 // is (function, grid, block, LDS bytes, argument bytes).  The list runs either
 // directly or as a HIP graph.
@@ -147,10 +170,17 @@ Launch make_launch(const void* f, dim3 g, dim3 b, size_t sh, const P& p) {
     return L;
 }
 
-int run_direct(std::vector<Launch>& ls, hipStream_t st) {
-    for (auto& L : ls) {
+// `timed` is the index of the launch to bracket with `ev` (-1: none).
+int run_direct(std::vector<Launch>& ls, hipStream_t st, int timed = -1, TimeEvents* ev = nullptr) {
+    for (size_t i = 0; i < ls.size(); ++i) {
+        Launch& L = ls[i];
         void* a[1] = {L.args.data()};
+        if ((int)i == timed) GDRR_HIP(hipEventRecord(ev->a, st));
         GDRR_HIP(hipLaunchKernel(L.func, L.grid, L.block, a, L.shmem, st));
+        if ((int)i == timed) {
+            GDRR_HIP(hipEventRecord(ev->b, st));
+            ev->recorded = true;
+        }
     }
     return GDRR_OK;
 }
@@ -178,10 +208,17 @@ std::mutex g_graph_mu;
 GraphEntry g_graphs[4];
 int g_graph_next = 0;
 
-int run_graph(std::vector<Launch>& ls, hipStream_t st) {
+int run_graph(std::vector<Launch>& ls, hipStream_t st, int timed = -1, TimeEvents* ev = nullptr) {
     int dev = 0;
     GDRR_HIP(hipGetDevice(&dev));
     std::vector<char> key = launch_key(ls);
+    {
+        const int t[1] = {timed};
+        key.insert(key.end(), (const char*)t, (const char*)t + sizeof(t));
+        const void* e[2] = {ev ? (const void*)ev->a : nullptr, ev ? (const void*)ev->b : nullptr};
+        key.insert(key.end(), (const char*)e, (const char*)e + sizeof(e));
+    }
+    if (ev && timed >= 0) ev->recorded = true;
     std::lock_guard<std::mutex> lk(g_graph_mu);
     for (auto& e : g_graphs)
         if (e.exec && e.device == dev && e.key == key) {
@@ -194,7 +231,13 @@ int run_graph(std::vector<Launch>& ls, hipStream_t st) {
     if (e.graph) { (void)hipGraphDestroy(e.graph); e.graph = nullptr; }
     GDRR_HIP(hipGraphCreate(&e.graph, 0));
     hipGraphNode_t prev = nullptr;
-    for (auto& L : ls) {
+    for (size_t i = 0; i < ls.size(); ++i) {
+        Launch& L = ls[i];
+        if ((int)i == timed) {
+            hipGraphNode_t en;
+            GDRR_HIP(hipGraphAddEventRecordNode(&en, e.graph, prev ? &prev : nullptr, prev ? 1 : 0, ev->a));
+            prev = en;
+        }
         hipKernelNodeParams kp{};
         void* a[1] = {L.args.data()};
         kp.func = const_cast<void*>(L.func);
@@ -206,6 +249,11 @@ int run_graph(std::vector<Launch>& ls, hipStream_t st) {
         hipGraphNode_t node;
         GDRR_HIP(hipGraphAddKernelNode(&node, e.graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
         prev = node;
+        if ((int)i == timed) {
+            hipGraphNode_t en;
+            GDRR_HIP(hipGraphAddEventRecordNode(&en, e.graph, &prev, 1, ev->b));
+            prev = en;
+        }
     }
     GDRR_HIP(hipGraphInstantiate(&e.exec, e.graph, nullptr, nullptr, 0));
     e.device = dev;
@@ -517,7 +565,11 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     kp.grad = B.grad;
     const void* mf = B.mode == kModeForward ? mc_func<kModeForward>()
                    : B.mode == kModeTrace ? mc_func<kModeTrace>() : mc_func<kModeBackward>();
-    if (chunks > 0) ls.push_back(make_launch(mf, dim3(grid), dim3(block), lds, kp));
+    int timed = -1;
+    if (chunks > 0) {
+        timed = (int)ls.size();
+        ls.push_back(make_launch(mf, dim3(grid), dim3(block), lds, kp));
+    }
     // ---- finalize ----
     if (B.mode == kModeForward) {
         int maxpix = 1;
@@ -526,7 +578,13 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
         ls.push_back(make_launch((const void*)&finalize_kernel,
                                  dim3((unsigned)std::min(1024, (4 * maxpix + 255) / 256), (unsigned)B.n_jobs), dim3(256), 0, fp));
     }
-    return B.use_graph ? run_graph(ls, st) : run_direct(ls, st);
+    TimeEvents* ev = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_time_mu);
+        if (g_timing && timed >= 0 && (rc = timing_events(&ev))) return rc;
+    }
+    if (!ev) timed = -1;
+    return B.use_graph ? run_graph(ls, st, timed, ev) : run_direct(ls, st, timed, ev);
 }
 
 size_t batch_bytes(const gdrr_physics* phys, const gdrr_source* srcs, int n_srcs, const gdrr_job* jobs, int n_jobs,
@@ -557,6 +615,23 @@ const char* gdrr_version(void) { return "gdrr-mi355x 0.1"; }
 int gdrr_init(void) {
     DevInfo d;
     return device_info(d);
+}
+
+int gdrr_enable_timing(int enable) {
+    std::lock_guard<std::mutex> lk(g_time_mu);
+    g_timing = enable != 0;
+    return GDRR_OK;
+}
+
+int gdrr_last_kernel_ms(float* ms) {
+    if (!ms) return fail(GDRR_EINVAL, "ms is NULL");
+    int dev = 0;
+    GDRR_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_time_mu);
+    if (dev < 0 || dev >= 64 || !g_tev[dev].recorded) return fail(GDRR_EINVAL, "no timed launch on this device");
+    GDRR_HIP(hipEventSynchronize(g_tev[dev].b));
+    GDRR_HIP(hipEventElapsedTime(ms, g_tev[dev].a, g_tev[dev].b));
+    return GDRR_OK;
 }
 
 int gdrr_default_tuning(gdrr_tuning* out) {

@@ -50,13 +50,14 @@ struct KParams {
     double* grad;
 };
 
+// LDS holds what every free flight reads: the total attenuation per
+// (material, grid point) and the majorants; interaction-type splits are read
+// from the global table at the (rarer) real collisions.
 __host__ __device__ inline size_t lds_bytes(int n_mat, int n_e, int n_vols, bool resp) {
-    return (size_t)n_mat * n_e * 16 + (size_t)n_mat * n_e * 8 + (size_t)n_vols * (n_e - 1) * 8 +
-           (resp ? (size_t)n_e * 8 : 0);
+    return (size_t)n_mat * n_e * 8 + (size_t)n_vols * (n_e - 1) * 8 + (resp ? (size_t)n_e * 8 : 0);
 }
 
 struct Tables {
-    const float4* rc;     // [m][j] (R_j, R_j+1 - R_j, C_j, C_j+1 - C_j)
     const float2* tot;    // [m][j] (tot_j, tot_j+1 - tot_j)
     const float2* maj;    // [v][j] (mbar, mean free path per unit of -ln u, mm)
     const float2* resp;   // [j] (r_j, r_j+1 - r_j)
@@ -274,19 +275,16 @@ __device__ __forceinline__ void visit(const KParams& P, const DVolume& V, bool i
 
 template <int MODE>
 __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
-    extern __shared__ float4 lds[];
+    extern __shared__ float2 lds[];
     // ---- stage the per-launch tables in LDS ----
-    float4* s_rc = lds;
-    float2* s_tot = reinterpret_cast<float2*>(s_rc + P.n_mat * P.n_e);
+    float2* s_tot = lds;
     float2* s_maj = s_tot + P.n_mat * P.n_e;
     float2* s_resp = s_maj + P.n_vols * (P.n_e - 1);
     for (int i = threadIdx.x; i < P.n_mat * P.n_e; i += blockDim.x) {
         const int j = i % P.n_e;
         const float* a = P.mu_mass + (size_t)i * 3;
         const float* b = j + 1 < P.n_e ? a + 3 : a;
-        const float r0 = a[0], c0 = a[1], p0 = a[2], r1 = b[0], c1 = b[1], p1 = b[2];
-        s_rc[i] = make_float4(r0, r1 - r0, c0, c1 - c0);
-        const float t0 = r0 + c0 + p0, t1 = r1 + c1 + p1;
+        const float t0 = a[0] + a[1] + a[2], t1 = b[0] + b[1] + b[2];
         s_tot[i] = make_float2(t0, t1 - t0);
     }
     for (int i = threadIdx.x; i < P.n_vols * (P.n_e - 1); i += blockDim.x) {
@@ -299,7 +297,7 @@ __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
             s_resp[i] = make_float2(r0, r1 - r0);
         }
     __syncthreads();
-    const Tables T{s_rc, s_tot, s_maj, s_resp};
+    const Tables T{s_tot, s_maj, s_resp};
     const bool interp = (P.flags & 1u) != 0;
     const int lane = __lane_id();
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -417,10 +415,10 @@ __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
         if (n_coll2 > 0 && (n_coll2 >= P.defer || n_fly2 == 0 || w_done || w_hold)) {
             if (ph.st == kColl) {
                 const int m = ph.pm;
-                const float4 rc = T.rc[m * P.n_e + ph.ec.j];
+                const float* a = P.mu_mass + ((size_t)m * P.n_e + ph.ec.j) * 3;   // j <= n_e - 2
+                const float R = a[0] + ph.ec.f * (a[3] - a[0]);
+                const float C = a[1] + ph.ec.f * (a[4] - a[1]);
                 const float2 tt = T.tot[m * P.n_e + ph.ec.j];
-                const float R = rc.x + ph.ec.f * rc.y;
-                const float C = rc.z + ph.ec.f * rc.w;
                 const float sel = ph.pu2 * (tt.x + ph.ec.f * tt.y);
                 float ct;
                 bool alive = true;

@@ -1,0 +1,117 @@
+"""GPU adjoint: path-replay gradient against the CPU oracle's adjoint on the
+same Philox streams (relative L2 <= 2 %), against central finite differences
+with common random numbers, and the autograd Function."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1204_6367_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1204_6367_amd import api
+    return api
+
+
+def small_problem(seed=21, n=(10, 10, 10), d=5.0):
+    rng = np.random.default_rng(seed)
+    mats = ["air", "soft_tissue", "bone"]
+    m = rng.integers(0, 3, n).astype(np.uint8)
+    base = np.array([0.0012, 1.03, 1.85])
+    dens = (base[m] * rng.uniform(0.7, 1.3, n)).astype(np.float32)
+    ph = W.Phantom(dens, m, (d, d, d), mats)
+    geom = W.Geometry(phi_rad=0.3, nu=16, nv=12, du_mm=8.0, dv_mm=8.0)
+    spec = (np.array([40.0, 60.0, 80.0], np.float32), np.array([0.3, 0.4, 0.3], np.float32))
+    src = W.Source(*spec, W.fluence_map(geom))
+    return W.Problem(ph, W.physics_for(ph), src, geom, 200_000)
+
+
+@pytest.mark.parametrize("interp", [True, False])
+def test_adjoint_matches_oracle(gpu, interp):
+    import torch
+    import oracle
+    prob = small_problem()
+    vol, phys, src = gpu.upload(prob)
+    g = prob.geom
+    rng = np.random.default_rng(5)
+    adj = rng.normal(size=(2, g.nv, g.nu))
+    b = gpu.Batch([vol], phys, [src], [gpu.JobSpec(g, prob.n_photons, 0)])
+    maj = gpu.majorant(vol, phys, interp, margin=0.2)[None]
+    log("gpu backward", interp)
+    gg = b.backward(torch.tensor(adj[None], device="cuda"), maj, seed=1, interp=interp).cpu().numpy()
+    p = oracle.Problem.from_workload(prob)
+    mo = oracle.majorant(p, interp, margin=0.2)
+    go = oracle.mc_backward(p, 1, prob.n_photons, adj, mo, interp=interp)
+    rel = np.linalg.norm(gg - go) / np.linalg.norm(go)
+    log("adjoint rel L2", rel)
+    assert rel <= 0.02
+
+
+def test_adjoint_of_linear_loss_matches_crn_finite_differences(gpu):
+    """L = sum_p a_p S_p: the adjoint and CRN central differences estimate the
+    same derivative; compared over replicas (seeds) on 16 voxels."""
+    import torch
+    prob = small_problem(seed=23)
+    vol, phys, src = gpu.upload(prob)
+    g = prob.geom
+    a = torch.tensor(np.random.default_rng(6).uniform(0.5, 1.5, (g.nv, g.nu)), device="cuda")
+    adj = torch.zeros(1, 2, g.nv, g.nu, dtype=torch.float64, device="cuda")
+    adj[0, 1] = a
+    n = 2_000_000
+    b = gpu.Batch([vol], phys, [src], [gpu.JobSpec(g, n, 0)])
+    rng = np.random.default_rng(7)
+    flat = np.flatnonzero(prob.phantom.material.ravel() > 0)
+    voxels = rng.choice(flat, 16, replace=False)
+    base = vol.density.clone()
+    maj = gpu.majorant(vol, phys, True, margin=0.3)[None]        # held fixed for all runs (valid for +h)
+    diffs = []
+    for seed in range(1, 9):
+        grad = b.backward(adj, maj, seed=seed).cpu().numpy().ravel()[voxels]
+        fd = []
+        for v in voxels:
+            h = 0.05 * float(base.view(-1)[v])
+            dp = base.clone(); dp.view(-1)[v] += h
+            dm = base.clone(); dm.view(-1)[v] -= h
+            tp = b.project(seed=seed, sumsq=False, majorants=maj, densities=[dp])
+            tm = b.project(seed=seed, sumsq=False, majorants=maj, densities=[dm])
+            sp = b.tally_views(tp)[0][2]
+            sm = b.tally_views(tm)[0][2]
+            fd.append(float(((sp - sm) * a).sum()) / (2 * h))
+        diffs.append(np.array(fd) - grad)
+        log("replica", seed)
+    d = np.array(diffs)
+    z = d.mean(0) / (d.std(0, ddof=1) / math.sqrt(len(d)) + 1e-30)
+    log("fd-adjoint z", np.round(z, 2))
+    assert np.abs(z).max() < 4.0
+
+
+def test_autograd_function(gpu):
+    import torch
+    prob = small_problem(seed=24)
+    vol, phys, src = gpu.upload(prob)
+    g = prob.geom
+    jobs = [gpu.JobSpec(g.replace(phi_rad=p), 100_000, k) for k, p in enumerate([0.0, 1.0])]
+    b = gpu.Batch([vol], phys, [src], jobs)
+    rho = vol.density.clone().requires_grad_(True)
+    ps = gpu.GdrrProject.apply(rho, b, 3, True, 0.2)
+    assert ps.shape == (2, 2, g.nv, g.nu)
+    w = torch.rand_like(ps)
+    (ps * w).sum().backward()
+    maj = b.majorants(True, 0.2, [rho.detach()])
+    direct = b.backward(w, maj, seed=3, densities=[rho.detach()])
+    assert torch.allclose(rho.grad.double(), direct, rtol=1e-5, atol=1e-12)
+    t = b.project(seed=3, sumsq=False, majorants=maj)
+    views = b.tally_views(t)
+    assert torch.equal(ps[1, 1], views[1][2])

@@ -171,3 +171,52 @@ def test_majorant_matches_oracle(gpu):
         mo = oracle.majorant(p, interp)
         assert np.all(mg >= mo)
         assert np.all(mg <= mo * (1 + 2**-23) + 1e-30)
+
+
+def test_launch_shape_does_not_change_tallies(gpu):
+    """Integer tallies keyed by photon index: any block / defer / chunk gives the same bits."""
+    import torch
+    prob = W.sphere_problem(300_000)
+    vol, phys, src = gpu.upload(prob)
+    jobs = [gpu.JobSpec(prob.geom.replace(phi_rad=a), 150_000, k) for k, a in enumerate([0.2, 2.2])]
+    b = gpu.Batch([vol], phys, [src], jobs)
+    ref = b.project(seed=4)
+    for t in (dict(block=64, defer=1, chunk=64), dict(block=512, defer=32, chunk=1024),
+              dict(block=1024, defer=64, chunk=128, blocks_per_cu=1)):
+        assert torch.equal(b.project(seed=4, tune=t), ref), t
+
+
+def test_flags_response_sumsq_accumulate_first_order(gpu):
+    import oracle
+    import torch
+    prob = W.sphere_problem(400_000)
+    resp = (0.8 * prob.physics.grid.energies() * (1 - np.exp(-prob.physics.grid.energies() / 30.0))).astype(np.float32)
+    prob.physics.response = resp
+    vol, phys, src = gpu.upload(prob)
+    p = oracle_problem(prob)
+    n = prob.n_photons
+    for flag, mode in ((0, 0), (gpu.SCATTER_FIRST, 1), (gpu.SCATTER_FIRST_COMPTON, 2)):
+        tg = gpu.project(vol, phys, src, prob.geom, n, seed=9, flags=flag).cpu().numpy()
+        to = oracle.mc_project(p, 9, n, mode=mode)["tally"]
+        r = tally_parity(tg, to, n, pool=8)
+        log("flags", flag, r)
+        assert r["P"]["rel_l2"] <= 0.01 and r["S"]["rel_l2"] <= 0.02
+        assert abs(tg[2].sum() - to[2].sum()) <= 0.01 * to[2].sum()
+    # without TALLY_SUMSQ the square planes are left alone; ACCUMULATE adds
+    out = torch.full((4, prob.geom.nv, prob.geom.nu), 7.0, dtype=torch.float64, device="cuda")
+    gpu.project(vol, phys, src, prob.geom, n, seed=9, sumsq=False, out=out)
+    assert torch.all(out[1] == 7.0) and torch.all(out[3] == 7.0)
+    once = out[0].clone()
+    gpu.project(vol, phys, src, prob.geom, n, seed=9, sumsq=False, out=out, flags=gpu.ACCUMULATE)
+    assert torch.allclose(out[0], 2 * once, rtol=1e-15, atol=0)
+
+
+def test_interpolation_off_matches_oracle(gpu):
+    import oracle
+    prob = W.pelvis_problem(300_000, shape=(48, 64, 64), spacing=(7.8, 7.8, 8.3))
+    vol, phys, src = gpu.upload(prob)
+    g = gpu.trace(vol, phys, src, prob.geom, prob.n_photons, seed=2, interp=False)
+    o = oracle.mc_project(oracle_problem(prob), 2, prob.n_photons, interp=False, trace=True)
+    frac, _ = compare_histories(g, o)
+    log("interp off identical", frac)
+    assert frac >= 0.995
