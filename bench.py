@@ -42,8 +42,9 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # 32-bit VALU lane-ops/s: 256 CUs x
 # 32-bit VALU issue slots (quarter-rate integer multiplies and transcendentals
 # count 4) and bytes the algorithm must gather.
 SLOTS_PHILOX = 10 * (4 * 4 + 2)          # 2 mul_hi + 2 mul_lo (quarter rate) + 2 xor3 per round
-SLOTS_FLIGHT_IN = SLOTS_PHILOX + 6 + 7 + 4 + 64 + 7     # uniforms, -ln u, move, trilinear, lookup+accept
-SLOTS_FLIGHT_OUT = SLOTS_PHILOX + 6 + 7 + 30           # the escaping flight: detector intersection
+# one Philox block serves two free flights (two words each)
+SLOTS_FLIGHT_IN = SLOTS_PHILOX // 2 + 3 + 7 + 4 + 64 + 7   # uniforms, -ln u, move, trilinear, lookup+ladder
+SLOTS_FLIGHT_OUT = SLOTS_PHILOX // 2 + 3 + 7 + 30         # the escaping flight: detector intersection
 SLOTS_TRY = SLOTS_PHILOX + 9 + 30                      # one angular-sampler try
 SLOTS_COLLISION = 6 + 55 + 40 + 10                     # type select, rotation, box exit, energy cache
 SLOTS_SOURCE = 2 * SLOTS_PHILOX + 40 + 34 + 45         # two blocks, CDFs (fp64), aim point, box entry

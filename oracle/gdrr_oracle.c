@@ -350,8 +350,12 @@ int or_majorant_margin(const or_problem* p, int32_t interp, double margin, doubl
 
 /* ------------------------------------------------------------------------ */
 /* Random-number layout: block (photon i, job, step, sub) under key = seed.  */
-/* step 0 = source; step k >= 1 = k-th free flight; sub 0 = the flight's     */
-/* own four uniforms, sub 1 + t = the t-th try of an angular sampler.        */
+/* step 0 = source (sub 0: energy and pixel, sub 1: position in the pixel).  */
+/* Free flight k >= 1 takes two words of block (i, job, (k+1)/2, 0): words   */
+/* 0 and 1 for odd k, words 2 and 3 for even k -- the first for the flight   */
+/* length, the second for the collision "ladder".  The t-th try of the       */
+/* angular sampler at flight k uses block (i, job, k, 1 + t); its word 3 is   */
+/* the azimuth if that try is accepted.                                      */
 /* ------------------------------------------------------------------------ */
 static void rblock(const or_ctx* c, uint32_t i, uint32_t step, uint32_t sub, uint32_t x[4])
 {
@@ -365,7 +369,7 @@ static void rblock(const or_ctx* c, uint32_t i, uint32_t step, uint32_t sub, uin
  * mixture of the densities 1/tau (weight ln(1/tau0)) and tau (weight
  * (1-tau0^2)/2), then accepted with probability 1 - tau sin^2/(1+tau^2). */
 static void compton(const or_ctx* c, uint32_t i, uint32_t step, double E, double* tau_out, double* cos_out,
-                    int* tries)
+                    double* az_out, int* tries)
 {
     double k = E / OR_ME_C2_KEV;
     double tau0 = 1.0 / (1.0 + 2.0 * k);
@@ -382,6 +386,7 @@ static void compton(const or_ctx* c, uint32_t i, uint32_t step, double E, double
         double sin2 = (1.0 - cost) * (1.0 + cost);
         double g = 1.0 - tau * sin2 / (1.0 + tau * tau);
         ++*tries;
+        *az_out = u24(x[3]);
         if (b2 <= g) { *tau_out = tau; *cos_out = cost; return; }
     }
     *tau_out = 1.0; *cos_out = 1.0;
@@ -394,7 +399,8 @@ static void compton(const or_ctx* c, uint32_t i, uint32_t step, double E, double
  * 1/lambda; below, x is drawn with density ~ x on [0, 1/lambda] and kept with
  * probability exp(-2x/x0).  Either way it is then kept with probability
  * (1 + cos^2)/2. */
-static double rayleigh(const or_ctx* c, uint32_t i, uint32_t step, double E, double x0, int* tries)
+static double rayleigh(const or_ctx* c, uint32_t i, uint32_t step, double E, double x0, double* az_out,
+                       int* tries)
 {
     double xmax = E / OR_HC_KEV_A;
     for (uint32_t t = 0; t < OR_MAX_TRIES; ++t) {
@@ -403,6 +409,7 @@ static double rayleigh(const or_ctx* c, uint32_t i, uint32_t step, double E, dou
         double b0 = u24(x[0]), b1 = u24(x[1]), b2 = u24(x[2]);
         double xx;
         ++*tries;
+        *az_out = u24(x[3]);
         if (xmax >= x0) {
             xx = -0.5 * x0 * log(b0 * b1);
             if (xx > xmax) continue;
@@ -507,11 +514,12 @@ static void history(const or_problem* p, const or_ctx* c, uint32_t i, or_outcome
     if (box_entry(c, pos, dir, &tin, &tout)) {
         for (int a = 0; a < 3; ++a) pos[a] += tin * dir[a];
         double trem = tout - tin;
+        uint32_t fb[4] = {0, 0, 0, 0};
         for (uint32_t step = 1;; ++step) {
             if (step > OR_MAX_STEPS) { o->cls = OR_LOST; o->pixel = -1; o->e_final = E; return; }
             o->steps = (int)step;
-            rblock(c, i, step, 0, x);
-            double r0 = u24(x[0]), r1 = u24(x[1]), r2 = u24(x[2]), r3 = u24(x[3]);
+            if (step & 1u) rblock(c, i, (step + 1) / 2, 0, fb);
+            double r0 = u24(fb[(step & 1u) ? 0 : 2]), r1 = u24(fb[(step & 1u) ? 1 : 3]);
             double f;
             int j = e_interval(p, E, &f);
             double mbar = c->mbar[j];
@@ -528,18 +536,22 @@ static void history(const or_problem* p, const or_ctx* c, uint32_t i, or_outcome
             xs_at(p, m, E, mu3);
             double tot = mu3[0] + mu3[1] + mu3[2];
             double mu = rho * tot;
-            int real = r1 * mbar < mu;
+            /* One uniform on [0, mbar) decides the event: Rayleigh below rho
+             * mu_R, Compton below rho (mu_R + mu_C), photoelectric below mu,
+             * null collision above -- probabilities rho mu_k / mbar and
+             * 1 - mu / mbar, as delta tracking requires. */
+            double ladder = r1 * mbar;
+            int real = ladder < mu;
             if (vis) visit(p, c, vis, pos, real, rho, tot, mbar);
             if (!real) continue;                              /* null collision */
             o->n_real++;
-            double sel = r2 * tot;
-            double cost;
-            if (sel < mu3[0]) {                               /* Rayleigh: E unchanged */
-                cost = rayleigh(c, i, step, E, p->x0_rayleigh, &o->tries);
+            double cost, az = 0.0;
+            if (ladder < rho * mu3[0]) {                      /* Rayleigh: E unchanged */
+                cost = rayleigh(c, i, step, E, p->x0_rayleigh, &az, &o->tries);
                 o->n_rayleigh++;
-            } else if (sel < mu3[0] + mu3[1]) {               /* Compton */
+            } else if (ladder < rho * (mu3[0] + mu3[1])) {    /* Compton */
                 double tau;
-                compton(c, i, step, E, &tau, &cost, &o->tries);
+                compton(c, i, step, E, &tau, &cost, &az, &o->tries);
                 o->recoil += E - tau * E;
                 E = tau * E;
                 o->n_compton++;
@@ -548,7 +560,7 @@ static void history(const or_problem* p, const or_ctx* c, uint32_t i, or_outcome
                 return;
             }
             double nd2[3];
-            or_rotate(dir, cost, 2.0 * M_PI * r3, nd2);
+            or_rotate(dir, cost, 2.0 * M_PI * az, nd2);
             dir[0] = nd2[0]; dir[1] = nd2[1]; dir[2] = nd2[2];
             scattered = 1;
             if (E < p->e_cut) { o->cls = OR_CUT; o->pixel = -1; o->e_final = E; return; }
@@ -952,7 +964,8 @@ int or_sample_compton(double E, uint64_t seed, uint64_t n, double* cost, double*
     memset(&c, 0, sizeof(c));
     c.key[0] = (uint32_t)seed; c.key[1] = (uint32_t)(seed >> 32);
     int tries = 0;
-    for (uint64_t i = 0; i < n; ++i) compton(&c, (uint32_t)i, 1, E, &tau[i], &cost[i], &tries);
+    double az;
+    for (uint64_t i = 0; i < n; ++i) compton(&c, (uint32_t)i, 1, E, &tau[i], &cost[i], &az, &tries);
     return 0;
 }
 
@@ -962,7 +975,8 @@ int or_sample_rayleigh(double E, double x0, uint64_t seed, uint64_t n, double* c
     memset(&c, 0, sizeof(c));
     c.key[0] = (uint32_t)seed; c.key[1] = (uint32_t)(seed >> 32);
     int tries = 0;
-    for (uint64_t i = 0; i < n; ++i) cost[i] = rayleigh(&c, (uint32_t)i, 1, E, x0, &tries);
+    double az;
+    for (uint64_t i = 0; i < n; ++i) cost[i] = rayleigh(&c, (uint32_t)i, 1, E, x0, &az, &tries);
     return 0;
 }
 

@@ -505,10 +505,10 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
         const gdrr_source& S = B.srcs[s];
         const SrcArea& A = L.src[s];
         SrcPrepParams sp{S.spec_prob, S.n_spec, A.spec_cdf, A.spec_guide, (int)A.spec_k, (unsigned int*)(L.counter + 1)};
-        ls.push_back(make_launch((const void*)&cdf_kernel, dim3(1), dim3(64), 0, sp));
+        ls.push_back(make_launch((const void*)&cdf_kernel, dim3(1), dim3(1024), 0, sp));
         ls.push_back(make_launch((const void*)&guide_kernel, dim3((A.spec_k + 255) / 256), dim3(256), 0, sp));
         SrcPrepParams fp{S.fluence, S.fu * S.fv, A.flu_cdf, A.flu_guide, (int)A.flu_k, (unsigned int*)(L.counter + 1)};
-        ls.push_back(make_launch((const void*)&cdf_kernel, dim3(1), dim3(64), 0, fp));
+        ls.push_back(make_launch((const void*)&cdf_kernel, dim3(1), dim3(1024), 0, fp));
         ls.push_back(make_launch((const void*)&guide_kernel, dim3((A.flu_k + 255) / 256), dim3(256), 0, fp));
     }
     // ---- the persistent transport kernel ----

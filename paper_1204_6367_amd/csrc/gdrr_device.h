@@ -55,6 +55,18 @@ __device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
 }
 
 __device__ __forceinline__ float fast_log(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+// -expm1(e) = 1 - exp(e) for e in [-0.5, 0] by its Taylor series to e^7
+// (relative error below 1e-7 there), without the cancellation of 1 - exp(e).
+__device__ __forceinline__ float one_minus_exp(float e) {
+    float t = 1.0f + e * (1.0f / 7.0f);
+    t = 1.0f + e * (1.0f / 6.0f) * t;
+    t = 1.0f + e * (1.0f / 5.0f) * t;
+    t = 1.0f + e * (1.0f / 4.0f) * t;
+    t = 1.0f + e * (1.0f / 3.0f) * t;
+    t = 1.0f + e * 0.5f * t;
+    return -e * t;
+}
 __device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
 // sin / cos of 2 pi r (the hardware unit takes revolutions)
 __device__ __forceinline__ float sin_rev(float r) { return __builtin_amdgcn_sinf(r); }
@@ -137,9 +149,9 @@ __device__ __forceinline__ void rotate(float& dx, float& dy, float& dz, float ct
 __device__ __forceinline__ float box_exit(const DVolume& V, float px, float py, float pz,
                                           float dx, float dy, float dz) {
     float t = INFINITY;
-    if (dx > 0.0f) t = fminf(t, (V.hix - px) / dx); else if (dx < 0.0f) t = fminf(t, (V.lox - px) / dx);
-    if (dy > 0.0f) t = fminf(t, (V.hiy - py) / dy); else if (dy < 0.0f) t = fminf(t, (V.loy - py) / dy);
-    if (dz > 0.0f) t = fminf(t, (V.hiz - pz) / dz); else if (dz < 0.0f) t = fminf(t, (V.loz - pz) / dz);
+    if (dx != 0.0f) t = fminf(t, ((dx > 0.0f ? V.hix : V.lox) - px) * fast_rcp(dx));
+    if (dy != 0.0f) t = fminf(t, ((dy > 0.0f ? V.hiy : V.loy) - py) * fast_rcp(dy));
+    if (dz != 0.0f) t = fminf(t, ((dz > 0.0f ? V.hiz : V.loz) - pz) * fast_rcp(dz));
     return fmaxf(t, 0.0f);
 }
 
@@ -155,7 +167,7 @@ __device__ __forceinline__ bool box_entry(const DVolume& V, float sx, float sy, 
             if (s[a] < lo[a] || s[a] > hi[a]) return false;
             continue;
         }
-        const float inv = 1.0f / d[a];
+        const float inv = fast_rcp(d[a]);
         float ta = (lo[a] - s[a]) * inv, tb = (hi[a] - s[a]) * inv;
         if (ta > tb) { const float t = ta; ta = tb; tb = t; }
         t0 = fmaxf(t0, ta);
@@ -169,12 +181,14 @@ __device__ __forceinline__ bool box_entry(const DVolume& V, float sx, float sy, 
 // Compton scattering, free-electron Klein-Nishina: tau = E'/E drawn from the
 // mixture of densities ~1/tau (weight ln(1+2k)) and ~tau (weight (1-tau0^2)/2)
 // on [tau0, 1], kept with probability 1 - tau sin^2/(1+tau^2).  One Philox
-// block (photon, job, step, 1 + try) per try.  Returns cos(theta); E *= tau.
+// block (photon, job, step, 1 + try) per try; the accepted try's fourth word
+// is the azimuth (in revolutions).  Returns cos(theta); E *= tau.
 __device__ __forceinline__ float compton(uint32_t pid, uint32_t job, uint32_t step, uint32_t k0, uint32_t k1,
-                                         float& E) {
+                                         float& E, float& az) {
     const float k = E * (1.0f / kMeC2);
-    const float tau0 = 1.0f / (1.0f + 2.0f * k);
+    const float tau0 = fast_rcp(1.0f + 2.0f * k);
     const float a1 = fast_log(1.0f + 2.0f * k);
+    const float ik = fast_rcp(k);
     const float omt02 = 1.0f - tau0 * tau0;
     const float a2 = 0.5f * omt02;
     for (int t = 0; t < kMaxTries; ++t) {
@@ -182,18 +196,20 @@ __device__ __forceinline__ float compton(uint32_t pid, uint32_t job, uint32_t st
         const float b0 = u24(b.x), b1 = u24(b.y), b2 = u24(b.z);
         float tau, omt;   // tau and 1 - tau, the latter without cancellation
         if (b0 * (a1 + a2) < a1) {
-            const float e = -a1 * b1;
-            tau = fast_exp(e);
-            omt = -expm1f(e);
+            const float e = -a1 * b1;               // in [-ln 3, 0]; |e| <= 0.47 for E <= 150 keV
+            omt = one_minus_exp(e);
+            tau = 1.0f - omt;
         } else {
             const float t2 = tau0 * tau0 + omt02 * b1;
             tau = sqrtf(t2);
-            omt = omt02 * (1.0f - b1) / (1.0f + tau);
+            omt = omt02 * (1.0f - b1) * fast_rcp(1.0f + tau);
         }
-        const float omc = omt / (k * tau);          // 1 - cos(theta)
+        const float itau = fast_rcp(tau);
+        const float omc = omt * ik * itau;          // 1 - cos(theta)
         const float ct = 1.0f - omc;
         const float sin2 = omc * (2.0f - omc);
-        const float g = 1.0f - tau * sin2 / (1.0f + tau * tau);
+        const float g = 1.0f - tau * sin2 * fast_rcp(1.0f + tau * tau);
+        az = u24(b.w);
         if (b2 <= g) {
             E *= tau;
             return ct;
@@ -207,19 +223,21 @@ __device__ __forceinline__ float compton(uint32_t pid, uint32_t job, uint32_t st
 // x0, else from the density ~x on [0, 1/lambda] kept with probability
 // exp(-2x/x0); then kept with probability (1 + cos^2)/2.
 __device__ __forceinline__ float rayleigh(uint32_t pid, uint32_t job, uint32_t step, uint32_t k0, uint32_t k1,
-                                          float E, float x0) {
+                                          float E, float x0, float& az) {
     const float xmax = E * (1.0f / kHc);
-    const float ixmax = kHc / E;
+    const float ixmax = kHc * fast_rcp(E);
+    const float m2ix0 = -2.0f * fast_rcp(x0);
     for (int t = 0; t < kMaxTries; ++t) {
         const Block b = philox(pid, job, step, 1u + (uint32_t)t, k0, k1);
         const float b0 = u24(b.x), b1 = u24(b.y), b2 = u24(b.z);
+        az = u24(b.w);
         float xx;
         if (xmax >= x0) {
             xx = -0.5f * x0 * (fast_log(b0) + fast_log(b1));
             if (xx > xmax) continue;
         } else {
             xx = xmax * sqrtf(b0);
-            if (b1 > fast_exp(-2.0f * xx / x0)) continue;
+            if (b1 > fast_exp(m2ix0 * xx)) continue;
         }
         const float r = xx * ixmax;
         const float ct = 1.0f - 2.0f * r * r;

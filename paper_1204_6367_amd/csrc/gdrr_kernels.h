@@ -139,7 +139,8 @@ struct Photon {
     int st;
     bool passb;                // adjoint: second (visiting) pass
     ECache ec;
-    float pu2, pu3;            // pending collision: type and azimuth uniforms
+    uint32_t rz, rw;           // second half of the flight block: the next (even) flight's words
+    float sel;                 // pending collision: ladder / rho, compared with mu_R and mu_R + mu_C
     int pm;                    // pending collision: material
     float w;                   // adjoint weight of the history
 };
@@ -189,7 +190,7 @@ __device__ __forceinline__ int detector_pixel(const DJob& J, const Photon& ph, i
     const float dn = ph.dx * J.nx + ph.dy * J.ny + ph.dz * J.nz;
     pixel = -1;
     if (!(dn > 0.0f)) return kMissed;
-    const float t = ((J.Px - ph.px) * J.nx + (J.Py - ph.py) * J.ny + (J.Pz - ph.pz) * J.nz) / dn;
+    const float t = ((J.Px - ph.px) * J.nx + (J.Py - ph.py) * J.ny + (J.Pz - ph.pz) * J.nz) * fast_rcp(dn);
     if (!(t >= 0.0f)) return kMissed;
     const float hx = ph.px + t * ph.dx - J.Px, hy = ph.py + t * ph.dy - J.Py, hz = ph.pz + t * ph.dz - J.Pz;
     const float fu = (hx * J.ux + hy * J.uy + hz * J.uz) * J.idu + 0.5f * (float)J.nu;
@@ -310,7 +311,8 @@ __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
     ph.pid = 0;
     ph.jid = 0;
     ph.nsc = 0;
-    ph.pu2 = ph.pu3 = 0.0f;
+    ph.sel = 0.0f;
+    ph.rz = ph.rw = 0u;
     ph.pm = 0;
 
     // wavefront-uniform dispenser state
@@ -382,8 +384,14 @@ __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
         }
         if (ph.st == kFly) {
             ph.step += 1;
-            const Block b = philox(ph.pid, ph.jid, ph.step, 0u, P.k0, P.k1);
-            const float s = -fast_log(u24(b.x)) * ph.ec.mfp;
+            uint32_t ra, rb;           // flight k: words 0,1 (k odd) or 2,3 (k even) of block (k+1)/2
+            if (ph.step & 1u) {
+                const Block b = philox(ph.pid, ph.jid, (ph.step + 1u) >> 1, 0u, P.k0, P.k1);
+                ra = b.x; rb = b.y; ph.rz = b.z; ph.rw = b.w;
+            } else {
+                ra = ph.rz; rb = ph.rw;
+            }
+            const float s = -fast_log(u24(ra)) * ph.ec.mfp;
             if (!(s < ph.trem)) {
                 int pixel;
                 const int cls = detector_pixel(P.jobs[ph.job], ph, pixel);
@@ -398,12 +406,13 @@ __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
                 m = m < P.n_mat ? m : P.n_mat - 1;
                 const float2 tt = T.tot[m * P.n_e + ph.ec.j];
                 const float tot = tt.x + ph.ec.f * tt.y;
-                const bool real = u24(b.y) * ph.ec.mbar < rho * tot;
+                // one uniform on [0, mbar): real below mu = rho tot, then the type ladder
+                const float ladder = u24(rb) * ph.ec.mbar;
+                const bool real = ladder < rho * tot;
                 if (MODE == kModeBackward && ph.passb) visit(P, V, interp, ph, real, rho, tot, ph.ec.mbar);
                 if (real) {
                     ph.st = kColl;
-                    ph.pu2 = u24(b.z);
-                    ph.pu3 = u24(b.w);
+                    ph.sel = ladder * fast_rcp(rho);
                     ph.pm = m;
                 }
             }
@@ -418,15 +427,14 @@ __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
                 const float* a = P.mu_mass + ((size_t)m * P.n_e + ph.ec.j) * 3;   // j <= n_e - 2
                 const float R = a[0] + ph.ec.f * (a[3] - a[0]);
                 const float C = a[1] + ph.ec.f * (a[4] - a[1]);
-                const float2 tt = T.tot[m * P.n_e + ph.ec.j];
-                const float sel = ph.pu2 * (tt.x + ph.ec.f * tt.y);
-                float ct;
+                const float sel = ph.sel;
+                float ct, az = 0.0f;
                 bool alive = true;
                 if (sel < R) {
-                    ct = rayleigh(ph.pid, ph.jid, ph.step, P.k0, P.k1, ph.E, P.x0);
+                    ct = rayleigh(ph.pid, ph.jid, ph.step, P.k0, P.k1, ph.E, P.x0, az);
                     ph.nsc += 1u << 16;
                 } else if (sel < R + C) {
-                    ct = compton(ph.pid, ph.jid, ph.step, P.k0, P.k1, ph.E);
+                    ct = compton(ph.pid, ph.jid, ph.step, P.k0, P.k1, ph.E, az);
                     ph.nsc += 1u;
                     ph.ec = energy_cache(P, T, vo, ph.E);
                 } else {
@@ -436,7 +444,7 @@ __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
                     ph.st = kDead;
                 }
                 if (alive) {
-                    rotate(ph.dx, ph.dy, ph.dz, ct, ph.pu3);
+                    rotate(ph.dx, ph.dy, ph.dz, ct, az);
                     if (ph.E < P.e_cut) {
                         if (MODE == kModeTrace) trace_out<MODE>(P, ph, kCut, -1);
                         ph.st = kDead;
@@ -541,20 +549,40 @@ struct SrcPrepParams {
     unsigned int* error;
 };
 
-__global__ __launch_bounds__(256) void cdf_kernel(SrcPrepParams S) {
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        int bad = 0;
-        for (int i = 0; i < S.n; ++i) {
-            const double x = (double)S.w[i];
-            if (!(x >= 0.0) || isinf(x)) bad = 1;
-            s += x;
-            S.cdf[i] = s;
-        }
-        if (!(s > 0.0)) bad = 1;
-        if (bad) atomicOr(S.error, 4u);
-        for (int i = 0; i < S.n; ++i) S.cdf[i] = S.cdf[i] / s;
+// One workgroup of 1024 threads: each thread sums a contiguous segment in
+// index order, the segment totals are scanned, and each thread writes its
+// segment's running sums divided by the total.  The sums are those of the
+// definition, accumulated in a different association (float64 rounding only).
+__global__ __launch_bounds__(1024) void cdf_kernel(SrcPrepParams S) {
+    __shared__ double part[1024];
+    __shared__ int bad;
+    const int t = threadIdx.x, nt = blockDim.x;
+    if (t == 0) bad = 0;
+    const int per = (S.n + nt - 1) / nt;
+    const int a = min(S.n, t * per), b = min(S.n, a + per);
+    double s = 0.0;
+    int mybad = 0;
+    for (int i = a; i < b; ++i) {
+        const double x = (double)S.w[i];
+        if (!(x >= 0.0) || isinf(x)) mybad = 1;
+        s += x;
     }
+    part[t] = s;
+    __syncthreads();
+    if (mybad) bad = 1;
+    for (int off = 1; off < nt; off <<= 1) {     // inclusive Hillis-Steele scan of the totals
+        const double v = t >= off ? part[t - off] : 0.0;
+        __syncthreads();
+        part[t] += v;
+        __syncthreads();
+    }
+    const double total = part[nt - 1];
+    double run = t > 0 ? part[t - 1] : 0.0;
+    for (int i = a; i < b; ++i) {
+        run += (double)S.w[i];
+        S.cdf[i] = run / total;
+    }
+    if (t == 0 && (bad || !(total > 0.0))) atomicOr(S.error, 4u);
 }
 
 __global__ __launch_bounds__(256) void guide_kernel(SrcPrepParams S) {

@@ -335,11 +335,11 @@ def test_sphere_symmetry(oracle_lib):
 # with Phi(x) = f |D-S|^2/cos(a) T_in(x, E) / |x-S|^2 the fluence per source
 # photon (f the aim-point density per area), p_k the angular pdf per sr.
 # ---------------------------------------------------------------------------
-def single_scatter_expectation(geom, half, table_grid, mu_tab, f_area, field_half, nvq=8, nq=4):
+def single_scatter_expectation(geom, half, table_grid, mu_tab, f_area, field_half, nvq=8, nq=4, rho=1.0):
     S, P, n, eu, ev = geo_frame(geom.phi_rad, geom.theta_rad, geom.sad_mm, geom.aid_mm)
     E = 60.0
     egrid = table_grid.energies()
-    mu_k = lambda e, k: 0.1 * np.interp(e, egrid, mu_tab[:, k].astype(np.float64))   # 1/mm
+    mu_k = lambda e, k: 0.1 * rho * np.interp(e, egrid, mu_tab[:, k].astype(np.float64))   # 1/mm
     mu_t = lambda e: mu_k(e, 0) + mu_k(e, 1) + mu_k(e, 2)
     kap = E / ME
     kn = lambda c: (lambda Pq: Pq * Pq * (Pq + 1 / Pq - (1 - c * c)))(1 / (1 + kap * (1 - c)))
@@ -390,9 +390,10 @@ def single_scatter_expectation(geom, half, table_grid, mu_tab, f_area, field_hal
     return out
 
 
-def test_single_scatter_matches_integral(oracle_lib):
+@pytest.mark.parametrize("rho", [1.0, 0.55])
+def test_single_scatter_matches_integral(oracle_lib, rho):
     nvox, d = 8, 5.0
-    ph = W.box_phantom((nvox, nvox, nvox), (d, d, d), "water", 1.0)
+    ph = W.box_phantom((nvox, nvox, nvox), (d, d, d), "water", rho)
     g = W.Geometry(nu=16, nv=16, du_mm=40.0, dv_mm=40.0)
     flu = np.zeros((16, 16), np.float32)
     flu[7:9, 7:9] = 1.0                                     # 80 mm square field
@@ -400,7 +401,7 @@ def test_single_scatter_matches_integral(oracle_lib):
     p = make(ph, g, fluence=flu, phys_grid=grid)
     half = np.full(3, 0.5 * nvox * d)
     mu_tab = W.cross_section_table(["water"], grid)[0]
-    want = single_scatter_expectation(g, half, grid, mu_tab, 1.0 / (80.0 * 80.0), 40.0)
+    want = single_scatter_expectation(g, half, grid, mu_tab, 1.0 / (80.0 * 80.0), 40.0, rho=float(np.float32(rho)))
     n = 4_000_000
     r = oracle_lib.mc_project(p, seed=17, n=n, mode=1)
     t, t2 = r["tally"][2], r["tally"][3]
