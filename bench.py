@@ -76,6 +76,15 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def autotune_for(batch):
+    """Launch shape from the autotuner (untimed setup, 2 % of the photons)."""
+    from paper_1204_6367_amd import autotune
+    t = time.time()
+    best = autotune.autotune(batch, fraction=0.02, min_photons=200_000, cache=None, force=True)
+    log(f"autotune {best} in {time.time() - t:.1f}s")
+    return best
+
+
 # ---------------------------------------------------------------------------
 # workloads
 # ---------------------------------------------------------------------------
@@ -92,17 +101,19 @@ def build_workload(name, api, W, torch):
         batch = api.Batch([vol], phys, [src], jobs)
         tallies = torch.zeros(batch.tally_elems, dtype=torch.float64, device="cuda")
         fwd = sum(j.n_photons for j in jobs)
+        tune = autotune_for(batch)
 
         def step():
             maj = batch.majorants(True)
-            batch.project(seed=1, majorants=maj, out=tallies)
+            batch.project(seed=1, majorants=maj, out=tallies, tune=tune)
             return [api.last_kernel_ms()]
 
         samples = [(prob, float(jobs[k].geom.phi_rad), jobs[k].job_id) for k in (0, len(jobs) // 2)]
         return dict(step=step, fwd=fwd, adj=0, samples=samples, adjoint=None,
                     config=dict(workload=name, phantom="256x256x160 @1.95x1.95x2.5mm ellipsoids",
                                 angles=len(jobs), photons_per_angle=jobs[0].n_photons,
-                                detector="256x192 @1.552mm", spectrum="120 kVp Kramers + 2.5 mm Al, bowtie 30 mm Al"))
+                                detector="256x192 @1.552mm", spectrum="120 kVp Kramers + 2.5 mm Al, bowtie 30 mm Al",
+                                tuning=tune))
     if name in ("c3", "c4"):
         if name == "c3":
             prob, target = W.adjoint_problem(10_000_000)
@@ -150,16 +161,17 @@ def build_workload(name, api, W, torch):
         fwd = sum(j.n_photons for j in jobs)
         adjh = sum(jobs[k].n_photons for k in adj_idx)
         state = {}
+        tune = autotune_for(batch)
 
         def step():
             maj = torch.stack([api.majorant(v, dphys, True, margins[k]) for k, v in enumerate(vols)])
-            batch.project(seed=1, sumsq=False, majorants=maj, out=tallies)
+            batch.project(seed=1, sumsq=False, majorants=maj, out=tallies, tune=tune)
             ms_f = api.last_kernel_ms()
             views = batch.tally_views(tallies)
             s_now = torch.stack([views[k][2] for k in adj_idx])
             adj = torch.zeros(len(adj_idx), 2, geom.nv, geom.nu, dtype=torch.float64, device="cuda")
             adj[:, 1] = s_now - s_target                       # d(0.5||S - S*||^2)/dS
-            adj_batch.backward(adj, maj, volume=adj_vol, seed=1, grad=grad)
+            adj_batch.backward(adj, maj, volume=adj_vol, seed=1, grad=grad, tune=tune)
             ms_b = api.last_kernel_ms()
             state["loss"] = 0.5 * float(((s_now - s_target) ** 2).sum())
             return [ms_f, ms_b]
@@ -172,7 +184,7 @@ def build_workload(name, api, W, torch):
                             jobs[k].job_id))
         adjoint = dict(problem=W.Problem(phantoms[adj_vol][0], physw, srcw, jobs[adj_idx[0]].geom, 1),
                        job_id=jobs[adj_idx[0]].job_id, margin=0.1)
-        cfg = dict(workload=name, angles=len(jobs), adjoint_angles=len(adj_idx),
+        cfg = dict(workload=name, angles=len(jobs), adjoint_angles=len(adj_idx), tuning=tune,
                    detector="256x192 @1.552mm", spectrum="120 kVp Kramers + 2.5 mm Al, bowtie 30 mm Al",
                    phantoms=[f"{'x'.join(map(str, ph.shape[::-1]))} @{ph.spacing_mm[0]}mm" for ph, _ in phantoms],
                    photons_per_angle=[p[2] for p in plan])

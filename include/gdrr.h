@@ -36,7 +36,9 @@
  * themselves are host pointers read during the call.  All calls are
  * asynchronous on `stream` (a hipStream_t passed as void*; NULL = the null
  * stream) and may be recorded into a HIP graph.  The library keeps no device
- * memory between calls: scratch lives in the caller's workspace.
+ * memory between calls: scratch lives in the caller's workspace, which also
+ * holds a per-call copy of each phantom laid out for the transport kernel
+ * (64 bytes per voxel: the eight interpolation corners of each cell).
  *
  * Errors: functions return GDRR_OK (0) or a negative code; no exception
  * crosses the ABI; gdrr_last_error() gives a message for the calling thread.
@@ -153,7 +155,7 @@ int gdrr_mc_project(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr
                     const gdrr_geometry* geom, const float* majorant, uint64_t seed,
                     uint64_t n_photons, uint32_t job_id, uint32_t flags, double* tally,
                     void* workspace, size_t ws_bytes, void* stream);
-size_t gdrr_mc_project_workspace(const gdrr_physics* phys, const gdrr_source* src,
+size_t gdrr_mc_project_workspace(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr_source* src,
                                  const gdrr_geometry* geom);
 
 /*
@@ -170,8 +172,9 @@ int gdrr_mc_project_batch(const gdrr_volume* vols, int32_t n_vols, const gdrr_ph
                           int32_t n_jobs, const float* majorants, uint64_t seed, uint32_t flags,
                           const gdrr_tuning* tune, double* tallies, void* workspace,
                           size_t ws_bytes, void* stream);
-size_t gdrr_mc_project_batch_workspace(const gdrr_physics* phys, const gdrr_source* srcs,
-                                       int32_t n_srcs, const gdrr_job* jobs, int32_t n_jobs);
+size_t gdrr_mc_project_batch_workspace(const gdrr_volume* vols, int32_t n_vols, const gdrr_physics* phys,
+                                       const gdrr_source* srcs, int32_t n_srcs, const gdrr_job* jobs,
+                                       int32_t n_jobs);
 
 /*
  * Gradient of a loss of the tallies with respect to voxel density (not in the

@@ -70,11 +70,12 @@ SIGNATURES = {
     "gdrr_majorant_workspace": (_sz, []),
     "gdrr_mc_project": (C.c_int, [_P(Volume), _P(Physics), _P(Source), _P(Geometry), _vp, C.c_uint64,
                                   C.c_uint64, C.c_uint32, C.c_uint32, _vp, _vp, _sz, _vp]),
-    "gdrr_mc_project_workspace": (_sz, [_P(Physics), _P(Source), _P(Geometry)]),
+    "gdrr_mc_project_workspace": (_sz, [_P(Volume), _P(Physics), _P(Source), _P(Geometry)]),
     "gdrr_mc_project_batch": (C.c_int, [_P(Volume), C.c_int32, _P(Physics), _P(Source), C.c_int32, _P(Job),
                                         C.c_int32, _vp, C.c_uint64, C.c_uint32, _P(Tuning), _vp, _vp, _sz,
                                         _vp]),
-    "gdrr_mc_project_batch_workspace": (_sz, [_P(Physics), _P(Source), C.c_int32, _P(Job), C.c_int32]),
+    "gdrr_mc_project_batch_workspace": (_sz, [_P(Volume), C.c_int32, _P(Physics), _P(Source), C.c_int32,
+                                             _P(Job), C.c_int32]),
     "gdrr_mc_backward": (C.c_int, [_P(Volume), C.c_int32, _P(Physics), _P(Source), C.c_int32, _P(Job),
                                    C.c_int32, C.c_int32, _vp, C.c_uint64, C.c_uint32, _P(Tuning), _vp, _vp,
                                    _vp, _sz, _vp]),

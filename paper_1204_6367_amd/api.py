@@ -132,7 +132,7 @@ def project(vol: DeviceVolume, phys: DevicePhysics, src: DeviceSource, geom, n_p
     v, p, s = vol.struct(density), phys.struct(), src.struct()
     if out is None:
         out = torch.zeros(4, geom.nv, geom.nu, dtype=torch.float64, device=vol.density.device)
-    nbytes = int(L.gdrr_mc_project_workspace(C.byref(p), C.byref(s), C.byref(g)))
+    nbytes = int(L.gdrr_mc_project_workspace(C.byref(v), C.byref(p), C.byref(s), C.byref(g)))
     ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=vol.density.device)
     mb = None if majorant_tab is None else majorant_tab.data_ptr()
     _abi.check(L.gdrr_mc_project(C.byref(v), C.byref(p), C.byref(s), C.byref(g), mb, seed, n_photons, job_id,
@@ -155,7 +155,7 @@ def trace(vol: DeviceVolume, phys: DevicePhysics, src: DeviceSource, geom, n_pho
                n_rayleigh=torch.empty(n_photons, dtype=torch.int32, device=dev))
     g = geometry_struct(geom)
     v, p, s = vol.struct(), phys.struct(), src.struct()
-    nbytes = int(L.gdrr_mc_project_workspace(C.byref(p), C.byref(s), C.byref(g)))
+    nbytes = int(L.gdrr_mc_project_workspace(C.byref(v), C.byref(p), C.byref(s), C.byref(g)))
     ws = torch.empty(max(nbytes, 1), dtype=torch.uint8, device=dev)
     mb = None if majorant_tab is None else majorant_tab.data_ptr()
     _abi.check(L.gdrr_mc_trace(C.byref(v), C.byref(p), C.byref(s), C.byref(g), mb, seed, n_photons, job_id,
@@ -227,9 +227,9 @@ class Batch:
 
     def workspace(self) -> torch.Tensor:
         L = _abi.lib()
-        _, sa, p = self._structs()
-        nbytes = int(L.gdrr_mc_project_batch_workspace(C.byref(p), sa, len(self.srcs), self._jobs_c,
-                                                      len(self.jobs)))
+        va, sa, p = self._structs()
+        nbytes = int(L.gdrr_mc_project_batch_workspace(va, len(self.vols), C.byref(p), sa, len(self.srcs),
+                                                      self._jobs_c, len(self.jobs)))
         if self._ws is None or self._ws.numel() < nbytes:
             self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.vols[0].density.device)
         return self._ws

@@ -18,7 +18,7 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotu
 
 CANDIDATES: List[Dict[str, int]] = [
     dict(block=b, defer=d, chunk=0, blocks_per_cu=0)
-    for b in (256, 512, 1024) for d in (1, 4, 8, 16, 32)
+    for b in (256, 512) for d in (8, 16, 24, 32, 40)
 ]
 
 

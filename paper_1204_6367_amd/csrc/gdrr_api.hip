@@ -282,13 +282,18 @@ struct Layout {
     unsigned int* rho_max;            // [n_vols][256]
     unsigned int* present;            // [n_vols][256]
     SrcArea src[GDRR_MAX_SOURCES];
+    CellRec* cells[GDRR_MAX_VOLUMES]; // per-volume cell records
     unsigned long long* tally;        // fixed-point tallies
     size_t tally_elems;
     size_t bytes;
 };
 
-Layout carve(void* ws, const gdrr_physics* phys, const gdrr_source* srcs, int n_srcs, int n_jobs, int n_vols,
-             size_t tally_elems, bool need_majorant) {
+size_t cell_count(const gdrr_volume& v) {
+    return (size_t)(v.nx + 1) * (size_t)(v.ny + 1) * (size_t)(v.nz + 1);
+}
+
+Layout carve(void* ws, const gdrr_volume* vols, const gdrr_physics* phys, const gdrr_source* srcs, int n_srcs,
+             int n_jobs, int n_vols, size_t tally_elems, bool need_majorant) {
     Carver c(ws);
     Layout L{};
     L.counter = c.take<unsigned long long>(8);
@@ -307,6 +312,7 @@ Layout carve(void* ws, const gdrr_physics* phys, const gdrr_source* srcs, int n_
         L.src[s].flu_cdf = c.take<double>((size_t)npix);
         L.src[s].flu_guide = c.take<uint32_t>(L.src[s].flu_k);
     }
+    for (int v = 0; v < n_vols; ++v) L.cells[v] = c.take<CellRec>(cell_count(vols[v]));
     L.tally = c.take<unsigned long long>(tally_elems);
     L.tally_elems = tally_elems;
     L.bytes = c.off + 256;
@@ -381,14 +387,14 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     if (rc) return rc;
     const gdrr_physics* phys = B.phys;
     const bool need_maj = B.majorants == nullptr;
-    const Layout L0 = carve(nullptr, phys, B.srcs, B.n_srcs, B.n_jobs, B.n_vols,
+    const Layout L0 = carve(nullptr, B.vols, phys, B.srcs, B.n_srcs, B.n_jobs, B.n_vols,
                             tally_elems_of(B.jobs, B.n_jobs, B.srcs), need_maj);
     if (!ws || ws_bytes < L0.bytes)
         return fail(GDRR_EINVAL, "workspace too small: need " + std::to_string(L0.bytes) + " bytes");
     DevInfo dev;
     if ((rc = device_info(dev))) return rc;
     char* wsa = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
-    const Layout L = carve(wsa, phys, B.srcs, B.n_srcs, B.n_jobs, B.n_vols, L0.tally_elems, need_maj);
+    const Layout L = carve(wsa, B.vols, phys, B.srcs, B.n_srcs, B.n_jobs, B.n_vols, L0.tally_elems, need_maj);
     const bool interp = (B.flags & GDRR_INTERP_DENSITY) != 0;
 
     // ---- host tables: jobs, chunk prefix, output offsets ----
@@ -416,7 +422,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
         c = std::max<unsigned long long>(64, std::min<unsigned long long>(4096, c));
         chunk = (int)(c / 64 * 64);
     }
-    const int defer = tune.defer ? tune.defer : 8;
+    const int defer = tune.defer ? tune.defer : 32;
 
     const size_t n_jobs = (size_t)B.n_jobs;
     const size_t job_bytes = sizeof(unsigned long long) * (n_jobs + 1);
@@ -500,6 +506,19 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
         }
         maj = L.majorants;
     }
+    // ---- cell records of every volume that has photons ----
+    for (int v = 0; v < B.n_vols; ++v) {
+        bool used = false;
+        for (int k = 0; k < B.n_jobs; ++k)
+            used |= B.jobs[k].volume == v && B.jobs[k].n_photons > 0 && (B.only_volume < 0 || v == B.only_volume);
+        if (!used) continue;
+        const gdrr_volume& V = B.vols[v];
+        CellParams cp{V.density, V.material, V.nx, V.ny, V.nz, L.cells[v]};
+        const size_t nc = cell_count(V);
+        ls.push_back(make_launch((const void*)&cells_kernel,
+                                 dim3((unsigned)std::max<size_t>(1, std::min<size_t>((size_t)dev.cus * 16, (nc + 255) / 256))),
+                                 dim3(256), 0, cp));
+    }
     // ---- sources: CDFs and guide tables ----
     for (int s = 0; s < B.n_srcs; ++s) {
         const gdrr_source& S = B.srcs[s];
@@ -518,6 +537,9 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
         DVolume& d = kp.vol[v];
         d.density = V.density;
         d.material = V.material;
+        d.cells = L.cells[v];
+        d.cx = V.nx + 1;
+        d.cxy = (V.nx + 1) * (V.ny + 1);
         d.nx = V.nx; d.ny = V.ny; d.nz = V.nz; d.nxy = V.nx * V.ny;
         d.lox = (float)(-0.5 * V.nx * V.dx_mm); d.hix = -d.lox;
         d.loy = (float)(-0.5 * V.ny * V.dy_mm); d.hiy = -d.loy;
@@ -587,10 +609,15 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     return B.use_graph ? run_graph(ls, st, timed, ev) : run_direct(ls, st, timed, ev);
 }
 
-size_t batch_bytes(const gdrr_physics* phys, const gdrr_source* srcs, int n_srcs, const gdrr_job* jobs, int n_jobs,
-                   int n_vols, bool need_maj) {
-    if (!phys || !srcs || !jobs || n_srcs < 1 || n_srcs > GDRR_MAX_SOURCES || n_jobs < 1 || n_vols < 1) return 0;
-    return carve(nullptr, phys, srcs, n_srcs, n_jobs, n_vols, tally_elems_of(jobs, n_jobs, srcs), need_maj).bytes + 256;
+size_t batch_bytes(const gdrr_volume* vols, int n_vols, const gdrr_physics* phys, const gdrr_source* srcs,
+                   int n_srcs, const gdrr_job* jobs, int n_jobs, bool need_maj) {
+    if (!vols || !phys || !srcs || !jobs || n_srcs < 1 || n_srcs > GDRR_MAX_SOURCES || n_jobs < 1 || n_vols < 1 ||
+        n_vols > GDRR_MAX_VOLUMES)
+        return 0;
+    for (int v = 0; v < n_vols; ++v)
+        if (vols[v].nx < 1 || vols[v].ny < 1 || vols[v].nz < 1) return 0;
+    return carve(nullptr, vols, phys, srcs, n_srcs, n_jobs, n_vols, tally_elems_of(jobs, n_jobs, srcs), need_maj).bytes +
+           256;
 }
 
 gdrr_job single_job(const gdrr_geometry* geom, uint64_t n, uint32_t job_id) {
@@ -639,7 +666,7 @@ int gdrr_default_tuning(gdrr_tuning* out) {
     out->block = 256;
     out->blocks_per_cu = 0;
     out->chunk = 0;
-    out->defer = 8;
+    out->defer = 32;
     return GDRR_OK;
 }
 
@@ -671,10 +698,11 @@ int gdrr_majorant(const gdrr_volume* vol, const gdrr_physics* phys, uint32_t fla
     return run_direct(ls, st);
 }
 
-size_t gdrr_mc_project_workspace(const gdrr_physics* phys, const gdrr_source* src, const gdrr_geometry* geom) {
+size_t gdrr_mc_project_workspace(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr_source* src,
+                                 const gdrr_geometry* geom) {
     if (!geom) return 0;
     gdrr_job j = single_job(geom, 0, 0);
-    return batch_bytes(phys, src, 1, &j, 1, 1, true);
+    return batch_bytes(vol, 1, phys, src, 1, &j, 1, true);
 }
 
 int gdrr_mc_project(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr_source* src,
@@ -689,9 +717,10 @@ int gdrr_mc_project(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr
     return run_batch(B, workspace, ws_bytes, (hipStream_t)stream);
 }
 
-size_t gdrr_mc_project_batch_workspace(const gdrr_physics* phys, const gdrr_source* srcs, int32_t n_srcs,
-                                       const gdrr_job* jobs, int32_t n_jobs) {
-    return batch_bytes(phys, srcs, n_srcs, jobs, n_jobs, GDRR_MAX_VOLUMES, true);
+size_t gdrr_mc_project_batch_workspace(const gdrr_volume* vols, int32_t n_vols, const gdrr_physics* phys,
+                                       const gdrr_source* srcs, int32_t n_srcs, const gdrr_job* jobs,
+                                       int32_t n_jobs) {
+    return batch_bytes(vols, n_vols, phys, srcs, n_srcs, jobs, n_jobs, true);
 }
 
 int gdrr_mc_project_batch(const gdrr_volume* vols, int32_t n_vols, const gdrr_physics* phys,

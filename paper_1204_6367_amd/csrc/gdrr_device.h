@@ -75,10 +75,23 @@ __device__ __forceinline__ float cos_rev(float r) { return __builtin_amdgcn_cosf
 // ---------------------------------------------------------------------------
 // Launch-time descriptors (built on the host).
 // ---------------------------------------------------------------------------
+// One record per cell of the lattice of voxel centres: cell (i, j, k),
+// i in [-1, nx-1], has the voxel centres i and i+1 (clamped into the volume)
+// as corners along x, likewise along y and z; corner c = bx + 2 by + 4 bz.
+// The record holds the eight corner densities and materials, so the stencil
+// of a free flight is one aligned 64-byte line.
+struct alignas(64) CellRec {
+    float d[8];
+    uint8_t m[8];
+    uint32_t spare[6];
+};
+
 struct DVolume {
     const float* density;
     const uint8_t* material;
+    const CellRec* cells;     // [(nz+1)][(ny+1)][(nx+1)]
     int nx, ny, nz, nxy;
+    int cx, cxy;              // cells per row (nx+1) and per slab ((nx+1)(ny+1))
     float lox, loy, loz;      // box corner (-n d / 2)
     float hix, hiy, hiz;
     float idx, idy, idz;      // 1 / voxel size

@@ -123,6 +123,36 @@ __device__ __forceinline__ float density_at(const DVolume& V, bool interp, float
     return b0 + fz * (b1 - b0);
 }
 
+// The same density and material from the cell records: one 64-byte line.
+// The containing voxel is corner (f >= 1/2) of the cell along each axis.
+__device__ __forceinline__ float cell_density(const DVolume& V, bool interp, float px, float py, float pz,
+                                              int& mat) {
+    const float hx = (px - V.lox) * V.idx - 0.5f, hy = (py - V.loy) * V.idy - 0.5f, hz = (pz - V.loz) * V.idz - 0.5f;
+    const float fx0 = floorf(hx), fy0 = floorf(hy), fz0 = floorf(hz);
+    const int ix = min(max((int)fx0, -1), V.nx - 1);
+    const int iy = min(max((int)fy0, -1), V.ny - 1);
+    const int iz = min(max((int)fz0, -1), V.nz - 1);
+    const float fx = fminf(fmaxf(hx - fx0, 0.0f), 1.0f);
+    const float fy = fminf(fmaxf(hy - fy0, 0.0f), 1.0f);
+    const float fz = fminf(fmaxf(hz - fz0, 0.0f), 1.0f);
+    const CellRec* r = V.cells + ((iz + 1) * V.cxy + (iy + 1) * V.cx + (ix + 1));
+    const float4 lo4 = *reinterpret_cast<const float4*>(&r->d[0]);
+    const float4 hi4 = *reinterpret_cast<const float4*>(&r->d[4]);
+    const uint2 mm = *reinterpret_cast<const uint2*>(&r->m[0]);
+    const int bits = (fx >= 0.5f ? 1 : 0) | (fy >= 0.5f ? 2 : 0) | (fz >= 0.5f ? 4 : 0);
+    const uint32_t mw = bits & 4 ? mm.y : mm.x;
+    mat = (int)((mw >> ((bits & 3) * 8)) & 0xFFu);
+    if (!interp) {
+        const float4 q = bits & 4 ? hi4 : lo4;
+        const int b2 = bits & 3;
+        return b2 == 0 ? q.x : (b2 == 1 ? q.y : (b2 == 2 ? q.z : q.w));
+    }
+    const float a00 = lo4.x + fx * (lo4.y - lo4.x), a01 = lo4.z + fx * (lo4.w - lo4.z);
+    const float a10 = hi4.x + fx * (hi4.y - hi4.x), a11 = hi4.z + fx * (hi4.w - hi4.z);
+    const float b0 = a00 + fy * (a01 - a00), b1 = a10 + fy * (a11 - a10);
+    return b0 + fz * (b1 - b0);
+}
+
 __device__ __forceinline__ float response_at(const KParams& P, const Tables& T, const ECache& ec, float E) {
     if (!P.response) return E;
     const float2 r = T.resp[ec.j];
@@ -402,7 +432,7 @@ __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
                 ph.pz += s * ph.dz;
                 ph.trem -= s;
                 int m;
-                const float rho = density_at<false>(V, interp, ph.px, ph.py, ph.pz, m, nullptr, nullptr);
+                const float rho = cell_density(V, interp, ph.px, ph.py, ph.pz, m);
                 m = m < P.n_mat ? m : P.n_mat - 1;
                 const float2 tt = T.tot[m * P.n_e + ph.ec.j];
                 const float tot = tt.x + ph.ec.f * tt.y;
@@ -534,6 +564,39 @@ __global__ __launch_bounds__(256) void majorant_kernel(MajFinParams F) {
     }
     if (blockIdx.x == 0 && threadIdx.x < 256 - F.n_mat && F.present[F.n_mat + threadIdx.x])
         atomicOr(F.error, 2u);   // material index out of range
+}
+
+// ---------------------------------------------------------------------------
+// Cell records of a volume (the per-flight data layout).
+// ---------------------------------------------------------------------------
+struct CellParams {
+    const float* density;
+    const uint8_t* material;
+    int nx, ny, nz;
+    CellRec* cells;
+};
+
+__global__ __launch_bounds__(256) void cells_kernel(CellParams C) {
+    const long long cx = C.nx + 1, cy = C.ny + 1, n = cx * cy * (long long)(C.nz + 1);
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(t % cx) - 1, j = (int)((t / cx) % cy) - 1, k = (int)(t / (cx * cy)) - 1;
+        float d[8];
+        uint32_t mlo = 0u, mhi = 0u;
+        for (int c = 0; c < 8; ++c) {
+            const int x = min(max(i + (c & 1), 0), C.nx - 1);
+            const int y = min(max(j + ((c >> 1) & 1), 0), C.ny - 1);
+            const int z = min(max(k + (c >> 2), 0), C.nz - 1);
+            const long long v = ((long long)z * C.ny + y) * C.nx + x;
+            d[c] = C.density[v];
+            const uint32_t m = C.material[v];
+            if (c < 4) mlo |= m << (8 * c); else mhi |= m << (8 * (c - 4));
+        }
+        float4* out = reinterpret_cast<float4*>(C.cells + t);
+        out[0] = make_float4(d[0], d[1], d[2], d[3]);
+        out[1] = make_float4(d[4], d[5], d[6], d[7]);
+        out[2] = make_float4(__uint_as_float(mlo), __uint_as_float(mhi), 0.0f, 0.0f);
+        out[3] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
 }
 
 // ---------------------------------------------------------------------------

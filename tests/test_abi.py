@@ -123,8 +123,8 @@ def test_too_many_photons_and_small_workspace(abi):
 def test_workspace_query_is_positive(abi):
     vol, phys, src, geom = _valid_structs(abi)
     L = abi.lib()
-    n = L.gdrr_mc_project_workspace(C.byref(phys), C.byref(src), C.byref(geom))
-    assert n > 8 * 4 * 16 * 12
+    n = L.gdrr_mc_project_workspace(C.byref(vol), C.byref(phys), C.byref(src), C.byref(geom))
+    assert n > 8 * 4 * 16 * 12 + 64 * 9 * 9 * 9
     assert L.gdrr_majorant_workspace() >= 2048
     assert L.gdrr_version().decode().startswith("gdrr")
 
