@@ -76,9 +76,14 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TUNE_MODE = "auto"
+
+
 def autotune_for(batch):
     """Launch shape from the autotuner (untimed setup, 2 % of the photons)."""
     from paper_1204_6367_amd import autotune
+    if TUNE_MODE == "default":
+        return None
     t = time.time()
     best = autotune.autotune(batch, fraction=0.02, min_photons=200_000, cache=None, force=True)
     log(f"autotune {best} in {time.time() - t:.1f}s")
@@ -251,6 +256,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune", default="auto", choices=["auto", "default"],
+                    help="auto: autotune the launch shape before timing; default: library defaults")
     ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per transport launch")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (reference for the HBM byte counters)")
@@ -269,6 +276,8 @@ def main():
               f"across GPUs with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
 
+    global TUNE_MODE
+    TUNE_MODE = args.tune
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
