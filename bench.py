@@ -42,13 +42,13 @@ ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # 32-bit VALU lane-ops/s: 256 CUs x
 # 32-bit VALU issue slots (quarter-rate integer multiplies and transcendentals
 # count 4) and bytes the algorithm must gather.
 SLOTS_PHILOX = 10 * (4 * 4 + 2)          # 2 mul_hi + 2 mul_lo (quarter rate) + 2 xor3 per round
-# one Philox block serves two free flights (two words each)
-SLOTS_FLIGHT_IN = SLOTS_PHILOX // 2 + 3 + 7 + 4 + 64 + 7   # uniforms, -ln u, move, trilinear, lookup+ladder
-SLOTS_FLIGHT_OUT = SLOTS_PHILOX // 2 + 3 + 7 + 30         # the escaping flight: detector intersection
+# free flights come in pairs sharing one Philox block (counted per history below)
+SLOTS_FLIGHT_IN = 3 + 7 + 4 + 24 + 7                   # uniforms, -ln u, move, cell-record trilinear, lookup+ladder
+SLOTS_FLIGHT_OUT = 3 + 7 + 30                          # the escaping flight: detector intersection
 SLOTS_TRY = SLOTS_PHILOX + 9 + 30                      # one angular-sampler try
 SLOTS_COLLISION = 6 + 55 + 40 + 10                     # type select, rotation, box exit, energy cache
 SLOTS_SOURCE = 2 * SLOTS_PHILOX + 40 + 34 + 45         # two blocks, CDFs (fp64), aim point, box entry
-BYTES_FLIGHT_IN = 8 * 4 + 1                            # eight density corners + the material byte
+BYTES_FLIGHT_IN = 8 * 4 + 1                            # eight density corners + the containing voxel's material
 BYTES_SOURCE = 2 * (2 * 8 + 4) + 4                     # CDF + guide reads for energy and pixel, energy
 BYTES_SCORE = 8                                        # one fixed-point atomic
 
@@ -66,7 +66,8 @@ def work_per_history(stats, n):
     # (or is absorbed/cut at a collision); in-box flights = flights - escapes
     escapes = (stats["classes"]["primary"] + stats["classes"]["scatter"] + stats["classes"]["missed"]) / h
     inbox = max(flights - escapes, 0.0)
-    slots = (inbox * SLOTS_FLIGHT_IN + escapes * SLOTS_FLIGHT_OUT + tries * SLOTS_TRY
+    pairs = 0.5 * (flights + real)                     # a real collision ends a pair early
+    slots = (pairs * SLOTS_PHILOX + inbox * SLOTS_FLIGHT_IN + escapes * SLOTS_FLIGHT_OUT + tries * SLOTS_TRY
              + real * 6 + scatter_events * (SLOTS_COLLISION - 6) + SLOTS_SOURCE)
     nbytes = inbox * BYTES_FLIGHT_IN + BYTES_SOURCE + scored * BYTES_SCORE
     return dict(slots=slots, bytes=nbytes, flights=flights, inbox_flights=inbox, real=real, tries=tries)

@@ -121,10 +121,13 @@ typedef struct gdrr_job {
 
 /* Launch shape of the persistent kernel (0 = library default). */
 typedef struct gdrr_tuning {
-    int32_t block;             /* threads per workgroup: 64, 128, 256 or 512 */
+    int32_t block;             /* threads per workgroup: a multiple of 64 up to 1024 */
     int32_t blocks_per_cu;     /* workgroups per compute unit */
-    int32_t chunk;             /* photons handed to a wavefront at a time (multiple of 64) */
-    int32_t defer;             /* interactions/refills are served when >= defer lanes wait (1..64) */
+    int32_t chunk;             /* photons handed out at a time (multiple of 64) */
+    int32_t defer;             /* scheme 1: interactions/refills run when >= defer lanes wait (1..64) */
+    int32_t scheme;            /* 1: each lane keeps its photon through interactions; 2: photons at a
+                                  real collision move to a workgroup queue in LDS and interactions and
+                                  source sampling run on packed lanes; results are identical */
 } gdrr_tuning;
 
 /*

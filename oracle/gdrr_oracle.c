@@ -351,11 +351,13 @@ int or_majorant_margin(const or_problem* p, int32_t interp, double margin, doubl
 /* ------------------------------------------------------------------------ */
 /* Random-number layout: block (photon i, job, step, sub) under key = seed.  */
 /* step 0 = source (sub 0: energy and pixel, sub 1: position in the pixel).  */
-/* Free flight k >= 1 takes two words of block (i, job, (k+1)/2, 0): words   */
-/* 0 and 1 for odd k, words 2 and 3 for even k -- the first for the flight   */
-/* length, the second for the collision "ladder".  The t-th try of the       */
-/* angular sampler at flight k uses block (i, job, k, 1 + t); its word 3 is   */
-/* the azimuth if that try is accepted.                                      */
+/* Free flights come in pairs: pair p takes block (i, job, p, 0), words 0-1 */
+/* for its first flight and words 2-3 for its second -- each time one word   */
+/* for the flight length and one for the collision "ladder".  A real         */
+/* collision ends the pair (its unused words are discarded), so the next     */
+/* flight opens pair p + 1.  The t-th try of the angular sampler at the k-th */
+/* flight of the history uses block (i, job, k, 1 + t); its word 3 is the    */
+/* azimuth if that try is accepted.                                          */
 /* ------------------------------------------------------------------------ */
 static void rblock(const or_ctx* c, uint32_t i, uint32_t step, uint32_t sub, uint32_t x[4])
 {
@@ -515,11 +517,14 @@ static void history(const or_problem* p, const or_ctx* c, uint32_t i, or_outcome
         for (int a = 0; a < 3; ++a) pos[a] += tin * dir[a];
         double trem = tout - tin;
         uint32_t fb[4] = {0, 0, 0, 0};
+        uint32_t pair = 0;
+        int half = 2;                                         /* 2: the next flight opens a pair */
         for (uint32_t step = 1;; ++step) {
             if (step > OR_MAX_STEPS) { o->cls = OR_LOST; o->pixel = -1; o->e_final = E; return; }
             o->steps = (int)step;
-            if (step & 1u) rblock(c, i, (step + 1) / 2, 0, fb);
-            double r0 = u24(fb[(step & 1u) ? 0 : 2]), r1 = u24(fb[(step & 1u) ? 1 : 3]);
+            if (half == 2) { ++pair; rblock(c, i, pair, 0, fb); half = 0; }
+            double r0 = u24(fb[2 * half]), r1 = u24(fb[2 * half + 1]);
+            ++half;
             double f;
             int j = e_interval(p, E, &f);
             double mbar = c->mbar[j];
@@ -545,6 +550,7 @@ static void history(const or_problem* p, const or_ctx* c, uint32_t i, or_outcome
             if (vis) visit(p, c, vis, pos, real, rho, tot, mbar);
             if (!real) continue;                              /* null collision */
             o->n_real++;
+            half = 2;                                         /* a real collision ends the pair */
             double cost, az = 0.0;
             if (ladder < rho * mu3[0]) {                      /* Rayleigh: E unchanged */
                 cost = rayleigh(c, i, step, E, p->x0_rayleigh, &az, &o->tries);

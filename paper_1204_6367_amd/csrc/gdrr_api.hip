@@ -11,6 +11,7 @@
 
 #include "gdrr.h"
 #include "gdrr_kernels.h"
+#include "gdrr_queue.h"
 
 using namespace gdrr;
 
@@ -375,12 +376,21 @@ int check_batch(const Batch& B) {
         if (t.chunk && (t.chunk % 64 || t.chunk < 64)) return fail(GDRR_EINVAL, "tune.chunk must be a positive multiple of 64");
         if (t.defer < 0 || t.defer > 64) return fail(GDRR_EINVAL, "tune.defer must be in [0, 64]");
         if (t.blocks_per_cu < 0 || t.blocks_per_cu > 64) return fail(GDRR_EINVAL, "tune.blocks_per_cu must be in [0, 64]");
+        if (t.scheme < 0 || t.scheme > 2) return fail(GDRR_EINVAL, "tune.scheme must be 0, 1 or 2");
     }
     return GDRR_OK;
 }
 
 template <int MODE>
-const void* mc_func() { return reinterpret_cast<const void*>(&mc_kernel<MODE>); }
+const void* mc_func(int scheme) {
+    return scheme == 2 ? reinterpret_cast<const void*>(&mc_queue_kernel<MODE>)
+                       : reinterpret_cast<const void*>(&mc_kernel<MODE>);
+}
+
+const void* mc_func_for(int mode, int scheme) {
+    return mode == kModeForward ? mc_func<kModeForward>(scheme)
+         : mode == kModeTrace ? mc_func<kModeTrace>(scheme) : mc_func<kModeBackward>(scheme);
+}
 
 int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     int rc = check_batch(B);
@@ -403,13 +413,14 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     unsigned long long total_photons = 0;
     for (int k = 0; k < B.n_jobs; ++k)
         if (B.only_volume < 0 || B.jobs[k].volume == B.only_volume) total_photons += B.jobs[k].n_photons;
-    const int block = tune.block ? tune.block : 256;
-    const size_t lds = lds_bytes(phys->n_mat, phys->n_e, B.n_vols, phys->response != nullptr);
-    if (lds > dev.lds_max) return fail(GDRR_ENOTSUP, "tables exceed the LDS of a workgroup");
+    const int scheme = tune.scheme ? tune.scheme : 1;
+    const int block = tune.block ? tune.block : (scheme == 2 ? 512 : 256);
+    const size_t lds = scheme == 2 ? queue_lds_bytes(phys->n_mat, phys->n_e, B.n_vols, phys->response != nullptr, block)
+                                   : lds_bytes(phys->n_mat, phys->n_e, B.n_vols, phys->response != nullptr);
+    if (lds > dev.lds_max) return fail(GDRR_ENOTSUP, "tables and queues exceed the LDS of a workgroup");
     int per_cu = tune.blocks_per_cu;
     if (!per_cu) {
-        const void* f = B.mode == kModeForward ? mc_func<kModeForward>()
-                      : B.mode == kModeTrace ? mc_func<kModeTrace>() : mc_func<kModeBackward>();
+        const void* f = mc_func_for(B.mode, scheme);
         int nb = 0;
         GDRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, block, lds));
         per_cu = std::max(nb, 1);
@@ -585,8 +596,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     kp.t_steps = B.t_steps; kp.t_nc = B.t_nc; kp.t_nr = B.t_nr;
     kp.adj = B.adj;
     kp.grad = B.grad;
-    const void* mf = B.mode == kModeForward ? mc_func<kModeForward>()
-                   : B.mode == kModeTrace ? mc_func<kModeTrace>() : mc_func<kModeBackward>();
+    const void* mf = mc_func_for(B.mode, scheme);
     int timed = -1;
     if (chunks > 0) {
         timed = (int)ls.size();
@@ -667,6 +677,7 @@ int gdrr_default_tuning(gdrr_tuning* out) {
     out->blocks_per_cu = 0;
     out->chunk = 0;
     out->defer = 32;
+    out->scheme = 1;
     return GDRR_OK;
 }
 

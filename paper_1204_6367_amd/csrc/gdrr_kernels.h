@@ -169,7 +169,7 @@ struct Photon {
     int st;
     bool passb;                // adjoint: second (visiting) pass
     ECache ec;
-    uint32_t rz, rw;           // second half of the flight block: the next (even) flight's words
+    uint32_t pair;             // flight pairs opened so far (Philox step of the flight block)
     float sel;                 // pending collision: ladder / rho, compared with mu_R and mu_R + mu_C
     int pm;                    // pending collision: material
     float w;                   // adjoint weight of the history
@@ -199,6 +199,7 @@ __device__ __forceinline__ bool start_photon(const KParams& P, const Tables& T, 
     ph.E = fminf(fmaxf(S.spec_e[ke], P.e0), P.e_max);
     ph.ec = energy_cache(P, T, vol_off, ph.E);
     ph.step = 0;
+    ph.pair = 0;
     ph.nsc = 0;
     ph.pix0 = kf;
     float tin, tout;
@@ -304,10 +305,82 @@ __device__ __forceinline__ void visit(const KParams& P, const DVolume& V, bool i
     }
 }
 
+// One Woodcock free flight with uniforms (ra, rb): flight length -ln(u)/mbar,
+// then the collision ladder.  Returns true after a null collision (the photon
+// flies on); escape, a real collision or the step limit return false.
 template <int MODE>
-__global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
-    extern __shared__ float2 lds[];
-    // ---- stage the per-launch tables in LDS ----
+__device__ __forceinline__ bool flight(const KParams& P, const Tables& T, const DVolume& V, int vo, bool interp,
+                                       Photon& ph, uint32_t ra, uint32_t rb) {
+    if (ph.step >= kMaxSteps) {                          // step limit: the history is lost
+        if (MODE == kModeTrace) trace_out<MODE>(P, ph, kLost, -1);
+        ph.st = kDead;
+        return false;
+    }
+    ph.step += 1;
+    const float s = -fast_log(u24(ra)) * ph.ec.mfp;
+    if (!(s < ph.trem)) {
+        int pixel;
+        const int cls = detector_pixel(P.jobs[ph.job], ph, pixel);
+        finish<MODE>(P, T, V, vo, ph, cls, pixel);
+        return false;
+    }
+    ph.px += s * ph.dx;
+    ph.py += s * ph.dy;
+    ph.pz += s * ph.dz;
+    ph.trem -= s;
+    int m;
+    const float rho = cell_density(V, interp, ph.px, ph.py, ph.pz, m);
+    m = m < P.n_mat ? m : P.n_mat - 1;
+    const float2 tt = T.tot[m * P.n_e + ph.ec.j];
+    const float tot = tt.x + ph.ec.f * tt.y;
+    // one uniform on [0, mbar): real below mu = rho tot, then the type ladder
+    const float ladder = u24(rb) * ph.ec.mbar;
+    const bool real = ladder < rho * tot;
+    if (MODE == kModeBackward && ph.passb) visit(P, V, interp, ph, real, rho, tot, ph.ec.mbar);
+    if (real) {
+        ph.st = kColl;
+        ph.sel = ladder * fast_rcp(rho);
+        ph.pm = m;
+        return false;
+    }
+    return true;
+}
+
+// A real collision (Sec. 2.4): the ladder value picks Rayleigh, Compton or
+// photoelectric absorption; scattering samples the angle, updates energy and
+// direction and the distance to the phantom's boundary.
+template <int MODE>
+__device__ __forceinline__ void collide(const KParams& P, const Tables& T, const DVolume& V, int vo, Photon& ph) {
+    const int m = ph.pm;
+    const float* a = P.mu_mass + ((size_t)m * P.n_e + ph.ec.j) * 3;   // j <= n_e - 2
+    const float R = a[0] + ph.ec.f * (a[3] - a[0]);
+    const float C = a[1] + ph.ec.f * (a[4] - a[1]);
+    const float sel = ph.sel;
+    float ct, az = 0.0f;
+    if (sel < R) {
+        ct = rayleigh(ph.pid, ph.jid, ph.step, P.k0, P.k1, ph.E, P.x0, az);
+        ph.nsc += 1u << 16;
+    } else if (sel < R + C) {
+        ct = compton(ph.pid, ph.jid, ph.step, P.k0, P.k1, ph.E, az);
+        ph.nsc += 1u;
+        ph.ec = energy_cache(P, T, vo, ph.E);
+    } else {
+        if (MODE == kModeTrace) trace_out<MODE>(P, ph, kAbsorbed, -1);
+        ph.st = kDead;
+        return;
+    }
+    rotate(ph.dx, ph.dy, ph.dz, ct, az);
+    if (ph.E < P.e_cut) {
+        if (MODE == kModeTrace) trace_out<MODE>(P, ph, kCut, -1);
+        ph.st = kDead;
+        return;
+    }
+    ph.trem = box_exit(V, ph.px, ph.py, ph.pz, ph.dx, ph.dy, ph.dz);
+    ph.st = kFly;
+}
+
+// Copies the per-launch tables into LDS (all threads of the workgroup).
+__device__ __forceinline__ Tables stage_tables(const KParams& P, float2* lds) {
     float2* s_tot = lds;
     float2* s_maj = s_tot + P.n_mat * P.n_e;
     float2* s_resp = s_maj + P.n_vols * (P.n_e - 1);
@@ -327,8 +400,18 @@ __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
             const float r0 = P.response[i], r1 = P.response[i + 1 < P.n_e ? i + 1 : i];
             s_resp[i] = make_float2(r0, r1 - r0);
         }
+    return Tables{s_tot, s_maj, s_resp};
+}
+
+__host__ __device__ inline size_t table_floats2(int n_mat, int n_e, int n_vols, bool resp) {
+    return (size_t)n_mat * n_e + (size_t)n_vols * (n_e - 1) + (resp ? (size_t)n_e : 0);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
+    extern __shared__ float2 lds[];
+    const Tables T = stage_tables(P, lds);
     __syncthreads();
-    const Tables T{s_tot, s_maj, s_resp};
     const bool interp = (P.flags & 1u) != 0;
     const int lane = __lane_id();
     const uint64_t lt = (1ull << lane) - 1ull;
@@ -342,7 +425,7 @@ __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
     ph.jid = 0;
     ph.nsc = 0;
     ph.sel = 0.0f;
-    ph.rz = ph.rw = 0u;
+    ph.pair = 0u;
     ph.pm = 0;
 
     // wavefront-uniform dispenser state
@@ -408,82 +491,19 @@ __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
         const int vo = V.lds_majorant;
 
         // ---- flight: one Woodcock step (Sec. 2.4) ----
-        if (ph.st == kFly && ph.step >= kMaxSteps) {          // step limit: the history is lost
-            if (MODE == kModeTrace) trace_out<MODE>(P, ph, kLost, -1);
-            ph.st = kDead;
-        }
+        // Free flights in pairs (Sec. 2.4): one Philox block per pair, two words per
+        // flight; a null collision continues the pair, a real one ends it.
         if (ph.st == kFly) {
-            ph.step += 1;
-            uint32_t ra, rb;           // flight k: words 0,1 (k odd) or 2,3 (k even) of block (k+1)/2
-            if (ph.step & 1u) {
-                const Block b = philox(ph.pid, ph.jid, (ph.step + 1u) >> 1, 0u, P.k0, P.k1);
-                ra = b.x; rb = b.y; ph.rz = b.z; ph.rw = b.w;
-            } else {
-                ra = ph.rz; rb = ph.rw;
-            }
-            const float s = -fast_log(u24(ra)) * ph.ec.mfp;
-            if (!(s < ph.trem)) {
-                int pixel;
-                const int cls = detector_pixel(P.jobs[ph.job], ph, pixel);
-                finish<MODE>(P, T, V, vo, ph, cls, pixel);
-            } else {
-                ph.px += s * ph.dx;
-                ph.py += s * ph.dy;
-                ph.pz += s * ph.dz;
-                ph.trem -= s;
-                int m;
-                const float rho = cell_density(V, interp, ph.px, ph.py, ph.pz, m);
-                m = m < P.n_mat ? m : P.n_mat - 1;
-                const float2 tt = T.tot[m * P.n_e + ph.ec.j];
-                const float tot = tt.x + ph.ec.f * tt.y;
-                // one uniform on [0, mbar): real below mu = rho tot, then the type ladder
-                const float ladder = u24(rb) * ph.ec.mbar;
-                const bool real = ladder < rho * tot;
-                if (MODE == kModeBackward && ph.passb) visit(P, V, interp, ph, real, rho, tot, ph.ec.mbar);
-                if (real) {
-                    ph.st = kColl;
-                    ph.sel = ladder * fast_rcp(rho);
-                    ph.pm = m;
-                }
-            }
+            ph.pair += 1u;
+            const Block b = philox(ph.pid, ph.jid, ph.pair, 0u, P.k0, P.k1);
+            if (flight<MODE>(P, T, V, vo, interp, ph, b.x, b.y)) flight<MODE>(P, T, V, vo, interp, ph, b.z, b.w);
         }
 
         // ---- collision: interaction type and sampling ----
         const int n_coll2 = __popcll(__ballot(ph.st == kColl));
         const int n_fly2 = __popcll(__ballot(ph.st == kFly));
         if (n_coll2 > 0 && (n_coll2 >= P.defer || n_fly2 == 0 || w_done || w_hold)) {
-            if (ph.st == kColl) {
-                const int m = ph.pm;
-                const float* a = P.mu_mass + ((size_t)m * P.n_e + ph.ec.j) * 3;   // j <= n_e - 2
-                const float R = a[0] + ph.ec.f * (a[3] - a[0]);
-                const float C = a[1] + ph.ec.f * (a[4] - a[1]);
-                const float sel = ph.sel;
-                float ct, az = 0.0f;
-                bool alive = true;
-                if (sel < R) {
-                    ct = rayleigh(ph.pid, ph.jid, ph.step, P.k0, P.k1, ph.E, P.x0, az);
-                    ph.nsc += 1u << 16;
-                } else if (sel < R + C) {
-                    ct = compton(ph.pid, ph.jid, ph.step, P.k0, P.k1, ph.E, az);
-                    ph.nsc += 1u;
-                    ph.ec = energy_cache(P, T, vo, ph.E);
-                } else {
-                    ct = 1.0f;
-                    alive = false;
-                    if (MODE == kModeTrace) trace_out<MODE>(P, ph, kAbsorbed, -1);
-                    ph.st = kDead;
-                }
-                if (alive) {
-                    rotate(ph.dx, ph.dy, ph.dz, ct, az);
-                    if (ph.E < P.e_cut) {
-                        if (MODE == kModeTrace) trace_out<MODE>(P, ph, kCut, -1);
-                        ph.st = kDead;
-                    } else {
-                        ph.trem = box_exit(V, ph.px, ph.py, ph.pz, ph.dx, ph.dy, ph.dz);
-                        ph.st = kFly;
-                    }
-                }
-            }
+            if (ph.st == kColl) collide<MODE>(P, T, V, vo, ph);
         }
     }
 }

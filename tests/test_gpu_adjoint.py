@@ -59,6 +59,21 @@ def test_adjoint_matches_oracle(gpu, interp):
     assert rel <= 0.02
 
 
+def test_adjoint_schemes_agree(gpu):
+    """The workgroup-queue scheme replays the same histories: same gradient up to
+    the order of float64 atomic additions."""
+    import torch
+    prob = small_problem(seed=25)
+    vol, phys, src = gpu.upload(prob)
+    g = prob.geom
+    adj = torch.tensor(np.random.default_rng(8).normal(size=(1, 2, g.nv, g.nu)), device="cuda")
+    b = gpu.Batch([vol], phys, [src], [gpu.JobSpec(g, 300_000, 0)])
+    maj = gpu.majorant(vol, phys, True, margin=0.2)[None]
+    g1 = b.backward(adj, maj, seed=2, tune=dict(scheme=1))
+    g2 = b.backward(adj, maj, seed=2, tune=dict(scheme=2))
+    assert torch.allclose(g1, g2, rtol=1e-9, atol=1e-15 * float(g1.abs().max()))
+
+
 def test_adjoint_of_linear_loss_matches_crn_finite_differences(gpu):
     """L = sum_p a_p S_p: the adjoint and CRN central differences estimate the
     same derivative; compared over replicas (seeds) on 16 voxels."""
