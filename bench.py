@@ -77,6 +77,31 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_sources_sha() -> str:
+    """Hash of the HIP sources: measured traffic is valid only for this kernel."""
+    import hashlib
+    h = hashlib.sha1()
+    d = os.path.join(ROOT, "paper_1204_6367_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(path, workload):
+    """HBM bytes per transport launch from rocprofv3 FETCH_SIZE + WRITE_SIZE
+    (scaled by the copy calibration), if they were taken on this kernel."""
+    if not path or not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(workload)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel_sha") != kernel_sources_sha():
+        return None
+    return round(rec["fetch_bytes"] + rec["write_bytes"], 0)
+
+
 TUNE_MODE = "auto"
 
 
@@ -259,7 +284,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tune", default="auto", choices=["auto", "default"],
                     help="auto: autotune the launch shape before timing; default: library defaults")
-    ap.add_argument("--traffic", default=None, help="JSON file with measured HBM bytes per transport launch")
+    ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
+                    help="JSON with measured HBM bytes per transport launch (used if taken on this kernel)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a device-to-device copy of MIB MiB (reference for the HBM byte counters)")
     args = ap.parse_args()
@@ -314,9 +340,7 @@ def main():
         nbytes = w["bytes"] * wl["fwd"]
         alu_ach = slots / (fwd_ms * 1e-3) / 1e12
         hbm_ach = nbytes / (fwd_ms * 1e-3) / 1e9
-        traffic = None
-        if args.traffic and os.path.exists(args.traffic):
-            traffic = json.load(open(args.traffic)).get(args.workload)
+        traffic = measured_traffic(args.traffic, args.workload)
         alu = dict(bound="alu", achieved=round(alu_ach, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Tops/s",
                    frac=round(alu_ach / ALU_PEAK_TOPS, 4), traffic=traffic)
         hbm = dict(bound="hbm", achieved=round(hbm_ach, 1), peak=HBM_PEAK_GBS, unit="GB/s",
