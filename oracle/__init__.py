@@ -70,6 +70,7 @@ def lib():
         L.or_rho_integrals.argtypes = [P, i32, vp, vp, vp]
         L.or_mc_histories.argtypes = [P, u64, C.c_uint32, i32, vp, vp, C.c_int64, vp, vp, vp, vp, vp, vp, i32]
         L.or_primary_exact.argtypes = [P, i32, i32, vp]
+        L.or_primary_raytrace.argtypes = [P, i32, C.c_double, vp, C.c_int64, vp]
         L.or_rho_integrals_many.argtypes = [P, i32, vp, vp, C.c_int64, vp]
         L.or_sample_compton.argtypes = [C.c_double, u64, u64, vp, vp]
         L.or_sample_rayleigh.argtypes = [C.c_double, C.c_double, u64, u64, vp]
@@ -228,6 +229,22 @@ def primary_exact(p: Problem, interp: bool = True, nq: int = 8) -> np.ndarray:
     out = np.zeros((p.nv, p.nu), np.float64)
     if lib().or_primary_exact(p.ref, int(interp), nq, _ptr(out)):
         raise ValueError("oracle primary_exact: invalid input")
+    return out
+
+
+def primary_raytrace(p: Problem, interp: bool = True, dl: float = 0.0, pixels=None) -> np.ndarray:
+    """Eq. 1 by ray tracing (Sec. 2.3): per pixel, per source photon.  `dl` in
+    mm (<= 0: half the smallest voxel edge).  `pixels`: flat indices iv*nu+iu
+    (returns [m]), or None for the whole detector ([nv][nu])."""
+    if pixels is None:
+        out = np.zeros((p.nv, p.nu), np.float64)
+        rc = lib().or_primary_raytrace(p.ref, int(interp), float(dl), None, 0, _ptr(out))
+    else:
+        px = np.ascontiguousarray(pixels, np.int32).ravel()
+        out = np.zeros(px.size, np.float64)
+        rc = lib().or_primary_raytrace(p.ref, int(interp), float(dl), _ptr(px), px.size, _ptr(out))
+    if rc:
+        raise ValueError("oracle primary_raytrace: invalid input")
     return out
 
 

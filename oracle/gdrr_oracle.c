@@ -16,8 +16,10 @@
  *             tables mu_k(i,E) (k = Rayleigh, Compton, photoelectric), the
  *             spectrum phi(E) and fluence map w(u) as normalised pdfs, and the
  *             detector response r(E).
- *   Sec. 2.3  Eq. 1 (Beer-Lambert primary), evaluated here *exactly* for the
- *             trilinear / voxel-constant density model as a check of the MC.
+ *   Sec. 2.3  Eq. 1 (Beer-Lambert primary): the ray-tracing sum over
+ *             intervals of length dl with trilinearly interpolated attenuation
+ *             at their midpoints, and, as a check of the MC, the same
+ *             integral evaluated exactly for the MC's density model.
  *   Sec. 2.4  the MC: one history at a time -- source photon from spectrum and
  *             fluence map, Woodcock (delta) tracking, photoelectric absorption
  *             terminates, Compton and Rayleigh angles from their differential
@@ -1022,5 +1024,113 @@ int or_rho_integrals_many(const or_problem* p, int32_t interp, const double* a, 
 #endif
     for (int64_t k = 0; k < m; ++k)
         bad |= or_rho_integrals(p, interp, a, b + 3 * k, out + (size_t)k * p->n_mat) != 0;
+    return bad ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Primary signal by ray tracing, Sec. 2.3, Eq. 1:                           */
+/*   P(u) = sum_k phi_k w(u) r(E_k) exp(-sum_j dl_j mu(x_j, E_k))            */
+/* over the spectrum's energy channels.  The ray runs from the source to the */
+/* centre of pixel u.  Its length from the source is cut into intervals     */
+/* [j dl, (j+1) dl); the part of each interval inside the phantom box is     */
+/* one term, with mu taken at that part's midpoint (all terms have length dl */
+/* except the two cut by the box faces).  mu(x, E) is the trilinear          */
+/* interpolation of the voxel attenuation coefficients rho_v mu_tot(m_v, E)  */
+/* on the lattice of voxel centres (clamped at the edges); with the          */
+/* interpolation off it is the containing voxel's value.  dl <= 0 selects    */
+/* half of the smallest voxel edge.  phi and w are normalised to sum 1.      */
+/* Pixels: the m indices iv * nu + iu in pix, or all pixels when pix is      */
+/* NULL (out is then [nv][nu]).                                              */
+/* ------------------------------------------------------------------------ */
+int or_primary_raytrace(const or_problem* p, int32_t interp, double dl, const int32_t* pix, int64_t m,
+                        double* out)
+{
+    if (validate(p)) return -1;
+    const int64_t npx = pix ? m : (int64_t)p->nu * p->nv;
+    if (pix)
+        for (int64_t q = 0; q < m; ++q)
+            if (pix[q] < 0 || pix[q] >= p->nu * p->nv) return -1;
+    for (size_t v = 0; v < (size_t)p->nx * p->ny * p->nz; ++v)
+        if (p->material[v] >= p->n_mat) return -1;
+    if (!(dl > 0.0)) {
+        dl = p->dx;
+        if (p->dy < dl) dl = p->dy;
+        if (p->dz < dl) dl = p->dz;
+        dl *= 0.5;
+    }
+    or_ctx c;
+    memset(&c, 0, sizeof(c));
+    setup_geometry(p, &c);
+    double sp = 0.0, sf = 0.0;
+    for (int k = 0; k < p->n_spec; ++k) sp += p->spec_p[k];
+    for (int k = 0; k < p->nu * p->nv; ++k) sf += p->fluence[k];
+    if (!(sp > 0.0) || !(sf > 0.0)) return -1;
+    /* total mass attenuation of every material at every channel energy */
+    double* mut = (double*)malloc(sizeof(double) * (size_t)p->n_spec * p->n_mat);
+    if (!mut) return -1;
+    for (int k = 0; k < p->n_spec; ++k)
+        for (int mm = 0; mm < p->n_mat; ++mm) {
+            double mu3[3];
+            xs_at(p, mm, p->spec_e[k], mu3);
+            mut[(size_t)k * p->n_mat + mm] = mu3[0] + mu3[1] + mu3[2];
+        }
+    int bad = 0;
+#ifdef _OPENMP
+#pragma omp parallel reduction(|:bad)
+#endif
+    {
+        double* L = (double*)malloc(sizeof(double) * (size_t)p->n_spec);
+        if (!L) bad = 1;
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 16)
+#endif
+        for (int64_t q = 0; q < npx; ++q) {
+            if (!L) continue;
+            const int id = pix ? pix[q] : (int)q;
+            const int iu = id % p->nu, iv = id / p->nu;
+            const double uc = ((double)iu + 0.5 - 0.5 * p->nu) * p->du;
+            const double vc = ((double)iv + 0.5 - 0.5 * p->nv) * p->dv;
+            double d[3];
+            for (int a = 0; a < 3; ++a) d[a] = c.P[a] + uc * c.eu[a] + vc * c.ev[a] - c.S[a];
+            const double len = sqrt(dot3(d, d));
+            for (int a = 0; a < 3; ++a) d[a] /= len;
+            for (int k = 0; k < p->n_spec; ++k) L[k] = 0.0;
+            double tin, tout;
+            if (box_entry(&c, c.S, d, &tin, &tout)) {
+                if (tout > len) tout = len;
+                const int64_t j0 = (int64_t)floor(tin / dl), j1 = (int64_t)ceil(tout / dl);
+                for (int64_t j = j0; j < j1; ++j) {
+                    double a = (double)j * dl, b = (double)(j + 1) * dl;
+                    if (a < tin) a = tin;
+                    if (b > tout) b = tout;
+                    if (!(b > a)) continue;
+                    double x[3];
+                    for (int r = 0; r < 3; ++r) x[r] = c.S[r] + 0.5 * (a + b) * d[r];
+                    if (interp) {
+                        size_t vox[8];
+                        double wt[8];
+                        trilinear(p, &c, x, vox, wt);
+                        for (int k = 0; k < p->n_spec; ++k) {
+                            double mu = 0.0;
+                            for (int s = 0; s < 8; ++s)
+                                mu += wt[s] * (double)p->density[vox[s]] *
+                                      mut[(size_t)k * p->n_mat + p->material[vox[s]]];
+                            L[k] += (b - a) * mu;
+                        }
+                    } else {
+                        const size_t v = containing_voxel(p, &c, x);
+                        for (int k = 0; k < p->n_spec; ++k)
+                            L[k] += (b - a) * (double)p->density[v] * mut[(size_t)k * p->n_mat + p->material[v]];
+                    }
+                }
+            }
+            double acc = 0.0;
+            for (int k = 0; k < p->n_spec; ++k)       /* mm * 1/cm -> 0.1 */
+                acc += (p->spec_p[k] / sp) * response_at(p, p->spec_e[k]) * exp(-0.1 * L[k]);
+            out[q] = ((double)p->fluence[id] / sf) * acc;
+        }
+        free(L);
+    }
+    free(mut);
     return bad ? -1 : 0;
 }
