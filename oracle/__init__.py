@@ -71,6 +71,10 @@ def lib():
         L.or_mc_histories.argtypes = [P, u64, C.c_uint32, i32, vp, vp, C.c_int64, vp, vp, vp, vp, vp, vp, i32]
         L.or_primary_exact.argtypes = [P, i32, i32, vp]
         L.or_primary_raytrace.argtypes = [P, i32, C.c_double, vp, C.c_int64, vp]
+        L.or_denoise.argtypes = [vp, vp, i32, i32, i32, C.c_double, C.c_double, i32, C.c_double, vp]
+        L.or_noise.argtypes = [C.c_int64, vp, vp, vp, vp, C.c_double, vp, vp]
+        L.or_noise_scale.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.or_noise_scale.restype = C.c_double
         L.or_rho_integrals_many.argtypes = [P, i32, vp, vp, C.c_int64, vp]
         L.or_sample_compton.argtypes = [C.c_double, u64, u64, vp, vp]
         L.or_sample_rayleigh.argtypes = [C.c_double, C.c_double, u64, u64, vp]
@@ -246,6 +250,36 @@ def primary_raytrace(p: Problem, interp: bool = True, dl: float = 0.0, pixels=No
     if rc:
         raise ValueError("oracle primary_raytrace: invalid input")
     return out
+
+
+def denoise(shat, beta: float, iters: int, omega: float = 0.8, s_floor: float = 1e-12, s0=None) -> np.ndarray:
+    """Eq. 5 (Sec. 2.5) on [nv][nu] or [n][nv][nu] images; S^(0) = Shat unless s0 is given."""
+    h = np.ascontiguousarray(shat, np.float64)
+    shape = h.shape
+    h3 = h.reshape((-1,) + shape[-2:])
+    g = None if s0 is None else np.ascontiguousarray(s0, np.float64).reshape(h3.shape)
+    out = np.zeros_like(h3)
+    if lib().or_denoise(_ptr(h3), _ptr(g), h3.shape[0], h3.shape[1], h3.shape[2], float(beta), float(omega),
+                        int(iters), float(s_floor), _ptr(out)):
+        raise ValueError("oracle denoise: invalid input")
+    return out.reshape(shape)
+
+
+def noise_scale(n_sim: float, zeta: float, mas: float) -> float:
+    a = lib().or_noise_scale(float(n_sim), float(zeta), float(mas))
+    if a < 0:
+        raise ValueError("oracle noise_scale: invalid input")
+    return a
+
+
+def noise(phat, p, shat, s, alpha: float):
+    """Sec. 2.6: (N, P + S + N) with N = alpha ((Phat - P) + (Shat - S))."""
+    arrs = [np.ascontiguousarray(x, np.float64) for x in (phat, p, shat, s)]
+    n_out = np.zeros_like(arrs[0])
+    img = np.zeros_like(arrs[0])
+    if lib().or_noise(arrs[0].size, *map(_ptr, arrs), float(alpha), _ptr(n_out), _ptr(img)):
+        raise ValueError("oracle noise: invalid input")
+    return n_out, img
 
 
 def sample_compton(e_kev: float, seed: int, n: int):

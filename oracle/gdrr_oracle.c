@@ -1134,3 +1134,75 @@ int or_primary_raytrace(const or_problem* p, int32_t interp, double dl, const in
     free(mut);
     return bad ? -1 : 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Scatter denoising, Sec. 2.5: the iteration of Eq. 5,                      */
+/*   S'(i,j) = (1 - w) S(i,j) + (w/4) [sum of the 4 neighbours of S(i,j)     */
+/*             - (1/beta) (1 - Shat(i,j) / S(i,j))],                         */
+/* with every value on the right taken from the previous iterate and         */
+/* S^(0) = Shat.  At the detector edge a missing neighbour takes the pixel's */
+/* own value (no flux through the edge, the boundary condition under which   */
+/* Eq. 4 is the optimality condition of the discretised Eq. 2).  The data    */
+/* term is 1 where Shat = 0; iterates are kept at or above s_floor > 0 so    */
+/* that Shat / S stays defined.  images: [n_img][nv][nu]; s0 may be NULL     */
+/* (then S^(0) = Shat).                                                      */
+/* ------------------------------------------------------------------------ */
+int or_denoise(const double* shat, const double* s0, int32_t n_img, int32_t nv, int32_t nu, double beta,
+               double omega, int32_t iters, double s_floor, double* out)
+{
+    if (!shat || !out || n_img < 1 || nv < 1 || nu < 1 || !(beta > 0.0) || !(s_floor > 0.0) || iters < 0)
+        return -1;
+    const size_t npx = (size_t)nv * nu;
+    double* a = (double*)malloc(sizeof(double) * npx);
+    double* b = (double*)malloc(sizeof(double) * npx);
+    if (!a || !b) { free(a); free(b); return -1; }
+    for (int32_t m = 0; m < n_img; ++m) {
+        const double* h = shat + (size_t)m * npx;
+        const double* g = s0 ? s0 + (size_t)m * npx : h;
+        for (size_t k = 0; k < npx; ++k) a[k] = g[k] > s_floor ? g[k] : s_floor;
+        for (int32_t it = 0; it < iters; ++it) {
+            for (int32_t i = 0; i < nv; ++i)
+                for (int32_t j = 0; j < nu; ++j) {
+                    const double s = a[(size_t)i * nu + j];
+                    const double up = i > 0 ? a[(size_t)(i - 1) * nu + j] : s;
+                    const double dn = i + 1 < nv ? a[(size_t)(i + 1) * nu + j] : s;
+                    const double lf = j > 0 ? a[(size_t)i * nu + j - 1] : s;
+                    const double rt = j + 1 < nu ? a[(size_t)i * nu + j + 1] : s;
+                    const double hk = h[(size_t)i * nu + j];
+                    const double data = hk == 0.0 ? 1.0 : 1.0 - hk / s;
+                    double v = (1.0 - omega) * s + 0.25 * omega * ((up + dn + lf + rt) - data / beta);
+                    b[(size_t)i * nu + j] = v > s_floor ? v : s_floor;
+                }
+            double* t = a; a = b; b = t;
+        }
+        memcpy(out + (size_t)m * npx, a, sizeof(double) * npx);
+    }
+    free(a); free(b);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Noise assembly, Sec. 2.6: the MC noise Nhat = (Phat - P) + (Shat - S)     */
+/* (the second Eq. 4), scaled by alpha = sqrt(n_sim / (zeta I)) (the second  */
+/* Eq. 5) to the noise of a scan at I mAs: N = alpha Nhat; the simulated     */
+/* projection is P + S + N.  Either output may be NULL.                      */
+/* ------------------------------------------------------------------------ */
+int or_noise(int64_t n, const double* phat, const double* p, const double* shat, const double* s, double alpha,
+             double* noise, double* image)
+{
+    if (n < 0 || !phat || !p || !shat || !s) return -1;
+    for (int64_t k = 0; k < n; ++k) {
+        const double nn = alpha * ((phat[k] - p[k]) + (shat[k] - s[k]));
+        if (noise) noise[k] = nn;
+        if (image) image[k] = p[k] + s[k] + nn;
+    }
+    return 0;
+}
+
+/* Sec. 2.6, second Eq. 5: alpha = sqrt(n_sim / (zeta I)), I the mAs level and
+ * zeta the effective source photons per mAs. */
+double or_noise_scale(double n_sim, double zeta, double mas)
+{
+    if (!(n_sim > 0.0) || !(zeta > 0.0) || !(mas > 0.0)) return -1.0;
+    return sqrt(n_sim / (zeta * mas));
+}
