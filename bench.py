@@ -8,7 +8,9 @@ scoring and finalisation, and (for workloads with a loss) the path-replay
 adjoint.  Inputs are resident in HBM before the timed region.  Prints ONE
 JSON line with the whole-step histories/s, the roofline of the transport
 kernel (timed with HIP events on its own stream, inside the library) and the
-CPU oracle timed on a bounded sample of the same workload.
+CPU oracle timed on a bounded sample of the same workload.  Beside the step,
+outside its timing, the ray-tracing primary (Eq. 1) of the same jobs is timed
+and reported under "raytrace" with its own roofline and oracle rate.
 
 Workloads (synthetic, seeded; sizes of the paper's CBCT setting):
   c1  one projection: 256x256x160 ellipsoid phantom, 120 kVp + bowtie, 1e8 photons
@@ -140,7 +142,7 @@ def build_workload(name, api, W, torch):
             return [api.last_kernel_ms()]
 
         samples = [(prob, float(jobs[k].geom.phi_rad), jobs[k].job_id) for k in (0, len(jobs) // 2)]
-        return dict(step=step, fwd=fwd, adj=0, samples=samples, adjoint=None,
+        return dict(step=step, fwd=fwd, adj=0, samples=samples, adjoint=None, batch=batch, prob_of=lambda k: prob,
                     config=dict(workload=name, phantom="256x256x160 @1.95x1.95x2.5mm ellipsoids",
                                 angles=len(jobs), photons_per_angle=jobs[0].n_photons,
                                 detector="256x192 @1.552mm", spectrum="120 kVp Kramers + 2.5 mm Al, bowtie 30 mm Al",
@@ -219,8 +221,96 @@ def build_workload(name, api, W, torch):
                    detector="256x192 @1.552mm", spectrum="120 kVp Kramers + 2.5 mm Al, bowtie 30 mm Al",
                    phantoms=[f"{'x'.join(map(str, ph.shape[::-1]))} @{ph.spacing_mm[0]}mm" for ph, _ in phantoms],
                    photons_per_angle=[p[2] for p in plan])
-        return dict(step=step, fwd=fwd, adj=adjh, samples=samples, adjoint=adjoint, config=cfg)
+        def prob_of(k):
+            return W.Problem(phantoms[jobs[k].volume][0], physw, srcw, jobs[k].geom, 0)
+
+        return dict(step=step, fwd=fwd, adj=adjh, samples=samples, adjoint=adjoint, config=cfg, batch=batch,
+                    prob_of=prob_of)
     raise SystemExit(f"unknown workload {name}")
+
+
+# ---------------------------------------------------------------------------
+# Ray-tracing primary (Eq. 1) over the same jobs: measured beside the step
+# ---------------------------------------------------------------------------
+# per interval: position (3 FMA), lattice coordinates (6), floor/convert/clamp
+# (12), fractions (6), cell address (4), trilinear (14), accumulate (2), loop (5)
+SLOTS_RT_INTERVAL = 52
+BYTES_RT_INTERVAL = 8 * 4 + 8        # eight corner densities and materials
+
+
+def rt_intervals(batch, dl_of):
+    """Intervals the ray tracer evaluates (ray parts inside the phantom box,
+    cut at multiples of dl from the source), counted on the host in float64."""
+    total = 0
+    for j in batch.jobs:
+        g, v = j.geom, batch.vols[j.volume]
+        nz, ny, nx = v.shape
+        half = 0.5 * np.array([nx, ny, nz]) * np.array(v.spacing_mm)
+        cq, sq = math.cos(g.phi_rad + g.theta_rad), math.sin(g.phi_rad + g.theta_rad)
+        S = -g.sad_mm * np.array([math.cos(g.phi_rad), math.sin(g.phi_rad), 0.0])
+        P = g.aid_mm * np.array([cq, sq, 0.0])
+        eu = np.array([-sq, cq, 0.0])
+        uc = (np.arange(g.nu) + 0.5 - 0.5 * g.nu) * g.du_mm
+        vc = (np.arange(g.nv) + 0.5 - 0.5 * g.nv) * g.dv_mm
+        D = P[None, None] + uc[None, :, None] * eu[None, None] + vc[:, None, None] * np.array([0, 0, 1.0])[None, None]
+        d = (D - S).reshape(-1, 3)
+        ln = np.linalg.norm(d, axis=1)
+        d /= ln[:, None]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            ta = (-half[None] - S[None]) / d
+            tb = (half[None] - S[None]) / d
+        t0 = np.maximum(np.nanmax(np.minimum(ta, tb), axis=1), 0.0)
+        t1 = np.minimum(np.nanmin(np.maximum(ta, tb), axis=1), ln)
+        dl = dl_of(v)
+        hit = t1 > t0
+        total += int((np.ceil(t1[hit] / dl) - np.floor(t0[hit] / dl)).sum())
+    return total
+
+
+def raytrace_leg(wl, api, torch, steps, cpu):
+    batch = wl["batch"]
+    dl_of = lambda v: 0.5 * min(v.spacing_mm)
+    batch.primary()                                   # workspace and cell records
+    torch.cuda.synchronize()
+    ms, walls = [], []
+    for _ in range(max(steps, 1)):
+        t = time.perf_counter()
+        batch.primary()
+        ms.append(api.last_kernel_ms())
+        torch.cuda.synchronize()
+        walls.append((time.perf_counter() - t) * 1e3)
+    kms = float(np.mean(ms))
+    rays = sum(j.geom.nu * j.geom.nv for j in batch.jobs)
+    iv = rt_intervals(batch, dl_of)
+    alu = iv * SLOTS_RT_INTERVAL / (kms * 1e-3) / 1e12
+    gbs = iv * BYTES_RT_INTERVAL / (kms * 1e-3) / 1e9
+    ra = dict(bound="alu", achieved=round(alu, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Tops/s",
+              frac=round(alu / ALU_PEAK_TOPS, 4), traffic=None)
+    rh = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+              frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None)
+    out = dict(images=len(batch.jobs), kernel_ms=round(kms, 3), wall_ms=round(float(np.mean(walls)), 3),
+               images_per_s=round(len(batch.jobs) / (kms * 1e-3), 1), rays_per_s=round(rays / (kms * 1e-3), 1),
+               intervals=iv, intervals_per_s=round(iv / (kms * 1e-3), 1),
+               roofline=ra if ra["frac"] >= rh["frac"] else rh, roofline_other=rh if ra["frac"] >= rh["frac"] else ra)
+    if cpu:
+        import oracle
+        k = 0
+        p = oracle.Problem.from_workload(wl["prob_of"](k), phi_rad=batch.jobs[k].geom.phi_rad)
+        rng = np.random.default_rng(0)
+        g = batch.jobs[k].geom
+        n = 256
+        while True:
+            pix = rng.choice(g.nu * g.nv, min(n, g.nu * g.nv), replace=False)
+            t = time.time()
+            oracle.primary_raytrace(p, pixels=pix)
+            dt = time.time() - t
+            if dt > 2.0 or n >= g.nu * g.nv:
+                break
+            n *= 4
+        out["cpu_baseline"] = dict(value=round(len(pix) / dt, 1), unit="rays/s",
+                                   cores=int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count(),
+                                   kind="oracle", sample=f"{len(pix)} rays of job 0")
+    return out
 
 
 # ---------------------------------------------------------------------------
@@ -282,6 +372,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-raytrace", action="store_true", help="skip the ray-tracing primary leg")
     ap.add_argument("--tune", default="auto", choices=["auto", "default"],
                     help="auto: autotune the launch shape before timing; default: library defaults")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -331,6 +422,7 @@ def main():
     fwd_ms = float(np.mean([k[0] for k in kms]))
     adj_ms = float(np.mean([k[1] for k in kms])) if wl["adj"] else None
 
+    rt = None if args.no_raytrace else raytrace_leg(wl, api, torch, args.steps, not args.no_cpu_baseline)
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
     roof = None
     extra = {}
@@ -364,7 +456,7 @@ def main():
                 fwd_histories_per_s=round(wl["fwd"] / (fwd_ms * 1e-3), 1),
                 adj_histories_per_s=round(wl["adj"] / (adj_ms * 1e-3), 1) if adj_ms else None,
                 transport_kernel_ms=round(fwd_ms, 3), adjoint_kernel_ms=round(adj_ms, 3) if adj_ms else None,
-                **extra)
+                **extra, raytrace=rt)
     print(json.dumps(line), flush=True)
 
 

@@ -12,7 +12,8 @@
  * add r(E) to a primary or a scatter tally per pixel depending on whether they
  * scattered.  Tallies are per source photon (Sec. 2.6).  It also offers the
  * gradient of a loss of the tallies with respect to voxel densities (path
- * replay of the same random numbers; not in the paper).
+ * replay of the same random numbers; not in the paper) and Step 1, the
+ * primary signal by tri-linear ray tracing (Sec. 2.3, Eq. 1).
  *
  * Conventions (the paper leaves them open; these are the library's reading):
  *  - lengths in mm, energies in keV, mass attenuation in cm^2/g, density in
@@ -211,6 +212,31 @@ int gdrr_mc_trace(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr_s
                   uint64_t n_photons, uint32_t job_id, uint32_t flags, int8_t* cls, int32_t* pixel,
                   float* e_final, int32_t* steps, int32_t* n_compton, int32_t* n_rayleigh,
                   void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Primary signal by ray tracing (Sec. 2.3, Eq. 1), the deterministic
+ * counterpart of the MC's primary tally, per source photon:
+ *   P(u) = sum_k phi_k w(u) r(E_k) exp(-sum_j dl_j mu(x_j, E_k)),
+ * phi and w normalised to sum 1, over the spectrum's channels (E_k, phi_k).
+ * The ray runs from S to the centre of pixel u; its length from S is cut
+ * into intervals [j dl, (j+1) dl), and the part of each interval inside the
+ * phantom box is one term with mu at its midpoint.  With GDRR_INTERP_DENSITY
+ * mu(x, E) interpolates the voxel attenuation coefficients
+ * rho_v mu_tot(m_v, E) trilinearly over the lattice of voxel centres
+ * (clamped at the edges); without it mu is the containing voxel's value.
+ * step_mm is dl (<= 0: half the smallest voxel edge of the job's volume);
+ * a ray may take at most 2^20 intervals.  Job k's image [nv][nu] (double)
+ * goes to out + jobs[k].tally_offset; n_photons and job_id are ignored.
+ * Flags: GDRR_INTERP_DENSITY, GDRR_ACCUMULATE (add to out); others are
+ * rejected.  Workspace: gdrr_primary_workspace() bytes (it holds the cell
+ * records of each volume when interpolating).  The timing hook brackets the
+ * ray-tracing kernel.
+ */
+int gdrr_primary(const gdrr_volume* vols, int32_t n_vols, const gdrr_physics* phys, const gdrr_source* srcs,
+                 int32_t n_srcs, const gdrr_job* jobs, int32_t n_jobs, float step_mm, uint32_t flags,
+                 double* out, void* workspace, size_t ws_bytes, void* stream);
+size_t gdrr_primary_workspace(const gdrr_volume* vols, int32_t n_vols, const gdrr_physics* phys,
+                              const gdrr_source* srcs, int32_t n_srcs, const gdrr_job* jobs, int32_t n_jobs);
 
 /*
  * Timing hook (autotuner, benchmarks): while enabled, the transport kernel of

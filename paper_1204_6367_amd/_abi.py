@@ -82,6 +82,10 @@ SIGNATURES = {
     "gdrr_mc_trace": (C.c_int, [_P(Volume), _P(Physics), _P(Source), _P(Geometry), _vp, C.c_uint64,
                                 C.c_uint64, C.c_uint32, C.c_uint32, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _sz,
                                 _vp]),
+    "gdrr_primary": (C.c_int, [_P(Volume), C.c_int32, _P(Physics), _P(Source), C.c_int32, _P(Job), C.c_int32,
+                               C.c_float, C.c_uint32, _vp, _vp, _sz, _vp]),
+    "gdrr_primary_workspace": (_sz, [_P(Volume), C.c_int32, _P(Physics), _P(Source), C.c_int32, _P(Job),
+                                     C.c_int32]),
     "gdrr_enable_timing": (C.c_int, [C.c_int]),
     "gdrr_last_kernel_ms": (C.c_int, [_P(C.c_float)]),
     "gdrr_default_tuning": (C.c_int, [_P(Tuning)]),

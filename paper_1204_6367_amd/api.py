@@ -165,6 +165,14 @@ def trace(vol: DeviceVolume, phys: DevicePhysics, src: DeviceSource, geom, n_pho
     return out
 
 
+def primary(vol: DeviceVolume, phys: DevicePhysics, src: DeviceSource, geom, interp: bool = True,
+            step_mm: float = 0.0, density: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Eq. 1 by ray tracing: primary signal [nv][nu] float64 per source photon."""
+    b = Batch([vol], phys, [src], [JobSpec(geom, 0, 0)])
+    return b.primary(interp=interp, step_mm=step_mm, densities=None if density is None else [density],
+                     stream=stream)[0]
+
+
 def enable_timing(on: bool = True):
     """Bracket every transport-kernel launch with HIP events on its stream."""
     _abi.check(_abi.lib().gdrr_enable_timing(1 if on else 0))
@@ -185,7 +193,8 @@ class JobSpec:
         self.volume, self.source = int(volume), int(source)
 
 
-def _jobs_array(jobs: Sequence[JobSpec]):
+def _jobs_array(jobs: Sequence[JobSpec], planes: int = 4):
+    """C job array with each job's output block of `planes` [nv][nu] images packed in order."""
     arr = (_abi.Job * len(jobs))()
     off = 0
     for k, j in enumerate(jobs):
@@ -193,7 +202,7 @@ def _jobs_array(jobs: Sequence[JobSpec]):
         arr[k].geom = geometry_struct(j.geom)
         arr[k].n_photons, arr[k].job_id, arr[k].reserved = j.n_photons, j.job_id, 0
         arr[k].tally_offset = off
-        off += 4 * j.geom.nu * j.geom.nv
+        off += planes * j.geom.nu * j.geom.nv
     return arr, off
 
 
@@ -241,6 +250,35 @@ class Batch:
             out.append(tallies[off:off + n].view(4, j.geom.nv, j.geom.nu))
             off += n
         return out
+
+    def primary(self, interp: bool = True, step_mm: float = 0.0, accumulate: bool = False,
+                out: Optional[torch.Tensor] = None, densities=None, stream=None) -> List[torch.Tensor]:
+        """Eq. 1 by ray tracing for every job: a list of [nv][nu] float64 views
+        into one flat buffer (`out`, if given, holds sum(nv*nu) elements)."""
+        L = _abi.lib()
+        if not hasattr(self, "_img_jobs"):
+            self._img_jobs = _jobs_array(self.jobs, planes=1)
+        jobs_c, n = self._img_jobs
+        va, sa, p = self._structs(densities)
+        dev = self.vols[0].density.device
+        if out is None:
+            out = torch.zeros(n, dtype=torch.float64, device=dev)
+        nbytes = int(L.gdrr_primary_workspace(va, len(self.vols), C.byref(p), sa, len(self.srcs), jobs_c,
+                                              len(self.jobs)))
+        if nbytes == 0:
+            raise ValueError("invalid batch for gdrr_primary")
+        if getattr(self, "_rt_ws", None) is None or self._rt_ws.numel() < nbytes:
+            self._rt_ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        flags = (INTERP_DENSITY if interp else 0) | (ACCUMULATE if accumulate else 0)
+        _abi.check(L.gdrr_primary(va, len(self.vols), C.byref(p), sa, len(self.srcs), jobs_c, len(self.jobs),
+                                  float(step_mm), flags, out.data_ptr(), self._rt_ws.data_ptr(),
+                                  self._rt_ws.numel(), _stream(stream)))
+        views, off = [], 0
+        for j in self.jobs:
+            k = j.geom.nu * j.geom.nv
+            views.append(out[off:off + k].view(j.geom.nv, j.geom.nu))
+            off += k
+        return views
 
     def majorants(self, interp: bool = True, margin: float = 2.0**-20, densities=None, stream=None):
         ms = [majorant(v, self.phys, interp, margin, None if densities is None else densities[k], stream)

@@ -12,6 +12,7 @@
 #include "gdrr.h"
 #include "gdrr_kernels.h"
 #include "gdrr_queue.h"
+#include "gdrr_raytrace.h"
 
 using namespace gdrr;
 
@@ -350,6 +351,28 @@ struct Batch {
 
 thread_local std::vector<char> g_staging;
 
+// Geometry part of a job record (Sec. 2.1), evaluated in double and stored as float.
+DJob djob_of(const gdrr_job& J) {
+    const gdrr_geometry& g = J.geom;
+    const double phi = g.phi_rad, th = g.theta_rad;
+    const double cq = std::cos(phi + th), sq = std::sin(phi + th);
+    DJob d{};
+    d.Sx = (float)(-g.sad_mm * std::cos(phi));
+    d.Sy = (float)(-g.sad_mm * std::sin(phi));
+    d.Sz = 0.0f;
+    d.Px = (float)(g.aid_mm * cq);
+    d.Py = (float)(g.aid_mm * sq);
+    d.Pz = 0.0f;
+    d.nx = (float)cq; d.ny = (float)sq; d.nz = 0.0f;
+    d.ux = (float)(-sq); d.uy = (float)cq; d.uz = 0.0f;
+    d.du = g.du_mm; d.dv = g.dv_mm;
+    d.idu = (float)(1.0 / g.du_mm); d.idv = (float)(1.0 / g.dv_mm);
+    d.nu = g.nu; d.nv = g.nv;
+    d.src = J.source; d.vol = J.volume;
+    d.job_id = J.job_id;
+    return d;
+}
+
 int check_batch(const Batch& B) {
     if (B.n_vols < 1 || B.n_vols > GDRR_MAX_VOLUMES) return fail(GDRR_EINVAL, "n_vols must be in [1, 8]");
     if (B.n_srcs < 1 || B.n_srcs > GDRR_MAX_SOURCES) return fail(GDRR_EINVAL, "n_srcs must be in [1, 8]");
@@ -445,22 +468,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     for (size_t k = 0; k < n_jobs; ++k) {
         const gdrr_job& J = B.jobs[k];
         const gdrr_geometry& g = J.geom;
-        const double phi = g.phi_rad, th = g.theta_rad;
-        const double cq = std::cos(phi + th), sq = std::sin(phi + th);
-        DJob d{};
-        d.Sx = (float)(-g.sad_mm * std::cos(phi));
-        d.Sy = (float)(-g.sad_mm * std::sin(phi));
-        d.Sz = 0.0f;
-        d.Px = (float)(g.aid_mm * cq);
-        d.Py = (float)(g.aid_mm * sq);
-        d.Pz = 0.0f;
-        d.nx = (float)cq; d.ny = (float)sq; d.nz = 0.0f;
-        d.ux = (float)(-sq); d.uy = (float)cq; d.uz = 0.0f;
-        d.du = g.du_mm; d.dv = g.dv_mm;
-        d.idu = (float)(1.0 / g.du_mm); d.idv = (float)(1.0 / g.dv_mm);
-        d.nu = g.nu; d.nv = g.nv;
-        d.src = J.source; d.vol = J.volume;
-        d.job_id = J.job_id;
+        DJob d = djob_of(J);
         const bool run = B.only_volume < 0 || J.volume == B.only_volume;
         const unsigned long long n = run ? J.n_photons : 0ull;
         d.n_lo = (uint32_t)J.n_photons;
@@ -630,6 +638,241 @@ size_t batch_bytes(const gdrr_volume* vols, int n_vols, const gdrr_physics* phys
            256;
 }
 
+// --------------------------------------------------------------------------
+// Ray-tracing primary (Eq. 1): workspace layout and launch.
+// --------------------------------------------------------------------------
+struct RtLayout {
+    DJob* jobs;                          // [n_jobs]
+    int* unit_job;                       // [max units]
+    unsigned int* unit_first;
+    unsigned int* unit_pref;
+    long long* out_off;                  // [n_jobs]
+    float* coef[GDRR_MAX_SOURCES];       // [n_spec]
+    float* tab[GDRR_MAX_SOURCES];        // [n_spec][n_mat]
+    double* inv_wsum[GDRR_MAX_SOURCES];  // [1]
+    CellRec* cells[GDRR_MAX_VOLUMES];    // volumes that some job uses
+    size_t bytes;
+};
+
+bool volume_used(const gdrr_job* jobs, int n_jobs, int v) {
+    for (int k = 0; k < n_jobs; ++k)
+        if (jobs[k].volume == v) return true;
+    return false;
+}
+
+
+unsigned long long rt_tiles(const gdrr_geometry& g) {
+    return (unsigned long long)((g.nu + 15) / 16) * (unsigned long long)((g.nv + 15) / 16);
+}
+
+// Work units: a job's tiles in runs of `run` (whole jobs when there are
+// enough of them to fill every XCD several times).
+unsigned long long rt_run_length(const gdrr_job* jobs, int n_jobs) {
+    unsigned long long total = 0, most = 1;
+    for (int k = 0; k < n_jobs; ++k) {
+        total += rt_tiles(jobs[k].geom);
+        most = std::max(most, rt_tiles(jobs[k].geom));
+    }
+    return std::min(most, std::max<unsigned long long>(4, total / (8ull * kXcds)));
+}
+
+size_t rt_max_units(const gdrr_job* jobs, int n_jobs) {
+    const unsigned long long run = rt_run_length(jobs, n_jobs);
+    size_t u = 0;
+    for (int k = 0; k < n_jobs; ++k) u += (size_t)((rt_tiles(jobs[k].geom) + run - 1) / run);
+    return u;
+}
+
+RtLayout rt_carve(void* ws, const gdrr_volume* vols, int n_vols, const gdrr_physics* phys, const gdrr_source* srcs,
+                  int n_srcs, const gdrr_job* jobs, int n_jobs) {
+    Carver c(ws);
+    RtLayout L{};
+    L.jobs = c.take<DJob>((size_t)n_jobs);
+    const size_t units = rt_max_units(jobs, n_jobs);
+    L.unit_job = c.take<int>(units);
+    L.unit_first = c.take<unsigned int>(units);
+    L.unit_pref = c.take<unsigned int>(units);
+    L.out_off = c.take<long long>((size_t)n_jobs);
+    for (int s = 0; s < n_srcs; ++s) {
+        L.coef[s] = c.take<float>((size_t)srcs[s].n_spec);
+        L.tab[s] = c.take<float>((size_t)srcs[s].n_spec * phys->n_mat);
+        L.inv_wsum[s] = c.take<double>(1);
+    }
+    for (int v = 0; v < n_vols; ++v)
+        L.cells[v] = volume_used(jobs, n_jobs, v) ? c.take<CellRec>(cell_count(vols[v])) : nullptr;
+    L.bytes = c.off + 256;
+    return L;
+}
+
+constexpr unsigned kRtMaxTiles = (1u << 24) - 1024u;    // grid * block stays below 2^32 work-items
+
+int check_rt(const gdrr_volume* vols, int n_vols, const gdrr_physics* phys, const gdrr_source* srcs, int n_srcs,
+             const gdrr_job* jobs, int n_jobs, uint32_t flags) {
+    if (n_vols < 1 || n_vols > GDRR_MAX_VOLUMES) return fail(GDRR_EINVAL, "n_vols must be in [1, 8]");
+    if (n_srcs < 1 || n_srcs > GDRR_MAX_SOURCES) return fail(GDRR_EINVAL, "n_srcs must be in [1, 8]");
+    if (n_jobs < 1 || n_jobs > (1 << 20)) return fail(GDRR_EINVAL, "n_jobs must be in [1, 2^20]");
+    if (!vols || !srcs || !jobs) return fail(GDRR_EINVAL, "NULL array argument");
+    if (flags & ~(GDRR_INTERP_DENSITY | GDRR_ACCUMULATE))
+        return fail(GDRR_EINVAL, "gdrr_primary takes only GDRR_INTERP_DENSITY and GDRR_ACCUMULATE");
+    int rc;
+    if ((rc = check_physics(phys))) return rc;
+    for (int v = 0; v < n_vols; ++v)
+        if ((rc = check_volume(&vols[v]))) return rc;
+    for (int s = 0; s < n_srcs; ++s)
+        if ((rc = check_source(&srcs[s]))) return rc;
+    for (int k = 0; k < n_jobs; ++k) {
+        const gdrr_job& J = jobs[k];
+        if (J.volume < 0 || J.volume >= n_vols) return fail(GDRR_EINVAL, "job volume index out of range");
+        if (J.source < 0 || J.source >= n_srcs) return fail(GDRR_EINVAL, "job source index out of range");
+        if (J.tally_offset < 0) return fail(GDRR_EINVAL, "negative output offset");
+        if ((rc = check_geometry(&J.geom, &vols[J.volume], &srcs[J.source]))) return rc;
+    }
+    return GDRR_OK;
+}
+
+int run_primary(const gdrr_volume* vols, int n_vols, const gdrr_physics* phys, const gdrr_source* srcs, int n_srcs,
+                const gdrr_job* jobs, int n_jobs, float step_mm, uint32_t flags, double* out, void* ws,
+                size_t ws_bytes, hipStream_t st) {
+    int rc = check_rt(vols, n_vols, phys, srcs, n_srcs, jobs, n_jobs, flags);
+    if (rc) return rc;
+    if (!out) return fail(GDRR_EINVAL, "out is NULL");
+    if (!std::isfinite(step_mm)) return fail(GDRR_EINVAL, "step_mm must be finite");
+    const RtLayout L0 = rt_carve(nullptr, vols, n_vols, phys, srcs, n_srcs, jobs, n_jobs);
+    if (!ws || ws_bytes < L0.bytes)
+        return fail(GDRR_EINVAL, "workspace too small: need " + std::to_string(L0.bytes) + " bytes");
+    RtParams rp{};
+    for (int v = 0; v < n_vols; ++v) {
+        const gdrr_volume& V = vols[v];
+        const double edge = std::min(V.dx_mm, std::min(V.dy_mm, V.dz_mm));
+        const double dl = step_mm > 0.0f ? (double)step_mm : 0.5 * edge;
+        const double diag = std::sqrt((double)V.nx * V.dx_mm * V.nx * V.dx_mm + (double)V.ny * V.dy_mm * V.ny * V.dy_mm +
+                                      (double)V.nz * V.dz_mm * V.nz * V.dz_mm);
+        if (volume_used(jobs, n_jobs, v) && diag / dl > (double)(1 << 20))
+            return fail(GDRR_EINVAL, "step_mm too small: more than 2^20 intervals across a phantom");
+        rp.dl[v] = (float)dl;
+    }
+    const size_t lds = (size_t)phys->n_mat * kRtBlock * sizeof(float);
+    DevInfo dev;
+    if ((rc = device_info(dev))) return rc;
+    if (lds > dev.lds_max) return fail(GDRR_ENOTSUP, "per-material accumulators exceed the LDS of a workgroup");
+    char* wsa = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    const RtLayout L = rt_carve(wsa, vols, n_vols, phys, srcs, n_srcs, jobs, n_jobs);
+    const bool interp = (flags & GDRR_INTERP_DENSITY) != 0;
+
+    const size_t nj = (size_t)n_jobs;
+    std::vector<DJob> dj(nj);
+    std::vector<long long> off(nj);
+    unsigned long long tiles = 0;
+    for (size_t k = 0; k < nj; ++k) {
+        dj[k] = djob_of(jobs[k]);
+        dj[k].index = (uint32_t)k;
+        off[k] = jobs[k].tally_offset;
+        tiles += rt_tiles(jobs[k].geom);
+        if (tiles > kRtMaxTiles) return fail(GDRR_EINVAL, "too many pixels in one call (2^32 lanes)");
+    }
+    // Units to XCDs, in job order, each to the XCD with the least estimated
+    // work so far (tiles x intervals across the job's phantom): every XCD gets
+    // a share of every phantom, and walks its units in order, so the tiles in
+    // flight on it belong to one or two projections.
+    const unsigned long long run = rt_run_length(jobs, n_jobs);
+    std::vector<int> u_job[kXcds];
+    std::vector<unsigned int> u_first[kXcds];
+    double load[kXcds] = {0};
+    for (size_t k = 0; k < nj; ++k) {
+        const gdrr_volume& V = vols[jobs[k].volume];
+        const double span = std::sqrt((double)V.nx * V.dx_mm * V.nx * V.dx_mm + (double)V.ny * V.dy_mm * V.ny * V.dy_mm +
+                                      (double)V.nz * V.dz_mm * V.nz * V.dz_mm) / rp.dl[jobs[k].volume];
+        const unsigned long long tk = rt_tiles(jobs[k].geom);
+        for (unsigned long long f = 0; f < tk; f += run) {
+            const int x = (int)(std::min_element(load, load + kXcds) - load);
+            u_job[x].push_back((int)k);
+            u_first[x].push_back((unsigned int)f);
+            load[x] += (double)std::min(run, tk - f) * (span + 64.0);
+        }
+    }
+    std::vector<int> ujob;
+    std::vector<unsigned int> ufirst, upref;
+    unsigned int most = 0;
+    for (int x = 0; x < kXcds; ++x) {
+        rp.xcd_start[x] = (unsigned int)ujob.size();
+        unsigned int acc = 0;
+        for (size_t i = 0; i < u_job[x].size(); ++i) {
+            const int k = u_job[x][i];
+            ujob.push_back(k);
+            ufirst.push_back(u_first[x][i]);
+            upref.push_back(acc);
+            acc += (unsigned int)std::min<unsigned long long>(run, rt_tiles(jobs[k].geom) - u_first[x][i]);
+        }
+        rp.xcd_tiles[x] = acc;
+        most = std::max(most, acc);
+    }
+    rp.xcd_start[kXcds] = (unsigned int)ujob.size();
+    const size_t nu_ = ujob.size();
+    const size_t b_jobs = sizeof(DJob) * nj, b_u = sizeof(unsigned int) * nu_, b_off = sizeof(long long) * nj;
+    g_staging.resize(b_jobs + 3 * b_u + b_off);
+    char* hs = g_staging.data();
+    std::memcpy(hs, dj.data(), b_jobs);
+    std::memcpy(hs + b_jobs, ujob.data(), b_u);
+    std::memcpy(hs + b_jobs + b_u, ufirst.data(), b_u);
+    std::memcpy(hs + b_jobs + 2 * b_u, upref.data(), b_u);
+    std::memcpy(hs + b_jobs + 3 * b_u, off.data(), b_off);
+    GDRR_HIP(hipMemcpyAsync(L.jobs, hs, b_jobs, hipMemcpyHostToDevice, st));
+    GDRR_HIP(hipMemcpyAsync(L.unit_job, hs + b_jobs, b_u, hipMemcpyHostToDevice, st));
+    GDRR_HIP(hipMemcpyAsync(L.unit_first, hs + b_jobs + b_u, b_u, hipMemcpyHostToDevice, st));
+    GDRR_HIP(hipMemcpyAsync(L.unit_pref, hs + b_jobs + 2 * b_u, b_u, hipMemcpyHostToDevice, st));
+    GDRR_HIP(hipMemcpyAsync(L.out_off, hs + b_jobs + 3 * b_u, b_off, hipMemcpyHostToDevice, st));
+
+    std::vector<Launch> ls;
+    for (int v = 0; v < n_vols; ++v) {
+        const gdrr_volume& V = vols[v];
+        DVolume& d = rp.vol[v];
+        d.density = V.density;
+        d.material = V.material;
+        d.cells = interp ? L.cells[v] : nullptr;
+        d.cx = V.nx + 1;
+        d.cxy = (V.nx + 1) * (V.ny + 1);
+        d.nx = V.nx; d.ny = V.ny; d.nz = V.nz; d.nxy = V.nx * V.ny;
+        d.lox = (float)(-0.5 * V.nx * V.dx_mm); d.hix = -d.lox;
+        d.loy = (float)(-0.5 * V.ny * V.dy_mm); d.hiy = -d.loy;
+        d.loz = (float)(-0.5 * V.nz * V.dz_mm); d.hiz = -d.loz;
+        d.idx = (float)(1.0 / V.dx_mm); d.idy = (float)(1.0 / V.dy_mm); d.idz = (float)(1.0 / V.dz_mm);
+        if (interp && L.cells[v]) {
+            CellParams cp{V.density, V.material, V.nx, V.ny, V.nz, L.cells[v]};
+            const size_t nc = cell_count(V);
+            ls.push_back(make_launch((const void*)&cells_kernel,
+                                     dim3((unsigned)std::max<size_t>(1, std::min<size_t>((size_t)dev.cus * 16, (nc + 255) / 256))),
+                                     dim3(256), 0, cp));
+        }
+    }
+    for (int s = 0; s < n_srcs; ++s) {
+        const gdrr_source& S = srcs[s];
+        RtPrepParams pp{S.spec_e_kev, S.spec_prob, S.fluence, S.n_spec, S.fu * S.fv, phys->mu_mass, phys->response,
+                        phys->n_mat, phys->n_e, (double)phys->e0_kev, (double)phys->de_kev, L.coef[s], L.tab[s],
+                        L.inv_wsum[s]};
+        ls.push_back(make_launch((const void*)&raytrace_prep_kernel, dim3(1), dim3(256), 0, pp));
+        rp.src[s] = RtSource{S.fluence, L.coef[s], L.tab[s], L.inv_wsum[s], S.n_spec};
+    }
+    rp.jobs = L.jobs;
+    rp.unit_job = L.unit_job;
+    rp.unit_first = L.unit_first;
+    rp.unit_pref = L.unit_pref;
+    rp.out_off = L.out_off;
+    rp.out = out;
+    rp.n_mat = phys->n_mat;
+    rp.interp = interp ? 1 : 0;
+    rp.accumulate = (flags & GDRR_ACCUMULATE) ? 1 : 0;
+    const unsigned long long grid = (unsigned long long)kXcds * most;
+    if (grid * kRtBlock >= (1ull << 32)) return fail(GDRR_EINVAL, "too many pixels in one call (2^32 lanes)");
+    const int timed = (int)ls.size();
+    ls.push_back(make_launch((const void*)&raytrace_kernel, dim3((unsigned)grid), dim3(kRtBlock), lds, rp));
+    TimeEvents* ev = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_time_mu);
+        if (g_timing && (rc = timing_events(&ev))) return rc;
+    }
+    return run_direct(ls, st, ev ? timed : -1, ev);
+}
+
 gdrr_job single_job(const gdrr_geometry* geom, uint64_t n, uint32_t job_id) {
     gdrr_job j{};
     j.volume = 0;
@@ -760,6 +1003,27 @@ int gdrr_mc_backward(const gdrr_volume* vols, int32_t n_vols, const gdrr_physics
     Batch B{vols, n_vols, phys, srcs, n_srcs, jobs, n_jobs, majorants, seed, flags, tune, kModeBackward, volume,
             nullptr, adj, grad_density, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, false};
     return run_batch(B, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+size_t gdrr_primary_workspace(const gdrr_volume* vols, int32_t n_vols, const gdrr_physics* phys,
+                              const gdrr_source* srcs, int32_t n_srcs, const gdrr_job* jobs, int32_t n_jobs) {
+    if (!vols || !phys || !srcs || !jobs || n_vols < 1 || n_vols > GDRR_MAX_VOLUMES || n_srcs < 1 ||
+        n_srcs > GDRR_MAX_SOURCES || n_jobs < 1)
+        return 0;
+    for (int k = 0; k < n_jobs; ++k)
+        if (jobs[k].volume < 0 || jobs[k].volume >= n_vols) return 0;
+    for (int v = 0; v < n_vols; ++v)
+        if (vols[v].nx < 1 || vols[v].ny < 1 || vols[v].nz < 1) return 0;
+    for (int s = 0; s < n_srcs; ++s)
+        if (srcs[s].n_spec < 1) return 0;
+    return rt_carve(nullptr, vols, n_vols, phys, srcs, n_srcs, jobs, n_jobs).bytes + 256;
+}
+
+int gdrr_primary(const gdrr_volume* vols, int32_t n_vols, const gdrr_physics* phys, const gdrr_source* srcs,
+                 int32_t n_srcs, const gdrr_job* jobs, int32_t n_jobs, float step_mm, uint32_t flags, double* out,
+                 void* workspace, size_t ws_bytes, void* stream) {
+    return run_primary(vols, n_vols, phys, srcs, n_srcs, jobs, n_jobs, step_mm, flags, out, workspace, ws_bytes,
+                       (hipStream_t)stream);
 }
 
 int gdrr_mc_trace(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr_source* src,

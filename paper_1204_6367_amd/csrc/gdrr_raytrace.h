@@ -1,0 +1,250 @@
+// Primary signal by ray tracing (Sec. 2.3, Eq. 1): one lane per detector
+// pixel, every energy channel of the spectrum.
+//
+//   P(u) = sum_k phi_k w(u) r(E_k) exp(-sum_j dl_j mu(x_j, E_k))
+//
+// The ray from the source to the pixel centre is cut into intervals
+// [j dl, (j+1) dl) of its length from the source; the part of an interval
+// inside the phantom box is one term, evaluated at that part's midpoint.
+// mu(x, E) is the trilinear interpolation of the voxel attenuation
+// coefficients rho_v mu_tot(m_v, E) (the corners of the lattice cell around
+// x, clamped at the edges), or the containing voxel's value with the
+// interpolation off.
+//
+// mu is linear in the per-voxel products, so the energy channels share one
+// march: the lane accumulates, per material m, the line integral of the
+// density carried by m's corners (L_m), and the channel sums come out as
+// sum_m mu_tot(m, E_k) L_m after it.  Almost every lattice cell has a single
+// material; those steps add the interpolated density into one register
+// accumulator that is written to the lane's LDS slot of its material only when
+// the material changes.  Mixed cells add each corner's share to its
+// material's slot.
+#pragma once
+
+#include "gdrr_device.h"
+
+namespace gdrr {
+
+constexpr int kRtBlock = 256;     // 16 x 16 pixels; each wavefront an 8 x 8 quadrant
+constexpr int kXcds = 8;          // workgroup i runs on XCD i mod 8
+
+struct RtSource {
+    const float* fluence;         // [nv][nu] weights w(u) (unnormalised)
+    const float* coef;            // [n_spec] phi_k r(E_k) / sum phi
+    const float* tab;             // [n_spec][n_mat] 0.1 mu_tot(m, E_k): mm of density-length -> optical depth
+    const double* inv_wsum;       // 1 / sum_u w(u)
+    int n_spec;
+};
+
+struct RtParams {
+    DVolume vol[GDRR_MAX_VOLUMES];
+    RtSource src[GDRR_MAX_SOURCES];
+    float dl[GDRR_MAX_VOLUMES];   // interval length per volume, mm
+    const DJob* jobs;
+    // Work units (runs of consecutive tiles of one job), listed XCD by XCD:
+    // XCD x owns units [xcd_start[x], xcd_start[x+1]); unit_pref is the
+    // running tile count within its XCD's list.
+    const int* unit_job;
+    const unsigned int* unit_first;    // first tile of the unit within its job
+    const unsigned int* unit_pref;
+    unsigned int xcd_start[kXcds + 1];
+    unsigned int xcd_tiles[kXcds];
+    const long long* out_off;     // [n_jobs] element offset of each job's image in out
+    double* out;
+    int n_mat, interp, accumulate;
+};
+
+// Slab clip of t in [t0, t1] to lo <= s + t d <= hi.
+__device__ __forceinline__ void rt_slab(float s, float d, float lo, float hi, float& t0, float& t1) {
+    if (d != 0.0f) {
+        const float ta = (lo - s) / d, tb = (hi - s) / d;
+        t0 = fmaxf(t0, fminf(ta, tb));
+        t1 = fminf(t1, fmaxf(ta, tb));
+    } else if (s < lo || s > hi) {
+        t1 = -1.0f;
+    }
+}
+
+__global__ __launch_bounds__(kRtBlock) void raytrace_kernel(RtParams P) {
+    extern __shared__ float rt_lds[];          // [n_mat][kRtBlock]: the lanes' L_m
+    // Workgroups are dealt to the XCDs in turn; each XCD walks its own list of
+    // units in order, so the tiles in flight on an XCD are those of one or two
+    // projections: their rays advance together through the phantom and share
+    // that XCD's L2.  The host balances the lists by estimated work.
+    const unsigned int x = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
+    if (slot >= P.xcd_tiles[x]) return;         // whole workgroup; no barrier in this kernel
+    int lo = (int)P.xcd_start[x], hi = (int)P.xcd_start[x + 1] - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (P.unit_pref[mid] <= slot) lo = mid; else hi = mid - 1;
+    }
+    const DJob& J = P.jobs[P.unit_job[lo]];
+    const unsigned int local = P.unit_first[lo] + (slot - P.unit_pref[lo]);
+    const int tiles_u = (J.nu + 15) >> 4;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int iu = (int)(local % tiles_u) * 16 + (w & 1) * 8 + (l & 7);
+    const int iv = (int)(local / tiles_u) * 16 + (w >> 1) * 8 + (l >> 3);
+    if (iu >= J.nu || iv >= J.nv) return;
+
+    float* Lm = rt_lds + threadIdx.x;
+    for (int m = 0; m < P.n_mat; ++m) Lm[m * kRtBlock] = 0.0f;
+
+    const DVolume& V = P.vol[J.vol];
+    const float uc = ((float)iu + 0.5f - 0.5f * (float)J.nu) * J.du;
+    const float vc = ((float)iv + 0.5f - 0.5f * (float)J.nv) * J.dv;
+    float dx = J.Px + uc * J.ux - J.Sx;
+    float dy = J.Py + uc * J.uy - J.Sy;
+    float dz = J.Pz + vc - J.Sz;                       // v axis = +z
+    const float len = sqrtf(dx * dx + dy * dy + dz * dz);
+    dx /= len; dy /= len; dz /= len;
+    float t0 = 0.0f, t1 = len;
+    rt_slab(J.Sx, dx, V.lox, V.hix, t0, t1);
+    rt_slab(J.Sy, dy, V.loy, V.hiy, t0, t1);
+    rt_slab(J.Sz, dz, V.loz, V.hiz, t0, t1);
+
+    if (t0 < t1) {
+        const float dl = P.dl[J.vol];
+        // the volume's fields in registers for the march
+        const CellRec* __restrict__ cells = V.cells;
+        const float* __restrict__ dens = V.density;
+        const uint8_t* __restrict__ mats = V.material;
+        const int nx = V.nx, ny = V.ny, nz = V.nz, nxy = V.nxy, cx = V.cx, cxy = V.cxy;
+        const float lox = V.lox, loy = V.loy, loz = V.loz, idx = V.idx, idy = V.idy, idz = V.idz;
+        const int n_mat = P.n_mat;
+        const bool interp = P.interp != 0;
+        // one interval of slack on both sides; empty parts are skipped
+        const int j0 = (int)floorf(t0 / dl) - 1, j1 = (int)ceilf(t1 / dl) + 1;
+        float acc = 0.0f;
+        int cur = -1;
+        for (int j = j0; j < j1; ++j) {
+            const float a = fmaxf((float)j * dl, t0), e = fminf((float)(j + 1) * dl, t1);
+            if (!(e > a)) continue;
+            const float h = e - a, t = 0.5f * (a + e);
+            const float px = J.Sx + t * dx, py = J.Sy + t * dy, pz = J.Sz + t * dz;
+            const float gx = (px - lox) * idx - 0.5f, gy = (py - loy) * idy - 0.5f,
+                        gz = (pz - loz) * idz - 0.5f;
+            const float fx0 = floorf(gx), fy0 = floorf(gy), fz0 = floorf(gz);
+            const int ix = min(max((int)fx0, -1), nx - 1);
+            const int iy = min(max((int)fy0, -1), ny - 1);
+            const int iz = min(max((int)fz0, -1), nz - 1);
+            const float fx = fminf(fmaxf(gx - fx0, 0.0f), 1.0f);
+            const float fy = fminf(fmaxf(gy - fy0, 0.0f), 1.0f);
+            const float fz = fminf(fmaxf(gz - fz0, 0.0f), 1.0f);
+            if (!interp) {
+                // containing voxel: the cell corner nearest to the point
+                const int vx = min(max(ix + (fx >= 0.5f ? 1 : 0), 0), nx - 1);
+                const int vy = min(max(iy + (fy >= 0.5f ? 1 : 0), 0), ny - 1);
+                const int vz = min(max(iz + (fz >= 0.5f ? 1 : 0), 0), nz - 1);
+                const long long v = (long long)vz * nxy + (long long)vy * nx + vx;
+                const int m = min((int)mats[v], n_mat - 1);
+                if (m != cur) {
+                    if (cur >= 0) Lm[cur * kRtBlock] += acc;
+                    cur = m;
+                    acc = 0.0f;
+                }
+                acc += h * dens[v];
+                continue;
+            }
+            const CellRec* r = cells + ((iz + 1) * cxy + (iy + 1) * cx + (ix + 1));
+            const float4 d0 = *reinterpret_cast<const float4*>(&r->d[0]);
+            const float4 d1 = *reinterpret_cast<const float4*>(&r->d[4]);
+            const uint2 mm = *reinterpret_cast<const uint2*>(&r->m[0]);
+            const uint32_t m0 = mm.x & 0xFFu;
+            if (mm.x == mm.y && mm.x == m0 * 0x01010101u) {
+                const float a00 = d0.x + fx * (d0.y - d0.x), a01 = d0.z + fx * (d0.w - d0.z);
+                const float a10 = d1.x + fx * (d1.y - d1.x), a11 = d1.z + fx * (d1.w - d1.z);
+                const float b0 = a00 + fy * (a01 - a00), b1 = a10 + fy * (a11 - a10);
+                const int m = min((int)m0, n_mat - 1);
+                if (m != cur) {
+                    if (cur >= 0) Lm[cur * kRtBlock] += acc;
+                    cur = m;
+                    acc = 0.0f;
+                }
+                acc += h * (b0 + fz * (b1 - b0));
+            } else {
+                const float gx0 = 1.0f - fx, gy0 = 1.0f - fy, gz0 = 1.0f - fz;
+                const float wz0 = h * gz0, wz1 = h * fz;
+                const float cd[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    const uint32_t word = c < 4 ? mm.x : mm.y;
+                    const int m = min((int)((word >> (8 * (c & 3))) & 0xFFu), n_mat - 1);
+                    const float wc = (c & 1 ? fx : gx0) * (c & 2 ? fy : gy0) * (c & 4 ? wz1 : wz0);
+                    Lm[m * kRtBlock] += wc * cd[c];
+                }
+            }
+        }
+        if (cur >= 0) Lm[cur * kRtBlock] += acc;
+    }
+
+    float Lr[GDRR_MAX_MATERIALS];
+#pragma unroll
+    for (int m = 0; m < GDRR_MAX_MATERIALS; ++m) Lr[m] = m < P.n_mat ? Lm[m * kRtBlock] : 0.0f;
+    const RtSource& S = P.src[J.src];
+    float sum = 0.0f;
+    for (int k = 0; k < S.n_spec; ++k) {
+        const float* row = S.tab + k * P.n_mat;
+        float tau = 0.0f;
+#pragma unroll
+        for (int m = 0; m < GDRR_MAX_MATERIALS; ++m)
+            if (m < P.n_mat) tau += row[m] * Lr[m];
+        sum += S.coef[k] * expf(-tau);
+    }
+    const int pix = iv * J.nu + iu;
+    const double val = (double)S.fluence[pix] * S.inv_wsum[0] * (double)sum;
+    double* o = P.out + P.out_off[J.index] + pix;
+    *o = P.accumulate ? *o + val : val;
+}
+
+// Per source: the channel weights phi_k r(E_k) / sum phi, the table
+// 0.1 mu_tot(m, E_k) (linear in E between grid points) and 1 / sum w.
+struct RtPrepParams {
+    const float* spec_e;
+    const float* spec_p;
+    const float* fluence;
+    int n_spec, npix;
+    const float* mu_mass;         // [n_mat][n_e][3]
+    const float* response;        // [n_e] or null
+    int n_mat, n_e;
+    double e0, de;
+    float* coef;
+    float* tab;
+    double* inv_wsum;
+};
+
+__global__ __launch_bounds__(256) void raytrace_prep_kernel(RtPrepParams R) {
+    __shared__ double red[2][256];
+    double sp = 0.0, sw = 0.0;
+    for (int k = threadIdx.x; k < R.n_spec; k += 256) sp += (double)R.spec_p[k];
+    for (int k = threadIdx.x; k < R.npix; k += 256) sw += (double)R.fluence[k];
+    red[0][threadIdx.x] = sp;
+    red[1][threadIdx.x] = sw;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + s];
+            red[1][threadIdx.x] += red[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    const double psum = red[0][0], wsum = red[1][0];
+    if (threadIdx.x == 0) R.inv_wsum[0] = wsum > 0.0 ? 1.0 / wsum : 0.0;
+    for (int k = threadIdx.x; k < R.n_spec; k += 256) {
+        const double E = (double)R.spec_e[k];
+        const double g = (E - R.e0) / R.de;
+        int j = (int)floor(g);
+        j = j < 0 ? 0 : (j > R.n_e - 2 ? R.n_e - 2 : j);
+        const double f = g - (double)j;
+        double r = E;
+        if (R.response) r = (double)R.response[j] + f * ((double)R.response[j + 1] - (double)R.response[j]);
+        R.coef[k] = psum > 0.0 ? (float)((double)R.spec_p[k] / psum * r) : 0.0f;
+        for (int m = 0; m < R.n_mat; ++m) {
+            const float* a = R.mu_mass + ((size_t)m * R.n_e + j) * 3;
+            const double ta = (double)a[0] + (double)a[1] + (double)a[2];
+            const double tb = (double)a[3] + (double)a[4] + (double)a[5];
+            R.tab[k * R.n_mat + m] = (float)(0.1 * (ta + f * (tb - ta)));
+        }
+    }
+}
+
+}  // namespace gdrr

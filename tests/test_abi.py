@@ -139,3 +139,27 @@ def test_product_path_does_not_import_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "gdrr_oracle" not in text and "liboracle" not in text, f
+
+
+def _call_primary(abi, vol, phys, src, geom, flags=1, step=0.0, ws_bytes=1 << 30, out=0x2000):
+    L = abi.lib()
+    job = abi.Job()
+    job.volume, job.source, job.geom = 0, 0, geom
+    return L.gdrr_primary(C.byref(vol), 1, C.byref(phys), C.byref(src), 1, C.byref(job), 1, step, flags, out,
+                          0x3000, ws_bytes, None)
+
+
+def test_primary_rejects_bad_arguments_on_the_host(abi):
+    vol, phys, src, geom = _valid_structs(abi)
+    msg = lambda: abi.lib().gdrr_last_error().decode()
+    assert _call_primary(abi, vol, phys, src, geom, flags=2) == abi.GDRR_EINVAL and "only" in msg()
+    assert _call_primary(abi, vol, phys, src, geom, step=1e-6) == abi.GDRR_EINVAL and "2^20" in msg()
+    assert _call_primary(abi, vol, phys, src, geom, step=float("nan")) == abi.GDRR_EINVAL
+    assert _call_primary(abi, vol, phys, src, geom, ws_bytes=16) == abi.GDRR_EINVAL and "workspace" in msg()
+    assert _call_primary(abi, vol, phys, src, geom, out=None) == abi.GDRR_EINVAL
+    bad = abi.Source(1, 0x1000, 0x1000, 15, 12, 0x1000)
+    assert _call_primary(abi, vol, phys, bad, geom) == abi.GDRR_EINVAL and "fluence grid" in msg()
+    job = abi.Job()
+    job.volume, job.source, job.geom = 0, 0, geom
+    n = abi.lib().gdrr_primary_workspace(C.byref(vol), 1, C.byref(phys), C.byref(src), 1, C.byref(job), 1)
+    assert n > 64 * 9 * 9 * 9

@@ -1,0 +1,206 @@
+"""GPU parity of the ray-tracing primary (Sec. 2.3, Eq. 1) against the CPU
+oracle's ray tracer on the same inputs, pixel by pixel: several 16 x 16 tiles
+with ragged edges, several energy channels, materials and a response; the
+batched call against single calls; the full-size detector and phantoms of the
+multi-phantom workload on sampled pixels; accumulation and the empty phantom;
+and the MC primary tally against the ray tracer (same mean)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1204_6367_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+# float32 march against the float64 oracle: the line integrals carry a
+# relative rounding of about sqrt(n) 2^-24 over n <= 2^12 terms, the sample
+# positions (|x| <= 2 SAD) about 2^-23 |x| of absolute error, and the optical
+# depth tau = 0.1 sum_m mu_m L_m multiplies both into an absolute error of P/P
+# below 1e-5 (1 + tau) for the depths here (tau < 12).
+RTOL = 1e-5
+ATOL_REL = 1e-9          # of the image maximum, for pixels in deep shadow
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1204_6367_amd import api
+    return api
+
+
+def mixed_problem(seed=3, shape=(20, 24, 28), spacing=(3.0, 2.5, 2.0), nu=40, nv=27, du=7.0, phi=0.7,
+                  n_spec=24, response=True):
+    rng = np.random.default_rng(seed)
+    names = ["air", "soft_tissue", "bone", "lung"]
+    ph = W.ellipsoid_phantom(shape, spacing, seed, n_inner=6)
+    dens = (ph.density * rng.uniform(0.8, 1.2, ph.shape)).astype(np.float32)
+    ph = W.Phantom(dens, ph.material, ph.spacing_mm, names)
+    geom = W.Geometry(phi_rad=phi, theta_rad=0.02, nu=nu, nv=nv, du_mm=du, dv_mm=du)
+    e = np.linspace(20.0, 118.3, n_spec).astype(np.float32)
+    p = rng.uniform(0.2, 1.0, n_spec).astype(np.float32)
+    flu = rng.uniform(0.5, 1.5, (nv, nu)).astype(np.float32)
+    grid = W.EnergyGrid()
+    resp = (0.9 * (grid.e0_kev + grid.de_kev * np.arange(grid.n_e)) ** 0.95).astype(np.float32) if response else None
+    return W.Problem(ph, W.physics_for(ph, grid, resp), W.Source(e, p, flu), geom, 0)
+
+
+def check_image(g, o, label):
+    tol = RTOL * o * (1.0 + tau_of(o)) + ATOL_REL * o.max()
+    err = np.abs(g - o)
+    worst = float((err / np.maximum(o, 1e-300)).max())
+    log(label, "max rel err", worst, "pixels over tol", int((err > tol).sum()))
+    assert (err <= tol).all(), label
+
+
+def tau_of(o):
+    # rough optical depth from the image itself (shadow depth relative to the brightest pixel)
+    return np.maximum(0.0, -np.log(np.maximum(o / o.max(), 1e-30)))
+
+
+def test_raytrace_matches_oracle_interpolated(gpu):
+    import oracle
+    prob = mixed_problem()
+    vol, phys, src = gpu.upload(prob)
+    log("raytrace interp nu=40 nv=27")
+    g = gpu.primary(vol, phys, src, prob.geom, interp=True).cpu().numpy()
+    o = oracle.primary_raytrace(oracle.Problem.from_workload(prob), interp=True)
+    assert g.shape == o.shape == (27, 40)
+    check_image(g, o, "interp")
+
+
+@pytest.mark.parametrize("step", [0.37, 4.0])
+def test_raytrace_explicit_step(gpu, step):
+    import oracle
+    prob = mixed_problem(seed=4, nu=33, nv=17, phi=2.5)
+    vol, phys, src = gpu.upload(prob)
+    log("raytrace step", step)
+    g = gpu.primary(vol, phys, src, prob.geom, interp=True, step_mm=step).cpu().numpy()
+    o = oracle.primary_raytrace(oracle.Problem.from_workload(prob), interp=True, dl=step)
+    check_image(g, o, f"step {step}")
+
+
+def test_raytrace_interpolation_off(gpu):
+    """Voxel-constant attenuation: a sample point within float32 rounding of a
+    voxel face may take the neighbour's value on one side, so a few pixels may
+    differ by one interval of one voxel's attenuation; all others are held to
+    the same tolerance as the interpolated march."""
+    import oracle
+    prob = mixed_problem(seed=5)
+    vol, phys, src = gpu.upload(prob)
+    log("raytrace interp off")
+    g = gpu.primary(vol, phys, src, prob.geom, interp=False).cpu().numpy()
+    o = oracle.primary_raytrace(oracle.Problem.from_workload(prob), interp=False)
+    tol = RTOL * o * (1.0 + tau_of(o)) + ATOL_REL * o.max()
+    bad = np.abs(g - o) > tol
+    log("interp off: pixels over tol", int(bad.sum()), "of", o.size)
+    assert bad.mean() <= 0.02
+    # one interval (half a voxel edge) of the densest voxel at the lowest channel energy
+    grid = W.EnergyGrid()
+    eg = grid.e0_kev + grid.de_kev * np.arange(grid.n_e)
+    e_lo = float(prob.source.spec_e.min())
+    tot = prob.physics.mu_mass.astype(np.float64).sum(-1)
+    mu_max = max(np.interp(e_lo, eg, t) for t in tot) * float(prob.phantom.density.max())
+    step = 0.5 * min(prob.phantom.spacing_mm)
+    assert (np.abs(g - o) <= o * (math.exp(0.1 * mu_max * step) - 1.0) + tol).all()
+
+
+def test_batch_equals_single_calls(gpu):
+    import torch
+    a = mixed_problem(seed=6, nu=40, nv=27)
+    b = mixed_problem(seed=7, shape=(16, 18, 22), spacing=(4.0, 3.0, 3.5), nu=40, nv=27, response=True)
+    va, pa, sa = gpu.upload(a)
+    vb, _, sb = gpu.upload(b)
+    jobs = [gpu.JobSpec(a.geom.replace(phi_rad=p), 0, k, volume=k % 2, source=(k // 2) % 2)
+            for k, p in enumerate([0.0, 0.9, 2.0, 3.3, 5.1])]
+    bt = gpu.Batch([va, vb], pa, [sa, sb], jobs)
+    log("raytrace batch of 5")
+    imgs = bt.primary(interp=True)
+    for j, img in zip(jobs, imgs):
+        vol = [va, vb][j.volume]
+        src = [sa, sb][j.source]
+        one = gpu.primary(vol, pa, src, j.geom, interp=True)
+        assert torch.equal(img, one)
+    # accumulate adds on top
+    out = torch.cat([i.reshape(-1) for i in imgs]).clone()
+    again = bt.primary(interp=True, accumulate=True, out=out)
+    for x, y in zip(again, imgs):
+        assert torch.allclose(x, 2.0 * y, rtol=1e-15, atol=0)
+
+
+def test_empty_phantom_gives_the_unattenuated_signal(gpu):
+    prob = mixed_problem(seed=8)
+    prob.phantom.density[:] = 0.0
+    vol, phys, src = gpu.upload(prob)
+    g = gpu.primary(vol, phys, src, prob.geom).cpu().numpy()
+    s = prob.source
+    e = s.spec_e.astype(np.float64)
+    grid = W.EnergyGrid()
+    eg = grid.e0_kev + grid.de_kev * np.arange(grid.n_e)
+    r = np.interp(e, eg, prob.physics.response.astype(np.float64))
+    w = s.fluence.astype(np.float64) / s.fluence.astype(np.float64).sum()
+    expect = w * float((s.spec_p.astype(np.float64) / s.spec_p.astype(np.float64).sum() * r).sum())
+    assert np.allclose(g, expect, rtol=1e-6, atol=0)
+
+
+FULL = [
+    ("multi-512x512x256", 0, 1.3),
+    ("multi-256x256x160", 1, 2.1),
+    ("multi-128x128x64", 2, 4.0),
+]
+
+
+@pytest.mark.parametrize("label,idx,phi", FULL, ids=[c[0] for c in FULL])
+def test_full_size_sampled_pixels(gpu, label, idx, phi):
+    """The benchmark's detector, spectrum and phantoms: the whole image on the
+    GPU (the launch the benchmark times), 300 sampled pixels in the oracle."""
+    import oracle
+    log("raytrace full size", label)
+    ph = W.ellipsoid_phantom(*W.MULTI_PHANTOMS[idx][:3])
+    geom = W.Geometry(**W.PELVIS_DET).replace(phi_rad=phi)
+    prob = W.Problem(ph, W.physics_for(ph), W.pelvis_source(geom), geom, 0)
+    vol, phys, src = gpu.upload(prob)
+    g = gpu.primary(vol, phys, src, geom).cpu().numpy().ravel()
+    rng = np.random.default_rng(idx + 50)
+    pix = rng.choice(geom.nu * geom.nv, 300, replace=False)
+    o = oracle.primary_raytrace(oracle.Problem.from_workload(prob, phi_rad=phi), pixels=pix)
+    check_image(g[pix], o, label)
+
+
+def test_mc_primary_agrees_with_ray_tracing(gpu):
+    """One material, a smooth density that falls to zero inside the box: the
+    MC's expected primary tally is the pixel average of Eq. 1, the ray tracer
+    its value at the pixel centre; at 1e7 photons their difference is
+    statistical (the pixel-curvature term is far below one sigma here)."""
+    n = 10_000_000
+    shape = (40, 40, 40)
+    c = (np.arange(40) + 0.5 - 20) * 2.5
+    Z, Y, X = np.meshgrid(c, c, c, indexing="ij")
+    r2 = X * X + Y * Y + Z * Z
+    dens = np.clip(1.2 * (np.exp(-r2 / 28.0**2) - math.exp(-(50.0 / 28.0) ** 2)), 0.0, None).astype(np.float32)
+    ph = W.Phantom(dens, np.zeros(shape, np.uint8), (2.5, 2.5, 2.5), ["water"])
+    geom = W.Geometry(phi_rad=0.4, nu=64, nv=48, du_mm=4.0, dv_mm=4.0)
+    src = W.Source(*W.mono_spectrum(60.0), W.fluence_map(geom))
+    prob = W.Problem(ph, W.physics_for(ph), src, geom, n)
+    vol, phys, dsrc = gpu.upload(prob)
+    log("mc vs raytrace n", n)
+    t = gpu.project(vol, phys, dsrc, geom, n, seed=3).cpu().numpy()
+    rt = gpu.primary(vol, phys, dsrc, geom, step_mm=0.2).cpu().numpy()
+    var = np.maximum(t[1] - t[0] ** 2, 0.0) / n
+    hits = np.where(t[1] > 0, t[0] ** 2 / np.maximum(t[1], 1e-300), 0.0) * n
+    sel = hits >= 100
+    z = (t[0] - rt) / np.sqrt(var + 1e-300)
+    sig_tot = math.sqrt(var.sum())
+    d_tot = float(t[0].sum() - rt.sum())
+    log("max |z|", float(np.abs(z[sel]).max()), "pixels", int(sel.sum()), "total diff / sigma", d_tot / sig_tot)
+    assert sel.sum() > 1000
+    assert np.abs(z[sel]).max() < 5.0
+    assert abs(d_tot) < 4.0 * sig_tot
