@@ -9,8 +9,10 @@ adjoint.  Inputs are resident in HBM before the timed region.  Prints ONE
 JSON line with the whole-step histories/s, the roofline of the transport
 kernel (timed with HIP events on its own stream, inside the library) and the
 CPU oracle timed on a bounded sample of the same workload.  Beside the step,
-outside its timing, the ray-tracing primary (Eq. 1) of the same jobs is timed
-and reported under "raytrace" with its own roofline and oracle rate.
+outside its timing, the ray-tracing primary (Eq. 1) of the same jobs, the
+denoising of the step's scatter tallies (Eq. 5) and the noise assembly
+(Sec. 2.6) are timed and reported under "raytrace" and "denoise" with their
+own rooflines and oracle rates.
 
 Workloads (synthetic, seeded; sizes of the paper's CBCT setting):
   c1  one projection: 256x256x160 ellipsoid phantom, 120 kVp + bowtie, 1e8 photons
@@ -143,6 +145,7 @@ def build_workload(name, api, W, torch):
 
         samples = [(prob, float(jobs[k].geom.phi_rad), jobs[k].job_id) for k in (0, len(jobs) // 2)]
         return dict(step=step, fwd=fwd, adj=0, samples=samples, adjoint=None, batch=batch, prob_of=lambda k: prob,
+                    tallies=tallies,
                     config=dict(workload=name, phantom="256x256x160 @1.95x1.95x2.5mm ellipsoids",
                                 angles=len(jobs), photons_per_angle=jobs[0].n_photons,
                                 detector="256x192 @1.552mm", spectrum="120 kVp Kramers + 2.5 mm Al, bowtie 30 mm Al",
@@ -225,7 +228,7 @@ def build_workload(name, api, W, torch):
             return W.Problem(phantoms[jobs[k].volume][0], physw, srcw, jobs[k].geom, 0)
 
         return dict(step=step, fwd=fwd, adj=adjh, samples=samples, adjoint=adjoint, config=cfg, batch=batch,
-                    prob_of=prob_of)
+                    prob_of=prob_of, tallies=tallies)
     raise SystemExit(f"unknown workload {name}")
 
 
@@ -314,6 +317,62 @@ def raytrace_leg(wl, api, torch, steps, cpu):
 
 
 # ---------------------------------------------------------------------------
+# Scatter denoising (Eq. 5) and noise assembly (Sec. 2.6) of the step's tallies
+# ---------------------------------------------------------------------------
+DENOISE_ITERS = 256
+SLOTS_DN_SWEEP = 13            # per pixel and sweep: 3 adds, reciprocal (4), mul, sub, 2 FMA, mul, max
+BYTES_NOISE = 6 * 8            # Phat, P, Shat, S read; noise, image written
+
+
+def denoise_leg(wl, api, torch, steps, rt_images, cpu):
+    batch = wl["batch"]
+    g = batch.jobs[0].geom
+    if any((j.geom.nu, j.geom.nv) != (g.nu, g.nv) for j in batch.jobs):
+        return None
+    n = len(batch.jobs)
+    tal = wl["tallies"].view(n, 4, g.nv, g.nu)
+    shat = tal[:, 2]
+    med = float(shat.median())
+    beta = 4.0 / max(med, 1e-30)                       # beta * S ~ 4: smoothing over a few pixels
+    floor = 1e-6 * max(med, 1e-30)
+    p = torch.stack(rt_images) if rt_images is not None else torch.zeros(n, g.nv, g.nu, dtype=torch.float64,
+                                                                             device="cuda")
+    alpha = api.noise_scale(float(batch.jobs[0].n_photons), 5.2913e9, 0.6)
+    api.denoise(shat, beta, DENOISE_ITERS, s_floor=floor)
+    ms, wall_n = [], []
+    for _ in range(max(steps, 1)):
+        s_den = api.denoise(shat, beta, DENOISE_ITERS, s_floor=floor)
+        ms.append(api.last_kernel_ms())
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        api.noise(tal[:, 0], p, shat, s_den, alpha)
+        torch.cuda.synchronize()
+        wall_n.append((time.perf_counter() - t) * 1e3)
+    kms = float(np.mean(ms))
+    px = n * g.nu * g.nv
+    slots = px * DENOISE_ITERS * SLOTS_DN_SWEEP / (kms * 1e-3) / 1e12
+    nms = float(np.min(wall_n))
+    out = dict(images=n, iters=DENOISE_ITERS, omega=0.8, beta_times_median=4.0, kernel_ms=round(kms, 3),
+               pixel_sweeps_per_s=round(px * DENOISE_ITERS / (kms * 1e-3), 1),
+               roofline=dict(bound="alu", achieved=round(slots, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Tops/s",
+                             frac=round(slots / ALU_PEAK_TOPS, 4), traffic=None),
+               noise=dict(wall_ms=round(nms, 3), alpha=round(alpha, 6),
+                          roofline=dict(bound="hbm", achieved=round(px * BYTES_NOISE / (nms * 1e-3) / 1e9, 1),
+                                        peak=HBM_PEAK_GBS, unit="GB/s",
+                                        frac=round(px * BYTES_NOISE / (nms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                        traffic=None)))
+    if cpu:
+        import oracle
+        img = shat[0].cpu().numpy()
+        t = time.time()
+        oracle.denoise(img, beta, DENOISE_ITERS, s_floor=floor)
+        dt = time.time() - t
+        out["cpu_baseline"] = dict(value=round(g.nu * g.nv * DENOISE_ITERS / dt, 1), unit="pixel sweeps/s",
+                                   cores=1, kind="oracle", sample=f"1 image of {g.nv}x{g.nu}, {DENOISE_ITERS} sweeps")
+    return out
+
+
+# ---------------------------------------------------------------------------
 # CPU baseline: the oracle as it stands, on a bounded sample
 # ---------------------------------------------------------------------------
 def cpu_baseline(wl, budget_s=20.0):
@@ -372,7 +431,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c4", choices=["c1", "c2", "c3", "c4"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-raytrace", action="store_true", help="skip the ray-tracing primary leg")
+    ap.add_argument("--no-raytrace", action="store_true",
+                    help="skip the ray-tracing, denoising and noise legs")
     ap.add_argument("--tune", default="auto", choices=["auto", "default"],
                     help="auto: autotune the launch shape before timing; default: library defaults")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -423,6 +483,8 @@ def main():
     adj_ms = float(np.mean([k[1] for k in kms])) if wl["adj"] else None
 
     rt = None if args.no_raytrace else raytrace_leg(wl, api, torch, args.steps, not args.no_cpu_baseline)
+    dn = None if args.no_raytrace else denoise_leg(wl, api, torch, args.steps, wl["batch"].primary(),
+                                                   not args.no_cpu_baseline)
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
     roof = None
     extra = {}
@@ -456,7 +518,7 @@ def main():
                 fwd_histories_per_s=round(wl["fwd"] / (fwd_ms * 1e-3), 1),
                 adj_histories_per_s=round(wl["adj"] / (adj_ms * 1e-3), 1) if adj_ms else None,
                 transport_kernel_ms=round(fwd_ms, 3), adjoint_kernel_ms=round(adj_ms, 3) if adj_ms else None,
-                **extra, raytrace=rt)
+                **extra, raytrace=rt, denoise=dn)
     print(json.dumps(line), flush=True)
 
 

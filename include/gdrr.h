@@ -12,8 +12,10 @@
  * add r(E) to a primary or a scatter tally per pixel depending on whether they
  * scattered.  Tallies are per source photon (Sec. 2.6).  It also offers the
  * gradient of a loss of the tallies with respect to voxel densities (path
- * replay of the same random numbers; not in the paper) and Step 1, the
- * primary signal by tri-linear ray tracing (Sec. 2.3, Eq. 1).
+ * replay of the same random numbers; not in the paper), Step 1, the
+ * primary signal by tri-linear ray tracing (Sec. 2.3, Eq. 1), and Steps 3
+ * and 4, the Poisson denoising of the scatter (Sec. 2.5) and the noise of a
+ * scan at a given mAs (Sec. 2.6).
  *
  * Conventions (the paper leaves them open; these are the library's reading):
  *  - lengths in mm, energies in keV, mass attenuation in cm^2/g, density in
@@ -237,6 +239,38 @@ int gdrr_primary(const gdrr_volume* vols, int32_t n_vols, const gdrr_physics* ph
                  double* out, void* workspace, size_t ws_bytes, void* stream);
 size_t gdrr_primary_workspace(const gdrr_volume* vols, int32_t n_vols, const gdrr_physics* phys,
                               const gdrr_source* srcs, int32_t n_srcs, const gdrr_job* jobs, int32_t n_jobs);
+
+/*
+ * Scatter denoising (Sec. 2.5): n_img iterations of Eq. 5,
+ *   S'(i,j) = (1 - omega) S(i,j) + (omega/4) [S(i-1,j) + S(i+1,j) + S(i,j-1)
+ *             + S(i,j+1) - (1/beta) (1 - Shat(i,j) / S(i,j))],
+ * every value on the right from the previous iterate, S^(0) = Shat (the
+ * paper uses omega = 0.8).  A neighbour beyond the detector edge is the pixel
+ * itself; the data term is 1 where Shat = 0; iterates are held >= s_floor > 0.
+ * Arithmetic is float32 (images of up to 2^24 counts keep 7 digits).
+ * shat: image k is [nv][nu] doubles at shat + k * shat_stride (0 = nv*nu), so
+ * plane 2 of a batch's tallies can be passed in place (stride 4 nv nu);
+ * out: [n_img][nv][nu] doubles, not overlapping shat.  iters <= 2^20 (0 copies
+ * max(Shat, s_floor)).  Workspace: gdrr_denoise_workspace() bytes.  The timing
+ * hook brackets all passes.
+ */
+int gdrr_denoise(const double* shat, int64_t shat_stride, int32_t n_img, int32_t nv, int32_t nu, float beta,
+                 float omega, int32_t iters, float s_floor, double* out, void* workspace, size_t ws_bytes,
+                 void* stream);
+size_t gdrr_denoise_workspace(int32_t n_img, int32_t nv, int32_t nu);
+
+/*
+ * Noise of a simulated scan (Sec. 2.6): per pixel
+ *   noise = alpha ((Phat - P) + (Shat - S)),   image = P + S + noise,
+ * Phat, Shat the MC primary and scatter tallies, P the ray-traced primary, S
+ * the denoised scatter, alpha = sqrt(n_sim / (zeta I)) for n_sim simulated
+ * source photons, zeta source photons per mAs and I mAs.  Phat and Shat may
+ * be strided like gdrr_denoise's input (image k at + k * stride, 0 = npix);
+ * P, S, noise and image are [n_img][npix] doubles; noise or image may be NULL.
+ */
+int gdrr_noise(int32_t n_img, int64_t npix, const double* phat, int64_t phat_stride, const double* p,
+               const double* shat, int64_t shat_stride, const double* s, double alpha, double* noise,
+               double* image, void* stream);
 
 /*
  * Timing hook (autotuner, benchmarks): while enabled, the transport kernel of

@@ -86,6 +86,11 @@ SIGNATURES = {
                                C.c_float, C.c_uint32, _vp, _vp, _sz, _vp]),
     "gdrr_primary_workspace": (_sz, [_P(Volume), C.c_int32, _P(Physics), _P(Source), C.c_int32, _P(Job),
                                      C.c_int32]),
+    "gdrr_denoise": (C.c_int, [_vp, C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_int32,
+                               C.c_float, _vp, _vp, _sz, _vp]),
+    "gdrr_denoise_workspace": (_sz, [C.c_int32, C.c_int32, C.c_int32]),
+    "gdrr_noise": (C.c_int, [C.c_int32, C.c_int64, _vp, C.c_int64, _vp, _vp, C.c_int64, _vp, C.c_double, _vp, _vp,
+                             _vp]),
     "gdrr_enable_timing": (C.c_int, [C.c_int]),
     "gdrr_last_kernel_ms": (C.c_int, [_P(C.c_float)]),
     "gdrr_default_tuning": (C.c_int, [_P(Tuning)]),

@@ -173,6 +173,58 @@ def primary(vol: DeviceVolume, phys: DevicePhysics, src: DeviceSource, geom, int
                      stream=stream)[0]
 
 
+def _image_stack(x: torch.Tensor, name: str):
+    """(tensor, n, nv, nu, image stride) of [n][nv][nu] or [nv][nu] float64 images whose rows are contiguous."""
+    if x.dim() == 2:
+        x = x.unsqueeze(0)
+    if x.dim() != 3 or x.dtype != torch.float64 or not x.is_cuda:
+        raise ValueError(f"{name}: expected float64 [n][nv][nu] or [nv][nu] on the GPU")
+    n, nv, nu = x.shape
+    if x.stride(2) != 1 or (nv > 1 and x.stride(1) != nu):
+        raise ValueError(f"{name}: each image must be a contiguous [nv][nu] block")
+    return x, n, nv, nu, x.stride(0) if n > 1 else nv * nu
+
+
+def denoise(shat: torch.Tensor, beta: float, iters: int, omega: float = 0.8, s_floor: float = 1e-6,
+            out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Eq. 5 (Sec. 2.5) on float64 images [n][nv][nu] (or [nv][nu]); the images may be
+    strided views such as plane 2 of a batch's tallies.  Returns [n][nv][nu] float64."""
+    L = _abi.lib()
+    x, n, nv, nu, stride = _image_stack(shat, "shat")
+    if out is None:
+        out = torch.empty(n, nv, nu, dtype=torch.float64, device=x.device)
+    ws = torch.empty(int(L.gdrr_denoise_workspace(n, nv, nu)), dtype=torch.uint8, device=x.device)
+    _abi.check(L.gdrr_denoise(x.data_ptr(), stride, n, nv, nu, float(beta), float(omega), int(iters),
+                              float(s_floor), out.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)))
+    return out if shat.dim() == 3 else out[0]
+
+
+def noise(phat: torch.Tensor, p: torch.Tensor, shat: torch.Tensor, s: torch.Tensor, alpha: float,
+          stream=None):
+    """Sec. 2.6: (N, P + S + N) with N = alpha ((Phat - P) + (Shat - S)), float64 images."""
+    L = _abi.lib()
+    ph, n, nv, nu, sp = _image_stack(phat, "phat")
+    sh, n2, nv2, nu2, ss = _image_stack(shat, "shat")
+    pc = p.reshape(n, nv, nu).contiguous()
+    sc = s.reshape(n, nv, nu).contiguous()
+    if (n2, nv2, nu2) != (n, nv, nu) or pc.dtype != torch.float64 or sc.dtype != torch.float64:
+        raise ValueError("noise: images must agree in shape and be float64")
+    nz = torch.empty(n, nv, nu, dtype=torch.float64, device=ph.device)
+    img = torch.empty_like(nz)
+    _abi.check(L.gdrr_noise(n, nv * nu, ph.data_ptr(), sp, pc.data_ptr(), sh.data_ptr(), ss, sc.data_ptr(),
+                            float(alpha), nz.data_ptr(), img.data_ptr(), _stream(stream)))
+    if phat.dim() == 2:
+        return nz[0], img[0]
+    return nz, img
+
+
+def noise_scale(n_sim: float, zeta: float, mas: float) -> float:
+    """alpha = sqrt(n_sim / (zeta I)) of Sec. 2.6 (I in mAs, zeta source photons per mAs)."""
+    if not (n_sim > 0 and zeta > 0 and mas > 0):
+        raise ValueError("n_sim, zeta and mAs must be > 0")
+    return float(np.sqrt(n_sim / (zeta * mas)))
+
+
 def enable_timing(on: bool = True):
     """Bracket every transport-kernel launch with HIP events on its stream."""
     _abi.check(_abi.lib().gdrr_enable_timing(1 if on else 0))

@@ -13,6 +13,7 @@
 #include "gdrr_kernels.h"
 #include "gdrr_queue.h"
 #include "gdrr_raytrace.h"
+#include "gdrr_denoise.h"
 
 using namespace gdrr;
 
@@ -172,14 +173,17 @@ Launch make_launch(const void* f, dim3 g, dim3 b, size_t sh, const P& p) {
     return L;
 }
 
-// `timed` is the index of the launch to bracket with `ev` (-1: none).
-int run_direct(std::vector<Launch>& ls, hipStream_t st, int timed = -1, TimeEvents* ev = nullptr) {
+// Launches [timed, timed_last] are bracketed with `ev` (timed = -1: none;
+// timed_last = -1: the single launch `timed`).
+int run_direct(std::vector<Launch>& ls, hipStream_t st, int timed = -1, TimeEvents* ev = nullptr,
+               int timed_last = -1) {
+    if (timed_last < 0) timed_last = timed;
     for (size_t i = 0; i < ls.size(); ++i) {
         Launch& L = ls[i];
         void* a[1] = {L.args.data()};
         if ((int)i == timed) GDRR_HIP(hipEventRecord(ev->a, st));
         GDRR_HIP(hipLaunchKernel(L.func, L.grid, L.block, a, L.shmem, st));
-        if ((int)i == timed) {
+        if (timed >= 0 && (int)i == timed_last) {
             GDRR_HIP(hipEventRecord(ev->b, st));
             ev->recorded = true;
         }
@@ -873,6 +877,64 @@ int run_primary(const gdrr_volume* vols, int n_vols, const gdrr_physics* phys, c
     return run_direct(ls, st, ev ? timed : -1, ev);
 }
 
+// --------------------------------------------------------------------------
+// Denoising (Eq. 5) and noise assembly (Sec. 2.6).
+// --------------------------------------------------------------------------
+bool ranges_overlap(const void* a, size_t a_bytes, const void* b, size_t b_bytes) {
+    const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+    return a0 < b0 + b_bytes && b0 < a0 + a_bytes;
+}
+
+size_t dn_buffer_bytes(int n_img, int nv, int nu) {
+    return ((size_t)n_img * nv * nu * sizeof(float) + 255) & ~(size_t)255;
+}
+
+int run_denoise(const double* shat, long long stride, int n_img, int nv, int nu, float beta, float omega, int iters,
+                float s_floor, double* out, void* ws, size_t ws_bytes, hipStream_t st) {
+    if (!shat || !out) return fail(GDRR_EINVAL, "shat / out is NULL");
+    if (n_img < 1 || nv < 1 || nu < 1) return fail(GDRR_EINVAL, "n_img, nv and nu must be >= 1");
+    const long long npix = (long long)nv * nu;
+    if (stride == 0) stride = npix;
+    if (stride < npix) return fail(GDRR_EINVAL, "shat_stride must be 0 or >= nv * nu");
+    if (!(beta > 0.0f) || !std::isfinite(beta)) return fail(GDRR_EINVAL, "beta must be finite and > 0");
+    if (!(omega > 0.0f && omega < 2.0f)) return fail(GDRR_EINVAL, "omega must be in (0, 2)");
+    if (iters < 0 || iters > (1 << 20)) return fail(GDRR_EINVAL, "iters must be in [0, 2^20]");
+    if (!(s_floor > 0.0f) || !std::isfinite(s_floor)) return fail(GDRR_EINVAL, "s_floor must be finite and > 0");
+    const int tiles_u = (nu + kDnTileU - 1) / kDnTileU, tiles_v = (nv + kDnTileV - 1) / kDnTileV;
+    if ((long long)n_img * tiles_u * tiles_v >= (1ll << 31)) return fail(GDRR_EINVAL, "too many tiles in one call");
+    const size_t in_bytes = ((size_t)(n_img - 1) * (size_t)stride + (size_t)npix) * sizeof(double);
+    const size_t out_bytes = (size_t)n_img * (size_t)npix * sizeof(double);
+    if (ranges_overlap(shat, in_bytes, out, out_bytes)) return fail(GDRR_EINVAL, "out must not overlap shat");
+    const size_t buf = dn_buffer_bytes(n_img, nv, nu);
+    if (!ws || ws_bytes < 2 * buf + 256) return fail(GDRR_EINVAL, "workspace too small: need " + std::to_string(2 * buf + 256) + " bytes");
+    char* wsa = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+    float* pp[2] = {(float*)wsa, (float*)(wsa + buf)};
+    std::vector<Launch> ls;
+    const int passes = std::max(1, (iters + kDnHalo - 1) / kDnHalo);
+    for (int p = 0; p < passes; ++p) {
+        DnParams d{};
+        d.shat = shat;
+        d.shat_stride = stride;
+        d.s_in = p == 0 ? nullptr : pp[p & 1];
+        d.s_out = p + 1 == passes ? nullptr : pp[(p + 1) & 1];
+        d.out = p + 1 == passes ? out : nullptr;
+        d.n_img = n_img; d.nv = nv; d.nu = nu; d.tiles_u = tiles_u; d.tiles_v = tiles_v;
+        d.iters = std::min(kDnHalo, iters - p * kDnHalo);
+        d.omega = omega;
+        d.inv_beta = 1.0f / beta;
+        d.s_floor = s_floor;
+        ls.push_back(make_launch((const void*)&denoise_kernel, dim3((unsigned)(n_img * tiles_u * tiles_v)),
+                                 dim3(kDnBlock), 0, d));
+    }
+    TimeEvents* ev = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_time_mu);
+        int rc;
+        if (g_timing && (rc = timing_events(&ev))) return rc;
+    }
+    return run_direct(ls, st, ev ? 0 : -1, ev, ev ? (int)ls.size() - 1 : -1);
+}
+
 gdrr_job single_job(const gdrr_geometry* geom, uint64_t n, uint32_t job_id) {
     gdrr_job j{};
     j.volume = 0;
@@ -1024,6 +1086,35 @@ int gdrr_primary(const gdrr_volume* vols, int32_t n_vols, const gdrr_physics* ph
                  void* workspace, size_t ws_bytes, void* stream) {
     return run_primary(vols, n_vols, phys, srcs, n_srcs, jobs, n_jobs, step_mm, flags, out, workspace, ws_bytes,
                        (hipStream_t)stream);
+}
+
+size_t gdrr_denoise_workspace(int32_t n_img, int32_t nv, int32_t nu) {
+    if (n_img < 1 || nv < 1 || nu < 1) return 0;
+    return 2 * dn_buffer_bytes(n_img, nv, nu) + 256;
+}
+
+int gdrr_denoise(const double* shat, int64_t shat_stride, int32_t n_img, int32_t nv, int32_t nu, float beta,
+                 float omega, int32_t iters, float s_floor, double* out, void* workspace, size_t ws_bytes,
+                 void* stream) {
+    return run_denoise(shat, shat_stride, n_img, nv, nu, beta, omega, iters, s_floor, out, workspace, ws_bytes,
+                       (hipStream_t)stream);
+}
+
+int gdrr_noise(int32_t n_img, int64_t npix, const double* phat, int64_t phat_stride, const double* p,
+               const double* shat, int64_t shat_stride, const double* s, double alpha, double* noise,
+               double* image, void* stream) {
+    if (!phat || !p || !shat || !s) return fail(GDRR_EINVAL, "input pointer is NULL");
+    if (n_img < 1 || npix < 1) return fail(GDRR_EINVAL, "n_img and npix must be >= 1");
+    if (phat_stride == 0) phat_stride = npix;
+    if (shat_stride == 0) shat_stride = npix;
+    if (phat_stride < npix || shat_stride < npix) return fail(GDRR_EINVAL, "strides must be 0 or >= npix");
+    if (!std::isfinite(alpha)) return fail(GDRR_EINVAL, "alpha must be finite");
+    NoiseParams q{phat, phat_stride, p, shat, shat_stride, s, alpha, noise, image, npix, n_img};
+    const long long total = npix * (long long)n_img;
+    const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>(8192, (total + 255) / 256));
+    void* a[1] = {&q};
+    GDRR_HIP(hipLaunchKernel((const void*)&noise_kernel, dim3(grid), dim3(256), a, 0, (hipStream_t)stream));
+    return GDRR_OK;
 }
 
 int gdrr_mc_trace(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr_source* src,

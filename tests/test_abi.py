@@ -163,3 +163,25 @@ def test_primary_rejects_bad_arguments_on_the_host(abi):
     job.volume, job.source, job.geom = 0, 0, geom
     n = abi.lib().gdrr_primary_workspace(C.byref(vol), 1, C.byref(phys), C.byref(src), 1, C.byref(job), 1)
     assert n > 64 * 9 * 9 * 9
+
+
+def test_denoise_and_noise_reject_bad_arguments_on_the_host(abi):
+    L = abi.lib()
+    msg = lambda: L.gdrr_last_error().decode()
+    ws = L.gdrr_denoise_workspace(3, 20, 30)
+    assert ws >= 2 * 3 * 20 * 30 * 4
+    dn = lambda shat=0x10000, stride=0, n=3, beta=1.0, omega=0.8, it=10, fl=1e-6, out=0x100000, wsb=ws: \
+        L.gdrr_denoise(shat, stride, n, 20, 30, beta, omega, it, fl, out, 0x3000, wsb, None)
+    assert dn(beta=0.0) == abi.GDRR_EINVAL and "beta" in msg()
+    assert dn(omega=2.5) == abi.GDRR_EINVAL and "omega" in msg()
+    assert dn(it=-1) == abi.GDRR_EINVAL
+    assert dn(fl=0.0) == abi.GDRR_EINVAL and "s_floor" in msg()
+    assert dn(stride=100) == abi.GDRR_EINVAL and "stride" in msg()
+    assert dn(out=0x10000 + 8) == abi.GDRR_EINVAL and "overlap" in msg()
+    assert dn(wsb=16) == abi.GDRR_EINVAL and "workspace" in msg()
+    assert dn(shat=None) == abi.GDRR_EINVAL
+    nz = lambda n=2, npix=100, ps=0, alpha=1.0: L.gdrr_noise(n, npix, 0x1000, ps, 0x2000, 0x3000, 0, 0x4000, alpha,
+                                                             0x5000, None, None)
+    assert nz(npix=0) == abi.GDRR_EINVAL
+    assert nz(ps=50) == abi.GDRR_EINVAL and "stride" in msg()
+    assert nz(alpha=float("inf")) == abi.GDRR_EINVAL

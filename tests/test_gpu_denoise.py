@@ -1,0 +1,104 @@
+"""GPU parity of the scatter denoising (Sec. 2.5, Eq. 5) and the noise
+assembly (Sec. 2.6) against the CPU oracle on the same images: iteration
+counts across the LDS passes (0, 1, one pass, one pass + 1, many), ragged
+image sizes over several tiles, zeros in the data, strided input (plane 2 of
+a batch's tallies), and the full detector of the benchmark."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+# float32 sweeps against the float64 oracle: each sweep rounds at a few units
+# of 2^-24 relative and the map does not expand differences in the stable
+# range of beta used here, so after K sweeps the difference stays below
+# about (K + 2) 2^-22 of the image scale.
+def tol_of(o, k):
+    return (k + 2) * 2.0**-22 * float(np.abs(o).max())
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1204_6367_amd import api
+    return api
+
+
+def poisson_images(seed, n, nv, nu, mean=150.0):
+    rng = np.random.default_rng(seed)
+    y, x = np.mgrid[0:nv, 0:nu]
+    out = []
+    for k in range(n):
+        lam = mean * (1.0 + 0.5 * np.sin(x / (7.0 + k)) * np.cos(y / 9.0))
+        out.append(rng.poisson(lam).astype(np.float64))
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("iters", [0, 1, 8, 9, 40])
+def test_denoise_matches_oracle(gpu, iters):
+    import torch
+    import oracle
+    shat = poisson_images(iters + 1, 3, 70, 150)
+    shat[1, 10:14, 20:30] = 0.0
+    log("denoise iters", iters)
+    g = gpu.denoise(torch.tensor(shat, device="cuda"), beta=0.05, iters=iters, s_floor=1e-3).cpu().numpy()
+    o = oracle.denoise(shat, 0.05, iters, s_floor=1e-3)
+    err = np.abs(g - o).max()
+    log("max abs err", err, "tol", tol_of(o, iters))
+    assert err <= tol_of(o, iters)
+
+
+def test_denoise_strided_tally_planes(gpu):
+    """Plane 2 of [n][4][nv][nu] tallies in place equals the contiguous copy."""
+    import torch
+    shat = poisson_images(7, 4, 33, 65, mean=80.0)
+    t = torch.zeros(4, 4, 33, 65, dtype=torch.float64, device="cuda")
+    t[:, 2] = torch.tensor(shat, device="cuda")
+    t[:, 0] = 1e9                                          # must not be read
+    a = gpu.denoise(t[:, 2], beta=0.1, iters=20)
+    b = gpu.denoise(t[:, 2].contiguous(), beta=0.1, iters=20)
+    assert torch.equal(a, b)
+    one = gpu.denoise(t[2, 2], beta=0.1, iters=20)
+    assert torch.equal(one, a[2])
+
+
+def test_denoise_full_detector(gpu):
+    """The benchmark's detector (256 x 192), 40 images, 64 sweeps; 3 checked in the oracle."""
+    import torch
+    import oracle
+    shat = poisson_images(11, 40, 192, 256, mean=400.0)
+    log("denoise full detector")
+    g = gpu.denoise(torch.tensor(shat, device="cuda"), beta=0.02, iters=64).cpu().numpy()
+    for k in (0, 17, 39):
+        o = oracle.denoise(shat[k], 0.02, 64, s_floor=1e-6)
+        err = np.abs(g[k] - o).max()
+        log("image", k, "max abs err", err)
+        assert err <= tol_of(o, 64)
+
+
+def test_noise_matches_oracle(gpu):
+    import torch
+    import oracle
+    rng = np.random.default_rng(3)
+    n, nv, nu = 5, 19, 37
+    p = rng.uniform(0.5, 1.0, (n, nv, nu))
+    s = rng.uniform(0.1, 0.2, (n, nv, nu))
+    phat = p + rng.normal(0, 0.02, p.shape)
+    shat = s + rng.normal(0, 0.02, s.shape)
+    tal = torch.zeros(n, 4, nv, nu, dtype=torch.float64, device="cuda")
+    tal[:, 0] = torch.tensor(phat, device="cuda")
+    tal[:, 2] = torch.tensor(shat, device="cuda")
+    alpha = gpu.noise_scale(5e8, 5.2913e9, 0.6)
+    nz, img = gpu.noise(tal[:, 0], torch.tensor(p, device="cuda"), tal[:, 2], torch.tensor(s, device="cuda"), alpha)
+    on, oi = oracle.noise(phat, p, shat, s, alpha)
+    assert np.allclose(nz.cpu().numpy(), on, rtol=1e-14, atol=1e-16)
+    assert np.allclose(img.cpu().numpy(), oi, rtol=1e-14, atol=1e-16)
+    assert abs(alpha - oracle.noise_scale(5e8, 5.2913e9, 0.6)) < 1e-15
