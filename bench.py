@@ -107,15 +107,18 @@ def measured_traffic(path, workload):
 
 
 TUNE_MODE = "auto"
+TUNE_CACHE = None
 
 
 def autotune_for(batch):
-    """Launch shape from the autotuner (untimed setup, 2 % of the photons)."""
+    """Launch shape from the autotuner's cache for this workload class, or (not
+    cached) from a fresh search on 2 % of the photons; untimed setup either way."""
     from paper_1204_6367_amd import autotune
     if TUNE_MODE == "default":
         return None
     t = time.time()
-    best = autotune.autotune(batch, fraction=0.02, min_photons=200_000, cache=None, force=True)
+    best = autotune.autotune(batch, fraction=0.02, min_photons=200_000, cache=TUNE_CACHE,
+                             force=TUNE_MODE == "search")
     log(f"autotune {best} in {time.time() - t:.1f}s")
     return best
 
@@ -433,8 +436,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-raytrace", action="store_true",
                     help="skip the ray-tracing, denoising and noise legs")
-    ap.add_argument("--tune", default="auto", choices=["auto", "default"],
-                    help="auto: autotune the launch shape before timing; default: library defaults")
+    ap.add_argument("--tune", default="auto", choices=["auto", "search", "default"],
+                    help="auto: the autotuner's cached launch shape (searched if not cached); search: search "
+                         "again; default: library defaults")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file (default: the one shipped with the package)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
                     help="JSON with measured HBM bytes per transport launch (used if taken on this kernel)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -454,8 +460,10 @@ def main():
               f"across GPUs with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
 
-    global TUNE_MODE
+    global TUNE_MODE, TUNE_CACHE
     TUNE_MODE = args.tune
+    from paper_1204_6367_amd import autotune as _at
+    TUNE_CACHE = args.tune_cache or _at.DEFAULT_CACHE
     import torch
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
