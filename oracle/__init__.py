@@ -47,6 +47,7 @@ class _Problem(C.Structure):
         ("sad", C.c_double), ("aid", C.c_double), ("phi", C.c_double), ("theta", C.c_double),
         ("nu", C.c_int32), ("nv", C.c_int32),
         ("du", C.c_double), ("dv", C.c_double),
+        ("macro", C.c_int32), ("macro_margin", C.c_double),
     ]
 
 
@@ -74,6 +75,7 @@ def lib():
         L.or_denoise.argtypes = [vp, vp, i32, i32, i32, C.c_double, C.c_double, i32, C.c_double, vp]
         L.or_noise.argtypes = [C.c_int64, vp, vp, vp, vp, C.c_double, vp, vp]
         L.or_noise_scale.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.or_local_majorant_at.argtypes = [P, vp, vp, C.c_int64, vp]
         L.or_noise_scale.restype = C.c_double
         L.or_rho_integrals_many.argtypes = [P, i32, vp, vp, C.c_int64, vp]
         L.or_sample_compton.argtypes = [C.c_double, u64, u64, vp, vp]
@@ -136,6 +138,12 @@ class Problem:
                    g.theta_rad, g.nu, g.nv, g.du_mm, g.dv_mm, phys.response,
                    phys.rayleigh_x0, phys.e_cut_kev)
 
+    def local_majorants(self, macro: int, margin: float = 2.0**-20) -> "Problem":
+        """Switch the transport to local majorants on cubes of macro^3 voxels (0: back to the global one)."""
+        self.s.macro = int(macro)
+        self.s.macro_margin = float(margin)
+        return self
+
     @property
     def ref(self):
         return C.byref(self.s)
@@ -161,7 +169,7 @@ def mc_project(p: Problem, seed: int, n: int, job_id: int = 0, interp: bool = Tr
                nthreads: int = 0):
     """Returns dict(tally=[4][nv][nu], stats=..., and per-history arrays if trace)."""
     tally = np.zeros((4, p.nv, p.nu), np.float64)
-    stats = np.zeros(13, np.float64)
+    stats = np.zeros(14, np.float64)
     tr = {}
     if trace:
         tr = dict(cls=np.zeros(n, np.int8), pixel=np.zeros(n, np.int32),
@@ -177,7 +185,7 @@ def mc_project(p: Problem, seed: int, n: int, job_id: int = 0, interp: bool = Tr
     out = dict(tally=tally, stats=dict(
         steps=stats[0], real=stats[1], compton=stats[2], rayleigh=stats[3],
         classes={CLASS_NAMES[k]: stats[4 + k] for k in range(6)},
-        e_src=stats[10], e_out=stats[11], tries=stats[12]))
+        e_src=stats[10], e_out=stats[11], tries=stats[12], crossings=stats[13]))
     out.update(tr)
     return out
 
@@ -189,7 +197,7 @@ def mc_histories(p: Problem, seed: int, ids, majorant_tab: np.ndarray, job_id: i
     m = ids.shape[0]
     tr = dict(cls=np.zeros(m, np.int8), pixel=np.zeros(m, np.int32), e_final=np.zeros(m, np.float64),
               steps=np.zeros(m, np.int32), n_compton=np.zeros(m, np.int32), n_rayleigh=np.zeros(m, np.int32))
-    mb = np.ascontiguousarray(majorant_tab, np.float64)
+    mb = None if majorant_tab is None else np.ascontiguousarray(majorant_tab, np.float64)
     rc = lib().or_mc_histories(p.ref, seed, job_id, int(interp), _ptr(mb), _ptr(ids), m, _ptr(tr["cls"]),
                                _ptr(tr["pixel"]), _ptr(tr["e_final"]), _ptr(tr["steps"]),
                                _ptr(tr["n_compton"]), _ptr(tr["n_rayleigh"]), nthreads)
@@ -205,7 +213,7 @@ def mc_backward(p: Problem, seed: int, n: int, adj: np.ndarray, majorant_tab: np
     assert adj.shape == (2, p.nv, p.nu)
     if grad is None:
         grad = np.zeros(p.shape, np.float64)
-    mb = np.ascontiguousarray(majorant_tab, np.float64)
+    mb = None if majorant_tab is None else np.ascontiguousarray(majorant_tab, np.float64)
     if lib().or_mc_backward(p.ref, seed, n, job_id, int(interp), mode, _ptr(mb), _ptr(adj), _ptr(grad), nthreads):
         raise ValueError("oracle mc_backward: invalid input")
     return grad
@@ -263,6 +271,16 @@ def denoise(shat, beta: float, iters: int, omega: float = 0.8, s_floor: float = 
                         int(iters), float(s_floor), _ptr(out)):
         raise ValueError("oracle denoise: invalid input")
     return out.reshape(shape)
+
+
+def local_majorant_at(p: Problem, xyz, e) -> np.ndarray:
+    """Local majorant (1/cm) of the cube holding each position at each energy."""
+    x = np.ascontiguousarray(xyz, np.float64).reshape(-1, 3)
+    ee = np.ascontiguousarray(e, np.float64).ravel()
+    out = np.zeros(len(ee), np.float64)
+    if lib().or_local_majorant_at(p.ref, _ptr(x), _ptr(ee), len(ee), _ptr(out)):
+        raise ValueError("oracle local_majorant_at: invalid input")
+    return out
 
 
 def noise_scale(n_sim: float, zeta: float, mas: float) -> float:

@@ -69,6 +69,8 @@ typedef struct {
     double sad, aid, phi, theta;       /* mm, rad */
     int32_t nu, nv;
     double du, dv;                     /* mm */
+    int32_t macro;                     /* local majorants on cubes of macro^3 voxels; 0 = one global majorant */
+    double macro_margin;               /* their relative margin */
 } or_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -158,6 +160,9 @@ typedef struct {
     double* cdf_e;
     double* cdf_f;
     const double* mbar;                /* [n_e - 1], 1/cm */
+    int nb[3];                         /* macro cells per axis (local majorants) */
+    double* mac_rho;                   /* [nbz][nby][nbx] largest density the cell's positions can show */
+    uint64_t* mac_mask;                /* materials its positions can take, one bit each */
     uint32_t key[2];
     uint32_t job;
     int interp;
@@ -456,13 +461,118 @@ void or_rotate(const double d[3], double cost, double ph, double out[3])
 }
 
 /* ------------------------------------------------------------------------ */
+/* Local majorants (not in the paper: Woodcock tracking only needs a bound   */
+/* at every point, which may vary in space).  The phantom is cut into cubes  */
+/* of M^3 voxels (the last ones along an axis shorter).  Positions in a cube */
+/* take their density from voxel centres, and their material from the       */
+/* containing voxel, within one voxel of the cube (the interpolation corners */
+/* of any point in the cube, with one voxel to spare for rounding at its     */
+/* faces), so mbar_B(E) = (1 + margin) rho_max(B) max_{m in B} mu_tot(m, E)  */
+/* bounds mu there, with rho_max and the material set taken over the cube    */
+/* grown by one voxel.  A flight draws an optical depth tau = -ln u and      */
+/* spends it cube by cube along its line (each cube costs mbar_B times the   */
+/* length inside it); the collision point is where tau runs out, tested      */
+/* against that cube's mbar_B; running out of cubes is an escape.            */
+/* ------------------------------------------------------------------------ */
+static int build_macro(const or_problem* p, or_ctx* c)
+{
+    const int M = p->macro;
+    const int n[3] = { p->nx, p->ny, p->nz };
+    if (p->n_mat > 64) return -1;
+    for (int a = 0; a < 3; ++a) c->nb[a] = (n[a] + M - 1) / M;
+    const size_t nb = (size_t)c->nb[0] * c->nb[1] * c->nb[2];
+    c->mac_rho = (double*)calloc(nb, sizeof(double));
+    c->mac_mask = (uint64_t*)calloc(nb, sizeof(uint64_t));
+    if (!c->mac_rho || !c->mac_mask) return -1;
+    for (int bz = 0; bz < c->nb[2]; ++bz)
+        for (int by = 0; by < c->nb[1]; ++by)
+            for (int bx = 0; bx < c->nb[0]; ++bx) {
+                const int b[3] = { bx, by, bz };
+                int lo[3], hi[3];
+                for (int a = 0; a < 3; ++a) {
+                    lo[a] = clampi(b[a] * M - 1, 0, n[a] - 1);
+                    hi[a] = clampi((b[a] + 1) * M, 0, n[a] - 1);     /* inclusive: one voxel beyond the cube */
+                }
+                double r = 0.0;
+                uint64_t mask = 0;
+                for (int z = lo[2]; z <= hi[2]; ++z)
+                    for (int y = lo[1]; y <= hi[1]; ++y)
+                        for (int x = lo[0]; x <= hi[0]; ++x) {
+                            size_t v = vidx(p, x, y, z);
+                            if ((double)p->density[v] > r) r = (double)p->density[v];
+                            mask |= (uint64_t)1 << p->material[v];
+                        }
+                size_t bi = ((size_t)bz * c->nb[1] + by) * c->nb[0] + bx;
+                c->mac_rho[bi] = r;
+                c->mac_mask[bi] = mask;
+            }
+    return 0;
+}
+
+static double macro_mbar(const or_problem* p, const or_ctx* c, size_t bi, double E)
+{
+    double best = 0.0;
+    for (int m = 0; m < p->n_mat; ++m) {
+        if (!((c->mac_mask[bi] >> m) & 1u)) continue;
+        double mu3[3];
+        xs_at(p, m, E, mu3);
+        double t = mu3[0] + mu3[1] + mu3[2];
+        if (t > best) best = t;
+    }
+    return (1.0 + p->macro_margin) * c->mac_rho[bi] * best;
+}
+
+/* Spends optical depth tau from pos along dir; on a collision moves pos there,
+ * sets *mbar_out to the cube's bound and returns 1; returns 0 on leaving the
+ * phantom (pos then on its boundary).  *crossings counts cube faces crossed. */
+static int macro_flight(const or_problem* p, const or_ctx* c, double pos[3], const double dir[3], double E,
+                        double tau, double* mbar_out, int* crossings)
+{
+    const int M = p->macro;
+    const int n[3] = { p->nx, p->ny, p->nz };
+    int b[3];
+    for (int a = 0; a < 3; ++a)
+        b[a] = clampi((int)floor((pos[a] - c->lo[a]) / (M * c->vs[a])), 0, c->nb[a] - 1);
+    for (;;) {
+        const size_t bi = ((size_t)b[2] * c->nb[1] + b[1]) * c->nb[0] + b[0];
+        const double mb = macro_mbar(p, c, bi, E);
+        double texit = INFINITY;
+        int axis = 0;
+        for (int a = 0; a < 3; ++a) {
+            double t;
+            if (dir[a] > 0.0) {
+                int f = (b[a] + 1) * M < n[a] ? (b[a] + 1) * M : n[a];
+                t = (c->lo[a] + f * c->vs[a] - pos[a]) / dir[a];
+            } else if (dir[a] < 0.0) {
+                t = (c->lo[a] + b[a] * M * c->vs[a] - pos[a]) / dir[a];
+            } else {
+                continue;
+            }
+            if (t < texit) { texit = t; axis = a; }
+        }
+        if (texit < 0.0) texit = 0.0;
+        if (mb > 0.0 && tau < 0.1 * mb * texit) {            /* mbar in 1/cm, lengths in mm */
+            const double s = tau / (0.1 * mb);
+            for (int a = 0; a < 3; ++a) pos[a] += s * dir[a];
+            *mbar_out = mb;
+            return 1;
+        }
+        tau -= 0.1 * mb * texit;
+        for (int a = 0; a < 3; ++a) pos[a] += texit * dir[a];
+        b[axis] += dir[axis] > 0.0 ? 1 : -1;
+        ++*crossings;
+        if (b[axis] < 0 || b[axis] >= c->nb[axis]) return 0;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* One history, Sec. 2.4.                                                    */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int cls;
     int pixel;
     double e_src, e_final, recoil;
-    int steps, n_real, n_compton, n_rayleigh, tries;
+    int steps, n_real, n_compton, n_rayleigh, tries, crossings;
 } or_outcome;
 
 /* Visitor for tentative collisions inside the phantom (for the adjoint). */
@@ -503,7 +613,7 @@ static void history(const or_problem* p, const or_ctx* c, uint32_t i, or_outcome
     double ju = u24(x[0]), jv = u24(x[1]);
     double E = (double)p->spec_e[ke];
     o->e_src = E; o->recoil = 0.0;
-    o->steps = 0; o->n_real = 0; o->n_compton = 0; o->n_rayleigh = 0; o->tries = 0;
+    o->steps = 0; o->n_real = 0; o->n_compton = 0; o->n_rayleigh = 0; o->tries = 0; o->crossings = 0;
 
     /* aim point D on the detector, uniform within the sampled pixel */
     double uc = ((double)iu + ju - 0.5 * p->nu) * p->du;
@@ -527,13 +637,18 @@ static void history(const or_problem* p, const or_ctx* c, uint32_t i, or_outcome
             if (half == 2) { ++pair; rblock(c, i, pair, 0, fb); half = 0; }
             double r0 = u24(fb[2 * half]), r1 = u24(fb[2 * half + 1]);
             ++half;
-            double f;
-            int j = e_interval(p, E, &f);
-            double mbar = c->mbar[j];
-            double s = -log(r0) / (0.1 * mbar);              /* mm; mbar in 1/cm */
-            if (s >= trem) break;                             /* leaves the phantom */
-            for (int a = 0; a < 3; ++a) pos[a] += s * dir[a];
-            trem -= s;
+            double mbar;
+            if (p->macro > 0) {
+                if (!macro_flight(p, c, pos, dir, E, -log(r0), &mbar, &o->crossings)) break;   /* escaped */
+            } else {
+                double f;
+                int j = e_interval(p, E, &f);
+                mbar = c->mbar[j];
+                double s = -log(r0) / (0.1 * mbar);          /* mm; mbar in 1/cm */
+                if (s >= trem) break;                         /* leaves the phantom */
+                for (int a = 0; a < 3; ++a) pos[a] += s * dir[a];
+                trem -= s;
+            }
             size_t v = containing_voxel(p, c, pos);
             int m = p->material[v];
             double rho;
@@ -572,7 +687,7 @@ static void history(const or_problem* p, const or_ctx* c, uint32_t i, or_outcome
             dir[0] = nd2[0]; dir[1] = nd2[1]; dir[2] = nd2[2];
             scattered = 1;
             if (E < p->e_cut) { o->cls = OR_CUT; o->pixel = -1; o->e_final = E; return; }
-            trem = box_exit(c, pos, dir);
+            if (p->macro <= 0) trem = box_exit(c, pos, dir);
         }
     }
     o->e_final = E;
@@ -616,6 +731,7 @@ static int validate(const or_problem* p)
     for (int k = 0; k < p->n_spec; ++k)
         if (!(p->spec_e[k] >= p->e0 && p->spec_e[k] <= emax)) return -1;
     if (!(p->e_cut >= p->e0)) return -1;
+    if (p->macro < 0 || (p->macro > 0 && (p->n_mat > 64 || !(p->macro_margin >= 0.0)))) return -1;
     /* the phantom must lie on the source side of the detector plane */
     double rxy = sqrt(0.25 * (p->nx * p->dx) * (p->nx * p->dx) + 0.25 * (p->ny * p->dy) * (p->ny * p->dy));
     if (!(rxy < p->aid) || !(rxy < p->sad)) return -1;
@@ -633,6 +749,7 @@ static int make_ctx(const or_problem* p, uint64_t seed, uint32_t job, int interp
     if (build_cdf(p->spec_p, p->n_spec, c->cdf_e)) return -1;
     if (build_cdf(p->fluence, p->nu * p->nv, c->cdf_f)) return -1;
     c->mbar = mbar;
+    if (p->macro > 0 && build_macro(p, c)) return -1;
     c->key[0] = (uint32_t)seed;
     c->key[1] = (uint32_t)(seed >> 32);
     c->job = job;
@@ -640,7 +757,7 @@ static int make_ctx(const or_problem* p, uint64_t seed, uint32_t job, int interp
     return 0;
 }
 
-static void free_ctx(or_ctx* c) { free(c->cdf_e); free(c->cdf_f); }
+static void free_ctx(or_ctx* c) { free(c->cdf_e); free(c->cdf_f); free(c->mac_rho); free(c->mac_mask); }
 
 #define OR_CHUNK 4096
 
@@ -660,9 +777,9 @@ static int counts_as_scatter(const or_outcome* o, int mode)
  * tally [4][nv][nu]: sum r(E), sum r(E)^2 over primary hits, then the same
  * over scatter hits, each divided by n (per source photon).  Optional
  * per-history outputs (any may be NULL): cls, pixel, e_final, steps,
- * n_compton, n_rayleigh.  `mode` selects the scatter tally (above).  stats[13] (optional): totals of steps, real events,
+ * n_compton, n_rayleigh.  `mode` selects the scatter tally (above).  stats[14] (optional): totals of steps, real events,
  * Compton, Rayleigh, histories per class [6], source energy, final energy plus
- * recoil energy, angular-sampler tries.
+ * recoil energy, angular-sampler tries, cube faces crossed (local majorants).
  * `mbar` NULL => the majorant is computed here.
  */
 int or_mc_project(const or_problem* p, uint64_t seed, uint64_t n, uint32_t job, int32_t interp,
@@ -671,7 +788,7 @@ int or_mc_project(const or_problem* p, uint64_t seed, uint64_t n, uint32_t job, 
 {
     if (validate(p) || !tally || n > 0xFFFFFFFFull) return -1;
     double* mb = NULL;
-    if (!mbar_in) {
+    if (!mbar_in && p->macro <= 0) {
         mb = (double*)malloc(sizeof(double) * (size_t)(p->n_e - 1));
         if (!mb || or_majorant(p, interp, mb)) { free(mb); return -1; }
     }
@@ -717,6 +834,7 @@ int or_mc_project(const or_problem* p, uint64_t seed, uint64_t n, uint32_t job, 
                 ms[4 + o.cls] += 1.0;
                 ms[10] += o.e_src; ms[11] += o.e_final + o.recoil;
                 ms[12] += o.tries;
+                ms[13] += o.crossings;
             }
         }
     }
@@ -727,7 +845,7 @@ int or_mc_project(const or_problem* p, uint64_t seed, uint64_t n, uint32_t job, 
         tally[k] = s * inv;
     }
     if (stats)
-        for (int k = 0; k < 13; ++k) {
+        for (int k = 0; k < 14; ++k) {
             double s = 0.0;
             for (int t = 0; t < nt; ++t) s += st[t * 16 + k];
             stats[k] = s;
@@ -745,7 +863,7 @@ int or_mc_histories(const or_problem* p, uint64_t seed, uint32_t job, int32_t in
                     const uint32_t* ids, int64_t m, int8_t* cls, int32_t* pixel, double* e_final,
                     int32_t* steps, int32_t* n_compton, int32_t* n_rayleigh, int32_t nthreads)
 {
-    if (validate(p) || !mbar || !ids) return -1;
+    if (validate(p) || (!mbar && p->macro <= 0) || !ids) return -1;
     or_ctx c;
     if (make_ctx(p, seed, job, interp, mbar, &c)) { free_ctx(&c); return -1; }
     int nt = 1;
@@ -782,7 +900,7 @@ int or_mc_histories(const or_problem* p, uint64_t seed, uint32_t job, int32_t in
 int or_mc_backward(const or_problem* p, uint64_t seed, uint64_t n, uint32_t job, int32_t interp,
                    int32_t mode, const double* mbar, const double* adj, double* grad, int32_t nthreads)
 {
-    if (validate(p) || !mbar || !adj || !grad || n > 0xFFFFFFFFull) return -1;
+    if (validate(p) || (!mbar && p->macro <= 0) || !adj || !grad || n > 0xFFFFFFFFull) return -1;
     or_ctx c;
     if (make_ctx(p, seed, job, interp, mbar, &c)) { free_ctx(&c); return -1; }
     size_t npix = (size_t)p->nu * p->nv;
@@ -1205,4 +1323,23 @@ double or_noise_scale(double n_sim, double zeta, double mas)
 {
     if (!(n_sim > 0.0) || !(zeta > 0.0) || !(mas > 0.0)) return -1.0;
     return sqrt(n_sim / (zeta * mas));
+}
+
+/* Tests: the local majorant of the cube holding each position xyz[k] at
+ * energy e[k] (macro > 0 required). */
+int or_local_majorant_at(const or_problem* p, const double* xyz, const double* e, int64_t m, double* out)
+{
+    if (validate(p) || p->macro <= 0) return -1;
+    or_ctx c;
+    memset(&c, 0, sizeof(c));
+    setup_geometry(p, &c);
+    if (build_macro(p, &c)) { free_ctx(&c); return -1; }
+    for (int64_t k = 0; k < m; ++k) {
+        int b[3];
+        for (int a = 0; a < 3; ++a)
+            b[a] = clampi((int)floor((xyz[3 * k + a] - c.lo[a]) / (p->macro * c.vs[a])), 0, c.nb[a] - 1);
+        out[k] = macro_mbar(p, &c, ((size_t)b[2] * c.nb[1] + b[1]) * c.nb[0] + b[0], e[k]);
+    }
+    free_ctx(&c);
+    return 0;
 }
