@@ -78,6 +78,16 @@ typedef struct gdrr_volume {
     float dx_mm, dy_mm, dz_mm;
     const float* density;      /* [nz][ny][nx] g/cm^3, finite and >= 0 */
     const uint8_t* material;   /* [nz][ny][nx] indices < gdrr_physics.n_mat */
+    /* Local majorants (not in the paper; 0 = off): the volume is cut into cubes of
+     * `macro`^3 voxels (the last ones along an axis shorter), each with the bound
+     * (1 + macro_margin) rho_max max_m mu_tot(m, E) over the cube grown by one voxel;
+     * a free flight spends an optical depth -ln(u) cube by cube and the collision
+     * ladder runs against the bound of the cube it ends in.  Unbiased like the
+     * single majorant, with far fewer null collisions in air and soft tissue; it uses
+     * the random numbers differently, so results differ history by history.  When on,
+     * the `majorants` argument is not used for this volume.  1 <= macro <= 64. */
+    int32_t macro;
+    float macro_margin;        /* >= 0; 2^-20 for projections, 0.1-0.2 for the adjoint */
 } gdrr_volume;
 
 /* Mass attenuation tables mu_k(i, E) of Sec. 2.1 on the grid

@@ -46,6 +46,12 @@ class DeviceVolume:
         self.material = _t(material, torch.uint8, dev)
         assert self.density.shape == self.material.shape and self.density.dim() == 3
         self.spacing_mm = tuple(float(s) for s in spacing_mm)
+        self.macro, self.macro_margin = 0, 2.0**-20
+
+    def local_majorants(self, macro: int, margin: float = 2.0**-20) -> "DeviceVolume":
+        """Track with local majorants on cubes of macro^3 voxels (0: one majorant per energy interval)."""
+        self.macro, self.macro_margin = int(macro), float(margin)
+        return self
 
     @property
     def shape(self):
@@ -54,7 +60,8 @@ class DeviceVolume:
     def struct(self, density: Optional[torch.Tensor] = None) -> _abi.Volume:
         d = self.density if density is None else density
         nz, ny, nx = d.shape
-        return _abi.Volume(nx, ny, nz, *self.spacing_mm, d.data_ptr(), self.material.data_ptr())
+        return _abi.Volume(nx, ny, nz, *self.spacing_mm, d.data_ptr(), self.material.data_ptr(), self.macro,
+                           self.macro_margin)
 
 
 class DevicePhysics:

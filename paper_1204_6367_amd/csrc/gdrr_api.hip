@@ -92,8 +92,13 @@ int check_volume(const gdrr_volume* v) {
     if ((long long)v->nx * v->ny * v->nz >= (1ll << 31)) return fail(GDRR_EINVAL, "volume has 2^31 voxels or more");
     if (!(v->dx_mm > 0 && v->dy_mm > 0 && v->dz_mm > 0)) return fail(GDRR_EINVAL, "voxel sizes must be > 0");
     if (!v->density || !v->material) return fail(GDRR_EINVAL, "volume density/material pointer is NULL");
+    if (v->macro < 0 || v->macro > 64) return fail(GDRR_EINVAL, "volume macro must be in [0, 64]");
+    if (v->macro > 0 && (!(v->macro_margin >= 0.0f) || !std::isfinite(v->macro_margin)))
+        return fail(GDRR_EINVAL, "volume macro_margin must be finite and >= 0");
     return GDRR_OK;
 }
+
+int cubes(int n, int m) { return (n + m - 1) / m; }
 
 int check_physics(const gdrr_physics* p) {
     if (!p) return fail(GDRR_EINVAL, "physics is NULL");
@@ -289,6 +294,7 @@ struct Layout {
     unsigned int* present;            // [n_vols][256]
     SrcArea src[GDRR_MAX_SOURCES];
     CellRec* cells[GDRR_MAX_VOLUMES]; // per-volume cell records
+    uint2* macro[GDRR_MAX_VOLUMES];   // per-volume local majorants (volumes with macro > 0)
     unsigned long long* tally;        // fixed-point tallies
     size_t tally_elems;
     size_t bytes;
@@ -319,6 +325,12 @@ Layout carve(void* ws, const gdrr_volume* vols, const gdrr_physics* phys, const 
         L.src[s].flu_guide = c.take<uint32_t>(L.src[s].flu_k);
     }
     for (int v = 0; v < n_vols; ++v) L.cells[v] = c.take<CellRec>(cell_count(vols[v]));
+    for (int v = 0; v < n_vols; ++v) {
+        const gdrr_volume& V = vols[v];
+        L.macro[v] = V.macro > 0 ? c.take<uint2>((size_t)cubes(V.nx, V.macro) * cubes(V.ny, V.macro) *
+                                                 cubes(V.nz, V.macro))
+                                 : nullptr;
+    }
     L.tally = c.take<unsigned long long>(tally_elems);
     L.tally_elems = tally_elems;
     L.bytes = c.off + 256;
@@ -404,19 +416,23 @@ int check_batch(const Batch& B) {
         if (t.defer < 0 || t.defer > 64) return fail(GDRR_EINVAL, "tune.defer must be in [0, 64]");
         if (t.blocks_per_cu < 0 || t.blocks_per_cu > 64) return fail(GDRR_EINVAL, "tune.blocks_per_cu must be in [0, 64]");
         if (t.scheme < 0 || t.scheme > 2) return fail(GDRR_EINVAL, "tune.scheme must be 0, 1 or 2");
+        if (t.scheme == 2)
+            for (int v = 0; v < B.n_vols; ++v)
+                if (B.vols[v].macro > 0) return fail(GDRR_ENOTSUP, "tune.scheme 2 does not support local majorants");
     }
     return GDRR_OK;
 }
 
 template <int MODE>
-const void* mc_func(int scheme) {
-    return scheme == 2 ? reinterpret_cast<const void*>(&mc_queue_kernel<MODE>)
-                       : reinterpret_cast<const void*>(&mc_kernel<MODE>);
+const void* mc_func(int scheme, bool local) {
+    if (scheme == 2) return reinterpret_cast<const void*>(&mc_queue_kernel<MODE>);
+    return local ? reinterpret_cast<const void*>(&mc_kernel<MODE, true>)
+                 : reinterpret_cast<const void*>(&mc_kernel<MODE, false>);
 }
 
-const void* mc_func_for(int mode, int scheme) {
-    return mode == kModeForward ? mc_func<kModeForward>(scheme)
-         : mode == kModeTrace ? mc_func<kModeTrace>(scheme) : mc_func<kModeBackward>(scheme);
+const void* mc_func_for(int mode, int scheme, bool local) {
+    return mode == kModeForward ? mc_func<kModeForward>(scheme, local)
+         : mode == kModeTrace ? mc_func<kModeTrace>(scheme, local) : mc_func<kModeBackward>(scheme, local);
 }
 
 int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
@@ -441,13 +457,15 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     for (int k = 0; k < B.n_jobs; ++k)
         if (B.only_volume < 0 || B.jobs[k].volume == B.only_volume) total_photons += B.jobs[k].n_photons;
     const int scheme = tune.scheme ? tune.scheme : 1;
+    bool local = false;
+    for (int v = 0; v < B.n_vols; ++v) local |= B.vols[v].macro > 0;
     const int block = tune.block ? tune.block : (scheme == 2 ? 512 : 256);
     const size_t lds = scheme == 2 ? queue_lds_bytes(phys->n_mat, phys->n_e, B.n_vols, phys->response != nullptr, block)
                                    : lds_bytes(phys->n_mat, phys->n_e, B.n_vols, phys->response != nullptr);
     if (lds > dev.lds_max) return fail(GDRR_ENOTSUP, "tables and queues exceed the LDS of a workgroup");
     int per_cu = tune.blocks_per_cu;
     if (!per_cu) {
-        const void* f = mc_func_for(B.mode, scheme);
+        const void* f = mc_func_for(B.mode, scheme, local);
         int nb = 0;
         GDRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, block, lds));
         per_cu = std::max(nb, 1);
@@ -541,6 +559,15 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
         ls.push_back(make_launch((const void*)&cells_kernel,
                                  dim3((unsigned)std::max<size_t>(1, std::min<size_t>((size_t)dev.cus * 16, (nc + 255) / 256))),
                                  dim3(256), 0, cp));
+        if (L.macro[v]) {
+            MacroParams mp{V.density, V.material, V.nx, V.ny, V.nz, V.macro, cubes(V.nx, V.macro),
+                           cubes(V.ny, V.macro), cubes(V.nz, V.macro), phys->n_mat,
+                           1.0 + (double)V.macro_margin, L.macro[v]};
+            const size_t nm = (size_t)mp.mnx * mp.mny * mp.mnz;
+            ls.push_back(make_launch((const void*)&macro_kernel,
+                                     dim3((unsigned)std::max<size_t>(1, std::min<size_t>((size_t)dev.cus * 8, (nm + 255) / 256))),
+                                     dim3(256), 0, mp));
+        }
     }
     // ---- sources: CDFs and guide tables ----
     for (int s = 0; s < B.n_srcs; ++s) {
@@ -569,6 +596,17 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
         d.loz = (float)(-0.5 * V.nz * V.dz_mm); d.hiz = -d.loz;
         d.idx = (float)(1.0 / V.dx_mm); d.idy = (float)(1.0 / V.dy_mm); d.idz = (float)(1.0 / V.dz_mm);
         d.lds_majorant = v * (phys->n_e - 1);
+        d.macro = L.macro[v];
+        if (V.macro > 0) {
+            d.mnx = cubes(V.nx, V.macro); d.mny = cubes(V.ny, V.macro); d.mnz = cubes(V.nz, V.macro);
+            d.mcube = V.macro;
+            d.mex = (float)((double)V.macro * V.dx_mm);
+            d.mey = (float)((double)V.macro * V.dy_mm);
+            d.mez = (float)((double)V.macro * V.dz_mm);
+            d.imx = (float)(1.0 / ((double)V.macro * V.dx_mm));
+            d.imy = (float)(1.0 / ((double)V.macro * V.dy_mm));
+            d.imz = (float)(1.0 / ((double)V.macro * V.dz_mm));
+        }
     }
     for (int s = 0; s < B.n_srcs; ++s) {
         DSource& d = kp.src[s];
@@ -608,7 +646,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     kp.t_steps = B.t_steps; kp.t_nc = B.t_nc; kp.t_nr = B.t_nr;
     kp.adj = B.adj;
     kp.grad = B.grad;
-    const void* mf = mc_func_for(B.mode, scheme);
+    const void* mf = mc_func_for(B.mode, scheme, local);
     int timed = -1;
     if (chunks > 0) {
         timed = (int)ls.size();

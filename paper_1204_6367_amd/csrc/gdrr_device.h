@@ -96,6 +96,11 @@ struct DVolume {
     float hix, hiy, hiz;
     float idx, idy, idz;      // 1 / voxel size
     int lds_majorant;         // offset (float2 units) of this volume's majorant table in LDS
+    // local majorants (null: one majorant per energy interval for the whole volume)
+    const uint2* macro;       // per cube: (1 + margin) rho_max (float bits), material bit mask
+    int mnx, mny, mnz, mcube; // cubes per axis; voxels per cube edge
+    float mex, mey, mez;      // cube edge, mm
+    float imx, imy, imz;      // 1 / cube edge
 };
 
 struct DSource {

@@ -346,6 +346,89 @@ __device__ __forceinline__ bool flight(const KParams& P, const Tables& T, const 
     return true;
 }
 
+// One free flight under local majorants (uniforms ra, rb): an optical depth
+// tau = -ln(u) is spent cube by cube along the line, each cube at its own
+// bound mbar_B = (1 + margin) rho_max(B) max_{m in B} mu_tot(m, E); where tau
+// runs out the collision ladder runs against that cube's bound; leaving the
+// last cube is an escape.  Returns true after a null collision.
+template <int MODE>
+__device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, const DVolume& V, int vo,
+                                             bool interp, Photon& ph, uint32_t ra, uint32_t rb) {
+    if (ph.step >= kMaxSteps) {
+        if (MODE == kModeTrace) trace_out<MODE>(P, ph, kLost, -1);
+        ph.st = kDead;
+        return false;
+    }
+    ph.step += 1;
+    float tau = -fast_log(u24(ra));
+    int bx = min(max((int)floorf((ph.px - V.lox) * V.imx), 0), V.mnx - 1);
+    int by = min(max((int)floorf((ph.py - V.loy) * V.imy), 0), V.mny - 1);
+    int bz = min(max((int)floorf((ph.pz - V.loz) * V.imz), 0), V.mnz - 1);
+    const float rx = ph.dx != 0.0f ? fast_rcp(ph.dx) : 0.0f;
+    const float ry = ph.dy != 0.0f ? fast_rcp(ph.dy) : 0.0f;
+    const float rz = ph.dz != 0.0f ? fast_rcp(ph.dz) : 0.0f;
+    const int sx = ph.dx > 0.0f ? 1 : (ph.dx < 0.0f ? -1 : 0);
+    const int sy = ph.dy > 0.0f ? 1 : (ph.dy < 0.0f ? -1 : 0);
+    const int sz = ph.dz > 0.0f ? 1 : (ph.dz < 0.0f ? -1 : 0);
+    const float2* tot = T.tot + ph.ec.j;
+    float mb = 0.0f;
+    bool hit = false;
+    for (;;) {
+        const uint2 rec = V.macro[(bz * V.mny + by) * V.mnx + bx];
+        float tmax = 0.0f;
+        for (uint32_t mask = rec.y; mask; mask &= mask - 1u) {
+            const float2 tt = tot[(__builtin_ctz(mask)) * P.n_e];
+            tmax = fmaxf(tmax, tt.x + ph.ec.f * tt.y);
+        }
+        mb = __uint_as_float(rec.x) * tmax;
+        // distance to the cube's exit face along each axis (the last cube ends at the box face)
+        const float fx = sx > 0 ? fminf(V.lox + (float)(bx + 1) * V.mex, V.hix) : V.lox + (float)bx * V.mex;
+        const float fy = sy > 0 ? fminf(V.loy + (float)(by + 1) * V.mey, V.hiy) : V.loy + (float)by * V.mey;
+        const float fz = sz > 0 ? fminf(V.loz + (float)(bz + 1) * V.mez, V.hiz) : V.loz + (float)bz * V.mez;
+        const float tx = sx ? (fx - ph.px) * rx : INFINITY;
+        const float ty = sy ? (fy - ph.py) * ry : INFINITY;
+        const float tz = sz ? (fz - ph.pz) * rz : INFINITY;
+        const float texit = fmaxf(fminf(tx, fminf(ty, tz)), 0.0f);
+        const float need = 0.1f * mb * texit;              // mbar in 1/cm, lengths in mm
+        if (mb > 0.0f && tau < need) {
+            const float s = tau * fast_rcp(0.1f * mb);
+            ph.px += s * ph.dx;
+            ph.py += s * ph.dy;
+            ph.pz += s * ph.dz;
+            hit = true;
+            break;
+        }
+        tau -= need;
+        ph.px += texit * ph.dx;
+        ph.py += texit * ph.dy;
+        ph.pz += texit * ph.dz;
+        if (tx <= ty && tx <= tz) { bx += sx; if (bx < 0 || bx >= V.mnx) break; }
+        else if (ty <= tz) { by += sy; if (by < 0 || by >= V.mny) break; }
+        else { bz += sz; if (bz < 0 || bz >= V.mnz) break; }
+    }
+    if (!hit) {
+        int pixel;
+        const int cls = detector_pixel(P.jobs[ph.job], ph, pixel);
+        finish<MODE>(P, T, V, vo, ph, cls, pixel);
+        return false;
+    }
+    int m;
+    const float rho = cell_density(V, interp, ph.px, ph.py, ph.pz, m);
+    m = m < P.n_mat ? m : P.n_mat - 1;
+    const float2 tt = T.tot[m * P.n_e + ph.ec.j];
+    const float tot_m = tt.x + ph.ec.f * tt.y;
+    const float ladder = u24(rb) * mb;
+    const bool real = ladder < rho * tot_m;
+    if (MODE == kModeBackward && ph.passb) visit(P, V, interp, ph, real, rho, tot_m, mb);
+    if (real) {
+        ph.st = kColl;
+        ph.sel = ladder * fast_rcp(rho);
+        ph.pm = m;
+        return false;
+    }
+    return true;
+}
+
 // A real collision (Sec. 2.4): the ladder value picks Rayleigh, Compton or
 // photoelectric absorption; scattering samples the angle, updates energy and
 // direction and the distance to the phantom's boundary.
@@ -407,7 +490,9 @@ __host__ __device__ inline size_t table_floats2(int n_mat, int n_e, int n_vols, 
     return (size_t)n_mat * n_e + (size_t)n_vols * (n_e - 1) + (resp ? (size_t)n_e : 0);
 }
 
-template <int MODE>
+// LOCAL: some volume of the launch tracks with local majorants (a separate
+// instantiation, so that the single-majorant loop keeps its register budget).
+template <int MODE, bool LOCAL>
 __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
     extern __shared__ float2 lds[];
     const Tables T = stage_tables(P, lds);
@@ -496,7 +581,12 @@ __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
         if (ph.st == kFly) {
             ph.pair += 1u;
             const Block b = philox(ph.pid, ph.jid, ph.pair, 0u, P.k0, P.k1);
-            if (flight<MODE>(P, T, V, vo, interp, ph, b.x, b.y)) flight<MODE>(P, T, V, vo, interp, ph, b.z, b.w);
+            if (LOCAL && V.macro) {
+                if (flight_local<MODE>(P, T, V, vo, interp, ph, b.x, b.y))
+                    flight_local<MODE>(P, T, V, vo, interp, ph, b.z, b.w);
+            } else if (flight<MODE>(P, T, V, vo, interp, ph, b.x, b.y)) {
+                flight<MODE>(P, T, V, vo, interp, ph, b.z, b.w);
+            }
         }
 
         // ---- collision: interaction type and sampling ----
@@ -584,6 +674,40 @@ __global__ __launch_bounds__(256) void majorant_kernel(MajFinParams F) {
     }
     if (blockIdx.x == 0 && threadIdx.x < 256 - F.n_mat && F.present[F.n_mat + threadIdx.x])
         atomicOr(F.error, 2u);   // material index out of range
+}
+
+// ---------------------------------------------------------------------------
+// Local majorants: per cube of mcube^3 voxels, the largest density and the
+// materials over the cube grown by one voxel (the interpolation corners of
+// every point in the cube, with a voxel to spare at its faces).
+// ---------------------------------------------------------------------------
+struct MacroParams {
+    const float* density;
+    const uint8_t* material;
+    int nx, ny, nz, mcube, mnx, mny, mnz, n_mat;
+    double scale;              // 1 + margin
+    uint2* out;
+};
+
+__global__ __launch_bounds__(256) void macro_kernel(MacroParams M) {
+    const long long n = (long long)M.mnx * M.mny * M.mnz;
+    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+        const int bx = (int)(c % M.mnx), by = (int)((c / M.mnx) % M.mny), bz = (int)(c / ((long long)M.mnx * M.mny));
+        const int x0 = max(bx * M.mcube - 1, 0), x1 = min((bx + 1) * M.mcube, M.nx - 1);
+        const int y0 = max(by * M.mcube - 1, 0), y1 = min((by + 1) * M.mcube, M.ny - 1);
+        const int z0 = max(bz * M.mcube - 1, 0), z1 = min((bz + 1) * M.mcube, M.nz - 1);
+        float r = 0.0f;
+        uint32_t mask = 0u;
+        for (int z = z0; z <= z1; ++z)
+            for (int y = y0; y <= y1; ++y) {
+                const long long row = ((long long)z * M.ny + y) * M.nx;
+                for (int x = x0; x <= x1; ++x) {
+                    r = fmaxf(r, M.density[row + x]);
+                    mask |= 1u << min((int)M.material[row + x], M.n_mat - 1);
+                }
+            }
+        M.out[c] = make_uint2(__float_as_uint(__double2float_ru((double)r * M.scale)), mask);
+    }
 }
 
 // ---------------------------------------------------------------------------

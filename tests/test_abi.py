@@ -48,7 +48,7 @@ int main(void) {
     printf("gdrr_geometry %zu\n", sizeof(gdrr_geometry));
     printf("gdrr_job %zu\n", sizeof(gdrr_job));
     printf("gdrr_tuning %zu\n", sizeof(gdrr_tuning));
-    F(gdrr_volume, density) F(gdrr_volume, material)
+    F(gdrr_volume, density) F(gdrr_volume, material) F(gdrr_volume, macro) F(gdrr_volume, macro_margin)
     F(gdrr_physics, mu_mass) F(gdrr_physics, response) F(gdrr_physics, rayleigh_x0_invA) F(gdrr_physics, e_cut_kev)
     F(gdrr_source, spec_e_kev) F(gdrr_source, fu) F(gdrr_source, fluence)
     F(gdrr_job, geom) F(gdrr_job, n_photons) F(gdrr_job, job_id) F(gdrr_job, tally_offset)
@@ -79,7 +79,7 @@ def test_struct_layout_matches_binding(abi, tmp_path):
 def _valid_structs(abi):
     # non-null dummy device pointers: never dereferenced, the checks fail first
     p = 0x1000
-    vol = abi.Volume(8, 8, 8, 2.0, 2.0, 2.0, p, p)
+    vol = abi.Volume(8, 8, 8, 2.0, 2.0, 2.0, p, p, 0, 0.0)
     phys = abi.Physics(2, 299, 1.0, 0.5, p, None, 0.35, 1.0)
     src = abi.Source(1, p, p, 16, 12, p)
     geom = abi.Geometry(1000.0, 500.0, 0.0, 0.0, 16, 12, 8.0, 8.0)
@@ -96,6 +96,8 @@ def _call(abi, vol, phys, src, geom, n=1000, ws_bytes=1 << 30, tally=0x2000):
     (lambda v, p, s, g: setattr(v, "nx", 0), "dimensions"),
     (lambda v, p, s, g: setattr(v, "dx_mm", -1.0), "voxel sizes"),
     (lambda v, p, s, g: setattr(v, "density", None), "pointer"),
+    (lambda v, p, s, g: setattr(v, "macro", 65), "macro"),
+    (lambda v, p, s, g: (setattr(v, "macro", 2), setattr(v, "macro_margin", -1.0)), "macro_margin"),
     (lambda v, p, s, g: setattr(p, "n_mat", 17), "n_mat"),
     (lambda v, p, s, g: setattr(p, "n_e", 1), "n_e"),
     (lambda v, p, s, g: setattr(p, "e_cut_kev", 0.5), "e_cut"),
