@@ -52,6 +52,11 @@ SLOTS_FLIGHT_OUT = 3 + 7 + 30                          # the escaping flight: de
 SLOTS_TRY = SLOTS_PHILOX + 9 + 30                      # one angular-sampler try
 SLOTS_COLLISION = 6 + 55 + 40 + 10                     # type select, rotation, box exit, energy cache
 SLOTS_SOURCE = 2 * SLOTS_PHILOX + 40 + 34 + 45         # two blocks, CDFs (fp64), aim point, box entry
+# local majorants: every cube a flight visits (its first, and one per face crossed): record
+# address and load, bound from the material mask (~1.5 materials), exit-face distances, spend
+# or stop, advance, step the cube index
+SLOTS_CUBE = 50
+BYTES_CUBE = 8
 BYTES_FLIGHT_IN = 8 * 4 + 1                            # eight density corners + the containing voxel's material
 BYTES_SOURCE = 2 * (2 * 8 + 4) + 4                     # CDF + guide reads for energy and pixel, energy
 BYTES_SCORE = 8                                        # one fixed-point atomic
@@ -71,10 +76,13 @@ def work_per_history(stats, n):
     escapes = (stats["classes"]["primary"] + stats["classes"]["scatter"] + stats["classes"]["missed"]) / h
     inbox = max(flights - escapes, 0.0)
     pairs = 0.5 * (flights + real)                     # a real collision ends a pair early
+    crossings = stats.get("crossings", 0.0) / h
+    cubes = (crossings + flights) if crossings > 0 else 0.0
     slots = (pairs * SLOTS_PHILOX + inbox * SLOTS_FLIGHT_IN + escapes * SLOTS_FLIGHT_OUT + tries * SLOTS_TRY
-             + real * 6 + scatter_events * (SLOTS_COLLISION - 6) + SLOTS_SOURCE)
-    nbytes = inbox * BYTES_FLIGHT_IN + BYTES_SOURCE + scored * BYTES_SCORE
-    return dict(slots=slots, bytes=nbytes, flights=flights, inbox_flights=inbox, real=real, tries=tries)
+             + real * 6 + scatter_events * (SLOTS_COLLISION - 6) + SLOTS_SOURCE + cubes * SLOTS_CUBE)
+    nbytes = inbox * BYTES_FLIGHT_IN + BYTES_SOURCE + scored * BYTES_SCORE + cubes * BYTES_CUBE
+    return dict(slots=slots, bytes=nbytes, flights=flights, inbox_flights=inbox, real=real, tries=tries,
+                cube_visits=cubes)
 
 
 def log(*a):
@@ -108,6 +116,20 @@ def measured_traffic(path, workload):
 
 TUNE_MODE = "auto"
 TUNE_CACHE = None
+MAJORANT = "local"
+CUBE_MM = 40.0
+
+
+def apply_majorant(vol, margin):
+    """Local majorants on cubes of about CUBE_MM (or the single per-energy majorant)."""
+    if MAJORANT == "local":
+        vol.local_majorants(max(1, int(round(CUBE_MM / min(vol.spacing_mm)))), margin)
+
+
+def majorant_desc(vols):
+    if MAJORANT != "local":
+        return "global"
+    return f"local, cubes of {[v.macro for v in vols]} voxels (~{CUBE_MM:g} mm)"
 
 
 def autotune_for(batch):
@@ -131,6 +153,7 @@ def build_workload(name, api, W, torch):
     if name in ("c1", "c2"):
         prob = W.pelvis_problem(100_000_000)
         vol, phys, src = api.upload(prob)
+        apply_majorant(vol, 2.0**-20)
         if name == "c1":
             jobs = [api.JobSpec(prob.geom, 100_000_000, 0)]
         else:
@@ -146,13 +169,14 @@ def build_workload(name, api, W, torch):
             batch.project(seed=1, majorants=maj, out=tallies, tune=tune)
             return [api.last_kernel_ms()]
 
-        samples = [(prob, float(jobs[k].geom.phi_rad), jobs[k].job_id) for k in (0, len(jobs) // 2)]
+        samples = [(prob, float(jobs[k].geom.phi_rad), jobs[k].job_id, vol.macro, vol.macro_margin)
+                   for k in (0, len(jobs) // 2)]
         return dict(step=step, fwd=fwd, adj=0, samples=samples, adjoint=None, batch=batch, prob_of=lambda k: prob,
                     tallies=tallies,
                     config=dict(workload=name, phantom="256x256x160 @1.95x1.95x2.5mm ellipsoids",
                                 angles=len(jobs), photons_per_angle=jobs[0].n_photons,
                                 detector="256x192 @1.552mm", spectrum="120 kVp Kramers + 2.5 mm Al, bowtie 30 mm Al",
-                                tuning=tune))
+                                tuning=tune, majorant=majorant_desc([vol])))
     if name in ("c3", "c4"):
         if name == "c3":
             prob, target = W.adjoint_problem(10_000_000)
@@ -187,6 +211,8 @@ def build_workload(name, api, W, torch):
         batch = api.Batch(vols, dphys, [dsrc], jobs)
         adj_batch = api.Batch(vols, dphys, [dsrc], [jobs[k] for k in adj_idx])
         margins = [0.1 if v == adj_vol else 2.0**-20 for v in range(len(vols))]
+        for k, v in enumerate(vols):
+            apply_majorant(v, margins[k])
         # target tallies S* of the perturbed phantom (Philox seed 2), not timed
         tgt_vol = api.DeviceVolume(phantoms[adj_vol][1].density, phantoms[adj_vol][1].material,
                                    phantoms[adj_vol][1].spacing_mm)
@@ -220,10 +246,11 @@ def build_workload(name, api, W, torch):
             k = next(i for i, j in enumerate(jobs) if j.volume == v)
             ph = phantoms[v][0]
             samples.append((W.Problem(ph, physw, srcw, jobs[k].geom, nph), float(jobs[k].geom.phi_rad),
-                            jobs[k].job_id))
+                            jobs[k].job_id, vols[v].macro, vols[v].macro_margin))
         adjoint = dict(problem=W.Problem(phantoms[adj_vol][0], physw, srcw, jobs[adj_idx[0]].geom, 1),
-                       job_id=jobs[adj_idx[0]].job_id, margin=0.1)
+                       job_id=jobs[adj_idx[0]].job_id, margin=0.1, macro=vols[adj_vol].macro)
         cfg = dict(workload=name, angles=len(jobs), adjoint_angles=len(adj_idx), tuning=tune,
+                   majorant=majorant_desc(vols),
                    detector="256x192 @1.552mm", spectrum="120 kVp Kramers + 2.5 mm Al, bowtie 30 mm Al",
                    phantoms=[f"{'x'.join(map(str, ph.shape[::-1]))} @{ph.spacing_mm[0]}mm" for ph, _ in phantoms],
                    photons_per_angle=[p[2] for p in plan])
@@ -385,8 +412,8 @@ def cpu_baseline(wl, budget_s=20.0):
     stats_acc = None
     done, spent = 0, 0.0
     per = max(1, len(wl["samples"]))
-    for prob, phi, jid in wl["samples"]:
-        p = oracle.Problem.from_workload(prob, phi_rad=phi)
+    for prob, phi, jid, macro, margin in wl["samples"]:
+        p = oracle.Problem.from_workload(prob, phi_rad=phi).local_majorants(macro, margin)
         n = 20000
         while True:                                  # grow the sample until ~budget/per seconds
             t = time.time()
@@ -411,8 +438,8 @@ def cpu_baseline(wl, budget_s=20.0):
     out = dict(fwd_rate=fwd_rate, fwd_sample=done, stats=stats_acc, threads=nthreads)
     if wl["adjoint"] is not None:
         a = wl["adjoint"]
-        p = oracle.Problem.from_workload(a["problem"])
-        mb = oracle.majorant(p) * (1.0 + a["margin"])
+        p = oracle.Problem.from_workload(a["problem"]).local_majorants(a["macro"], a["margin"])
+        mb = None if a["macro"] else oracle.majorant(p, True, margin=a["margin"])
         adj = np.zeros((2, p.nv, p.nu))
         adj[1] = 1.0
         n = 20000
@@ -439,6 +466,11 @@ def main():
     ap.add_argument("--tune", default="auto", choices=["auto", "search", "default"],
                     help="auto: the autotuner's cached launch shape (searched if not cached); search: search "
                          "again; default: library defaults")
+    ap.add_argument("--majorant", default="local", choices=["local", "global"],
+                    help="local: bounds per cube of about --cube-mm (default); global: one per energy interval")
+    ap.add_argument("--cube-mm", type=float, default=40.0)
+    ap.add_argument("--no-global-reference", action="store_true",
+                    help="with local majorants, skip the reference forward with the single majorant")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (default: the one shipped with the package)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -460,8 +492,9 @@ def main():
               f"across GPUs with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
 
-    global TUNE_MODE, TUNE_CACHE
+    global TUNE_MODE, TUNE_CACHE, MAJORANT, CUBE_MM
     TUNE_MODE = args.tune
+    MAJORANT, CUBE_MM = args.majorant, args.cube_mm
     from paper_1204_6367_amd import autotune as _at
     TUNE_CACHE = args.tune_cache or _at.DEFAULT_CACHE
     import torch
@@ -490,6 +523,19 @@ def main():
     fwd_ms = float(np.mean([k[0] for k in kms]))
     adj_ms = float(np.mean([k[1] for k in kms])) if wl["adj"] else None
 
+    glob = None
+    if MAJORANT == "local" and not args.no_global_reference:
+        # the same forward with one majorant per energy interval (the paper's Woodcock tracking), for reference
+        b = wl["batch"]
+        saved = [(v.macro, v.macro_margin) for v in b.vols]
+        for v in b.vols:
+            v.local_majorants(0)
+        b.project(seed=1, sumsq=False, majorants=b.majorants(True), out=wl["tallies"])
+        gms = api.last_kernel_ms()
+        for v, (m, g) in zip(b.vols, saved):
+            v.local_majorants(m, g)
+        glob = dict(fwd_histories_per_s=round(wl["fwd"] / (gms * 1e-3), 1), transport_kernel_ms=round(gms, 3))
+        log(f"global-majorant forward: {gms:.1f} ms")
     rt = None if args.no_raytrace else raytrace_leg(wl, api, torch, args.steps, not args.no_cpu_baseline)
     dn = None if args.no_raytrace else denoise_leg(wl, api, torch, args.steps, wl["batch"].primary(),
                                                    not args.no_cpu_baseline)
@@ -526,7 +572,7 @@ def main():
                 fwd_histories_per_s=round(wl["fwd"] / (fwd_ms * 1e-3), 1),
                 adj_histories_per_s=round(wl["adj"] / (adj_ms * 1e-3), 1) if adj_ms else None,
                 transport_kernel_ms=round(fwd_ms, 3), adjoint_kernel_ms=round(adj_ms, 3) if adj_ms else None,
-                **extra, raytrace=rt, denoise=dn)
+                **extra, global_majorant=glob, raytrace=rt, denoise=dn)
     print(json.dumps(line), flush=True)
 
 

@@ -85,7 +85,7 @@ typedef struct gdrr_volume {
      * ladder runs against the bound of the cube it ends in.  Unbiased like the
      * single majorant, with far fewer null collisions in air and soft tissue; it uses
      * the random numbers differently, so results differ history by history.  When on,
-     * the `majorants` argument is not used for this volume.  1 <= macro <= 64. */
+     * the `majorants` argument is not used for this volume.  1 <= macro <= 256. */
     int32_t macro;
     float macro_margin;        /* >= 0; 2^-20 for projections, 0.1-0.2 for the adjoint */
 } gdrr_volume;

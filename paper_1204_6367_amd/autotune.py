@@ -18,12 +18,12 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotu
 
 CANDIDATES: List[Dict[str, int]] = [
     dict(block=b, defer=d, chunk=0, blocks_per_cu=0)
-    for b in (256, 512) for d in (8, 16, 24, 32, 40)
+    for b in (256, 512) for d in (8, 12, 16, 24, 32)
 ]
 
 
 def workload_key(batch: "api.Batch") -> str:
-    vols = ";".join("x".join(map(str, v.shape)) for v in batch.vols)
+    vols = ";".join("x".join(map(str, v.shape)) + (f"/m{v.macro}" if v.macro else "") for v in batch.vols)
     dets = sorted({(j.geom.nu, j.geom.nv) for j in batch.jobs})
     return f"vols={vols}|det={dets}|jobs={len(batch.jobs)}"
 

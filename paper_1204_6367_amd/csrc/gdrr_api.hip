@@ -92,7 +92,7 @@ int check_volume(const gdrr_volume* v) {
     if ((long long)v->nx * v->ny * v->nz >= (1ll << 31)) return fail(GDRR_EINVAL, "volume has 2^31 voxels or more");
     if (!(v->dx_mm > 0 && v->dy_mm > 0 && v->dz_mm > 0)) return fail(GDRR_EINVAL, "voxel sizes must be > 0");
     if (!v->density || !v->material) return fail(GDRR_EINVAL, "volume density/material pointer is NULL");
-    if (v->macro < 0 || v->macro > 64) return fail(GDRR_EINVAL, "volume macro must be in [0, 64]");
+    if (v->macro < 0 || v->macro > 256) return fail(GDRR_EINVAL, "volume macro must be in [0, 256]");
     if (v->macro > 0 && (!(v->macro_margin >= 0.0f) || !std::isfinite(v->macro_margin)))
         return fail(GDRR_EINVAL, "volume macro_margin must be finite and >= 0");
     return GDRR_OK;

@@ -96,7 +96,7 @@ def _call(abi, vol, phys, src, geom, n=1000, ws_bytes=1 << 30, tally=0x2000):
     (lambda v, p, s, g: setattr(v, "nx", 0), "dimensions"),
     (lambda v, p, s, g: setattr(v, "dx_mm", -1.0), "voxel sizes"),
     (lambda v, p, s, g: setattr(v, "density", None), "pointer"),
-    (lambda v, p, s, g: setattr(v, "macro", 65), "macro"),
+    (lambda v, p, s, g: setattr(v, "macro", 257), "macro"),
     (lambda v, p, s, g: (setattr(v, "macro", 2), setattr(v, "macro_margin", -1.0)), "macro_margin"),
     (lambda v, p, s, g: setattr(p, "n_mat", 17), "n_mat"),
     (lambda v, p, s, g: setattr(p, "n_e", 1), "n_e"),
