@@ -100,6 +100,11 @@ int check_volume(const gdrr_volume* v) {
 
 int cubes(int n, int m) { return (n + m - 1) / m; }
 
+#ifndef GDRR_MACRO_LDS_MAX
+#define GDRR_MACRO_LDS_MAX (32 << 10)
+#endif
+constexpr size_t kMacroLdsMax = GDRR_MACRO_LDS_MAX;   // bytes of cube records staged in LDS
+
 int check_physics(const gdrr_physics* p) {
     if (!p) return fail(GDRR_EINVAL, "physics is NULL");
     if (p->n_mat < 1 || p->n_mat > GDRR_MAX_MATERIALS) return fail(GDRR_EINVAL, "n_mat must be in [1, 16]");
@@ -460,8 +465,27 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     bool local = false;
     for (int v = 0; v < B.n_vols; ++v) local |= B.vols[v].macro > 0;
     const int block = tune.block ? tune.block : (scheme == 2 ? 512 : 256);
+    // local majorants go to LDS (after the tables) while all volumes' records fit in kMacroLdsMax
+    int macro_lds[GDRR_MAX_VOLUMES];
+    int macro_lds_n = 0;
+    for (int v = 0; v < GDRR_MAX_VOLUMES; ++v) macro_lds[v] = -1;
+    if (local && scheme != 2) {
+        size_t n = 0;
+        for (int v = 0; v < B.n_vols; ++v)
+            if (B.vols[v].macro > 0)
+                n += (size_t)cubes(B.vols[v].nx, B.vols[v].macro) * cubes(B.vols[v].ny, B.vols[v].macro) *
+                     cubes(B.vols[v].nz, B.vols[v].macro);
+        if (n * sizeof(uint2) <= kMacroLdsMax)
+            for (int v = 0; v < B.n_vols; ++v)
+                if (B.vols[v].macro > 0) {
+                    macro_lds[v] = macro_lds_n;
+                    macro_lds_n += cubes(B.vols[v].nx, B.vols[v].macro) * cubes(B.vols[v].ny, B.vols[v].macro) *
+                                   cubes(B.vols[v].nz, B.vols[v].macro);
+                }
+    }
     const size_t lds = scheme == 2 ? queue_lds_bytes(phys->n_mat, phys->n_e, B.n_vols, phys->response != nullptr, block)
-                                   : lds_bytes(phys->n_mat, phys->n_e, B.n_vols, phys->response != nullptr);
+                                   : lds_bytes(phys->n_mat, phys->n_e, B.n_vols, phys->response != nullptr) +
+                                         (size_t)macro_lds_n * sizeof(uint2);
     if (lds > dev.lds_max) return fail(GDRR_ENOTSUP, "tables and queues exceed the LDS of a workgroup");
     int per_cu = tune.blocks_per_cu;
     if (!per_cu) {
@@ -646,6 +670,8 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     kp.t_steps = B.t_steps; kp.t_nc = B.t_nc; kp.t_nr = B.t_nr;
     kp.adj = B.adj;
     kp.grad = B.grad;
+    for (int v = 0; v < kMaxVol; ++v) kp.macro_lds[v] = v < GDRR_MAX_VOLUMES ? macro_lds[v] : -1;
+    kp.macro_lds_n = macro_lds_n;
     const void* mf = mc_func_for(B.mode, scheme, local);
     int timed = -1;
     if (chunks > 0) {

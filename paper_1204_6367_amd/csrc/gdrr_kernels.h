@@ -48,6 +48,9 @@ struct KParams {
     // adjoint (backward mode)
     const double* adj;
     double* grad;
+    // local majorants staged in LDS after the tables: per volume the offset (uint2 units) or -1
+    int macro_lds[kMaxVol];
+    int macro_lds_n;          // records staged in total
 };
 
 // LDS holds what every free flight reads: the total attenuation per
@@ -353,7 +356,8 @@ __device__ __forceinline__ bool flight(const KParams& P, const Tables& T, const 
 // last cube is an escape.  Returns true after a null collision.
 template <int MODE>
 __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, const DVolume& V, int vo,
-                                             bool interp, Photon& ph, uint32_t ra, uint32_t rb) {
+                                             bool interp, Photon& ph, uint32_t ra, uint32_t rb,
+                                             const uint2* lds_rec) {
     if (ph.step >= kMaxSteps) {
         if (MODE == kModeTrace) trace_out<MODE>(P, ph, kLost, -1);
         ph.st = kDead;
@@ -364,48 +368,58 @@ __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, 
     int bx = min(max((int)floorf((ph.px - V.lox) * V.imx), 0), V.mnx - 1);
     int by = min(max((int)floorf((ph.py - V.loy) * V.imy), 0), V.mny - 1);
     int bz = min(max((int)floorf((ph.pz - V.loz) * V.imz), 0), V.mnz - 1);
+    // Distances along the line (from the flight's start) to the next cube face
+    // on each axis, advanced by one cube edge per crossing (Amanatides-Woo);
+    // on the positive side the last cube ends at the box face.
     const float rx = ph.dx != 0.0f ? fast_rcp(ph.dx) : 0.0f;
     const float ry = ph.dy != 0.0f ? fast_rcp(ph.dy) : 0.0f;
     const float rz = ph.dz != 0.0f ? fast_rcp(ph.dz) : 0.0f;
     const int sx = ph.dx > 0.0f ? 1 : (ph.dx < 0.0f ? -1 : 0);
     const int sy = ph.dy > 0.0f ? 1 : (ph.dy < 0.0f ? -1 : 0);
     const int sz = ph.dz > 0.0f ? 1 : (ph.dz < 0.0f ? -1 : 0);
+    const float bex = sx > 0 ? (V.hix - ph.px) * rx : INFINITY;       // box exit on the positive side
+    const float bey = sy > 0 ? (V.hiy - ph.py) * ry : INFINITY;
+    const float bez = sz > 0 ? (V.hiz - ph.pz) * rz : INFINITY;
+    float tmx = sx > 0 ? fminf((V.lox + (float)(bx + 1) * V.mex - ph.px) * rx, bex)
+              : (sx < 0 ? (V.lox + (float)bx * V.mex - ph.px) * rx : INFINITY);
+    float tmy = sy > 0 ? fminf((V.loy + (float)(by + 1) * V.mey - ph.py) * ry, bey)
+              : (sy < 0 ? (V.loy + (float)by * V.mey - ph.py) * ry : INFINITY);
+    float tmz = sz > 0 ? fminf((V.loz + (float)(bz + 1) * V.mez - ph.pz) * rz, bez)
+              : (sz < 0 ? (V.loz + (float)bz * V.mez - ph.pz) * rz : INFINITY);
+    const float dtx = V.mex * fabsf(rx), dty = V.mey * fabsf(ry), dtz = V.mez * fabsf(rz);
     const float2* tot = T.tot + ph.ec.j;
-    float mb = 0.0f;
+    float mb = 0.0f, t = 0.0f;
     bool hit = false;
     for (;;) {
-        const uint2 rec = V.macro[(bz * V.mny + by) * V.mnx + bx];
+        const int ci = (bz * V.mny + by) * V.mnx + bx;
+        const uint2 rec = lds_rec ? lds_rec[ci] : V.macro[ci];
         float tmax = 0.0f;
         for (uint32_t mask = rec.y; mask; mask &= mask - 1u) {
             const float2 tt = tot[(__builtin_ctz(mask)) * P.n_e];
             tmax = fmaxf(tmax, tt.x + ph.ec.f * tt.y);
         }
         mb = __uint_as_float(rec.x) * tmax;
-        // distance to the cube's exit face along each axis (the last cube ends at the box face)
-        const float fx = sx > 0 ? fminf(V.lox + (float)(bx + 1) * V.mex, V.hix) : V.lox + (float)bx * V.mex;
-        const float fy = sy > 0 ? fminf(V.loy + (float)(by + 1) * V.mey, V.hiy) : V.loy + (float)by * V.mey;
-        const float fz = sz > 0 ? fminf(V.loz + (float)(bz + 1) * V.mez, V.hiz) : V.loz + (float)bz * V.mez;
-        const float tx = sx ? (fx - ph.px) * rx : INFINITY;
-        const float ty = sy ? (fy - ph.py) * ry : INFINITY;
-        const float tz = sz ? (fz - ph.pz) * rz : INFINITY;
-        const float texit = fmaxf(fminf(tx, fminf(ty, tz)), 0.0f);
-        const float need = 0.1f * mb * texit;              // mbar in 1/cm, lengths in mm
+        const float tnext = fminf(tmx, fminf(tmy, tmz));
+        const float need = 0.1f * mb * fmaxf(tnext - t, 0.0f);   // mbar in 1/cm, lengths in mm
         if (mb > 0.0f && tau < need) {
-            const float s = tau * fast_rcp(0.1f * mb);
-            ph.px += s * ph.dx;
-            ph.py += s * ph.dy;
-            ph.pz += s * ph.dz;
+            t += tau * fast_rcp(0.1f * mb);
             hit = true;
             break;
         }
         tau -= need;
-        ph.px += texit * ph.dx;
-        ph.py += texit * ph.dy;
-        ph.pz += texit * ph.dz;
-        if (tx <= ty && tx <= tz) { bx += sx; if (bx < 0 || bx >= V.mnx) break; }
-        else if (ty <= tz) { by += sy; if (by < 0 || by >= V.mny) break; }
-        else { bz += sz; if (bz < 0 || bz >= V.mnz) break; }
+        t = fmaxf(t, tnext);
+        const bool ax = tmx <= tmy && tmx <= tmz, ay = !ax && tmy <= tmz, az = !ax && !ay;
+        bx += ax ? sx : 0;
+        by += ay ? sy : 0;
+        bz += az ? sz : 0;
+        tmx = ax ? fminf(tmx + dtx, bex) : tmx;
+        tmy = ay ? fminf(tmy + dty, bey) : tmy;
+        tmz = az ? fminf(tmz + dtz, bez) : tmz;
+        if (bx < 0 || bx >= V.mnx || by < 0 || by >= V.mny || bz < 0 || bz >= V.mnz) break;
     }
+    ph.px += t * ph.dx;
+    ph.py += t * ph.dy;
+    ph.pz += t * ph.dz;
     if (!hit) {
         int pixel;
         const int cls = detector_pixel(P.jobs[ph.job], ph, pixel);
@@ -496,6 +510,14 @@ template <int MODE, bool LOCAL>
 __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
     extern __shared__ float2 lds[];
     const Tables T = stage_tables(P, lds);
+    // local majorants small enough to stage: every volume's cube records after the tables
+    uint2* lds_macro = reinterpret_cast<uint2*>(lds + table_floats2(P.n_mat, P.n_e, P.n_vols, P.response != nullptr));
+    if (LOCAL)
+        for (int v = 0; v < P.n_vols; ++v) {
+            if (P.macro_lds[v] < 0 || !P.vol[v].macro) continue;
+            const int n = P.vol[v].mnx * P.vol[v].mny * P.vol[v].mnz;
+            for (int i = threadIdx.x; i < n; i += blockDim.x) lds_macro[P.macro_lds[v] + i] = P.vol[v].macro[i];
+        }
     __syncthreads();
     const bool interp = (P.flags & 1u) != 0;
     const int lane = __lane_id();
@@ -582,8 +604,9 @@ __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
             ph.pair += 1u;
             const Block b = philox(ph.pid, ph.jid, ph.pair, 0u, P.k0, P.k1);
             if (LOCAL && V.macro) {
-                if (flight_local<MODE>(P, T, V, vo, interp, ph, b.x, b.y))
-                    flight_local<MODE>(P, T, V, vo, interp, ph, b.z, b.w);
+                const uint2* lr = P.macro_lds[w_vol] >= 0 ? lds_macro + P.macro_lds[w_vol] : nullptr;
+                if (flight_local<MODE>(P, T, V, vo, interp, ph, b.x, b.y, lr))
+                    flight_local<MODE>(P, T, V, vo, interp, ph, b.z, b.w, lr);
             } else if (flight<MODE>(P, T, V, vo, interp, ph, b.x, b.y)) {
                 flight<MODE>(P, T, V, vo, interp, ph, b.z, b.w);
             }
