@@ -100,9 +100,14 @@ def kernel_sources_sha() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(path, workload):
-    """HBM bytes per transport launch from rocprofv3 FETCH_SIZE + WRITE_SIZE
-    (scaled by the copy calibration), if they were taken on this kernel."""
+TRAFFIC_PATH = None
+
+
+def measured_traffic(path, workload, kernel=None):
+    """Memory-side bytes per launch of a kernel from rocprofv3 FETCH_SIZE +
+    WRITE_SIZE (scaled by the copy calibration), if they were taken on the
+    current kernel sources.  `kernel` selects a secondary record
+    (e.g. "raytrace_kernel") of the workload."""
     if not path or not os.path.exists(path):
         return None
     try:
@@ -111,6 +116,10 @@ def measured_traffic(path, workload):
         return None
     if not rec or rec.get("kernel_sha") != kernel_sources_sha():
         return None
+    if kernel is not None:
+        rec = rec.get("others", {}).get(kernel)
+        if not rec:
+            return None
     return round(rec["fetch_bytes"] + rec["write_bytes"], 0)
 
 
@@ -317,10 +326,11 @@ def raytrace_leg(wl, api, torch, steps, cpu):
     iv = rt_intervals(batch, dl_of)
     alu = iv * SLOTS_RT_INTERVAL / (kms * 1e-3) / 1e12
     gbs = iv * BYTES_RT_INTERVAL / (kms * 1e-3) / 1e9
+    tr = measured_traffic(TRAFFIC_PATH, wl["config"]["workload"], "raytrace_kernel")
     ra = dict(bound="alu", achieved=round(alu, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Tops/s",
-              frac=round(alu / ALU_PEAK_TOPS, 4), traffic=None)
+              frac=round(alu / ALU_PEAK_TOPS, 4), traffic=tr)
     rh = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-              frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None)
+              frac=round(gbs / HBM_PEAK_GBS, 4), traffic=tr)
     out = dict(images=len(batch.jobs), kernel_ms=round(kms, 3), wall_ms=round(float(np.mean(walls)), 3),
                images_per_s=round(len(batch.jobs) / (kms * 1e-3), 1), rays_per_s=round(rays / (kms * 1e-3), 1),
                intervals=iv, intervals_per_s=round(iv / (kms * 1e-3), 1),
@@ -385,7 +395,8 @@ def denoise_leg(wl, api, torch, steps, rt_images, cpu):
     out = dict(images=n, iters=DENOISE_ITERS, omega=0.8, beta_times_median=4.0, kernel_ms=round(kms, 3),
                pixel_sweeps_per_s=round(px * DENOISE_ITERS / (kms * 1e-3), 1),
                roofline=dict(bound="alu", achieved=round(slots, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Tops/s",
-                             frac=round(slots / ALU_PEAK_TOPS, 4), traffic=None),
+                             frac=round(slots / ALU_PEAK_TOPS, 4),
+                             traffic=measured_traffic(TRAFFIC_PATH, wl["config"]["workload"], "denoise_kernel")),
                noise=dict(wall_ms=round(nms, 3), alpha=round(alpha, 6),
                           roofline=dict(bound="hbm", achieved=round(px * BYTES_NOISE / (nms * 1e-3) / 1e9, 1),
                                         peak=HBM_PEAK_GBS, unit="GB/s",
@@ -492,9 +503,10 @@ def main():
               f"across GPUs with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
 
-    global TUNE_MODE, TUNE_CACHE, MAJORANT, CUBE_MM
+    global TUNE_MODE, TUNE_CACHE, MAJORANT, CUBE_MM, TRAFFIC_PATH
     TUNE_MODE = args.tune
     MAJORANT, CUBE_MM = args.majorant, args.cube_mm
+    TRAFFIC_PATH = args.traffic
     from paper_1204_6367_amd import autotune as _at
     TUNE_CACHE = args.tune_cache or _at.DEFAULT_CACHE
     import torch
