@@ -43,7 +43,7 @@ class _Problem(C.Structure):
         ("mu", C.c_void_p), ("response", C.c_void_p),
         ("x0_rayleigh", C.c_double), ("e_cut", C.c_double),
         ("n_spec", C.c_int32),
-        ("spec_e", C.c_void_p), ("spec_p", C.c_void_p), ("fluence", C.c_void_p),
+        ("spec_e", C.c_void_p), ("spec_p", C.c_void_p), ("spec_rows", C.c_int32), ("fluence", C.c_void_p),
         ("sad", C.c_double), ("aid", C.c_double), ("phi", C.c_double), ("theta", C.c_double),
         ("nu", C.c_int32), ("nv", C.c_int32),
         ("du", C.c_double), ("dv", C.c_double),
@@ -122,6 +122,13 @@ class Problem:
         s.mu, s.response = _ptr(self.mu), _ptr(self.response)
         s.x0_rayleigh, s.e_cut = float(x0_rayleigh), float(e_cut_kev)
         s.n_spec = self.spec_e.shape[0]
+        # a [nu][n_spec] table is the joint source phi(E|u): one spectrum per detector column
+        if self.spec_p.ndim == 2:
+            if self.spec_p.shape != (self.nu, s.n_spec):
+                raise ValueError("a joint spectrum table must be [nu][n_spec]")
+            s.spec_rows = self.nu
+        elif self.spec_p.shape != (s.n_spec,):
+            raise ValueError("spec_p must be [n_spec] or [nu][n_spec]")
         s.spec_e, s.spec_p, s.fluence = _ptr(self.spec_e), _ptr(self.spec_p), _ptr(self.fluence)
         s.sad, s.aid, s.phi, s.theta = float(sad_mm), float(aid_mm), float(phi_rad), float(theta_rad)
         s.nu, s.nv = self.nu, self.nv

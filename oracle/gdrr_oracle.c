@@ -15,7 +15,10 @@
  *             voxel phantom (material index + density), the mass attenuation
  *             tables mu_k(i,E) (k = Rayleigh, Compton, photoelectric), the
  *             spectrum phi(E) and fluence map w(u) as normalised pdfs, and the
- *             detector response r(E).
+ *             detector response r(E).  Optionally the spectrum varies with
+ *             the detector column the photon is aimed at (a joint pdf
+ *             w(u) phi(E|u), the fuller form of a source after a bowtie); the
+ *             aim pixel is drawn first, then the energy from its column's row.
  *   Sec. 2.3  Eq. 1 (Beer-Lambert primary): the ray-tracing sum over
  *             intervals of length dl with trilinearly interpolated attenuation
  *             at their midpoints, and, as a check of the MC, the same
@@ -64,7 +67,9 @@ typedef struct {
     double e_cut;                      /* keV */
     int32_t n_spec;
     const float* spec_e;               /* [n_spec] keV */
-    const float* spec_p;               /* [n_spec] */
+    const float* spec_p;               /* [n_spec], or [nu][n_spec] when spec_rows = nu */
+    int32_t spec_rows;                 /* 0 or 1: one spectrum phi(E) for every direction; nu: row iu is
+                                          the spectrum of photons aimed at detector column iu (joint E|u) */
     const float* fluence;              /* [nv][nu] */
     double sad, aid, phi, theta;       /* mm, rad */
     int32_t nu, nv;
@@ -147,6 +152,15 @@ int or_sample_cdf(const float* w, int32_t n, const double* u, int64_t m, int32_t
     return 0;
 }
 
+/* Spectrum of the photons aimed at detector column iu: the only one, or its
+ * row of the joint table phi(E|u) (a bowtie hardens the beam differently
+ * along u; the fluence map stays the marginal w(u) of the aim pixel). */
+static int spec_rows(const or_problem* p) { return p->spec_rows > 1 ? p->spec_rows : 1; }
+static const float* spec_row(const or_problem* p, int iu)
+{
+    return p->spec_p + (p->spec_rows > 1 ? (size_t)iu * p->n_spec : 0);
+}
+
 /* ------------------------------------------------------------------------ */
 /* Geometry, Sec. 2.1: the source S rotates in the xOy plane at distance SAD */
 /* with phi the angle from +x to SO; the detector is perpendicular to xOy    */
@@ -157,7 +171,7 @@ typedef struct {
     double S[3], P[3], n[3], eu[3], ev[3];
     double lo[3], hi[3], vs[3];
     int nvox[3];
-    double* cdf_e;
+    double* cdf_e;                     /* [rows][n_spec] */
     double* cdf_f;
     const double* mbar;                /* [n_e - 1], 1/cm */
     int nb[3];                         /* macro cells per axis (local majorants) */
@@ -606,9 +620,10 @@ static void history(const or_problem* p, const or_ctx* c, uint32_t i, or_outcome
 {
     uint32_t x[4];
     rblock(c, i, 0, 0, x);
-    int ke = cdf_search(c->cdf_e, p->n_spec, u53(x[0], x[1]));
     int kf = cdf_search(c->cdf_f, p->nu * p->nv, u53(x[2], x[3]));
     int iu = kf % p->nu, iv = kf / p->nu;
+    int row = p->spec_rows > 1 ? iu : 0;
+    int ke = cdf_search(c->cdf_e + (size_t)row * p->n_spec, p->n_spec, u53(x[0], x[1]));
     rblock(c, i, 0, 1, x);
     double ju = u24(x[0]), jv = u24(x[1]);
     double E = (double)p->spec_e[ke];
@@ -727,6 +742,7 @@ static int validate(const or_problem* p)
     if (!p->density || !p->material || !p->mu || !p->spec_e || !p->spec_p || !p->fluence) return -1;
     if (p->n_mat < 1 || p->n_mat > 256 || p->n_e < 2 || !(p->de > 0)) return -1;
     if (p->n_spec < 1 || p->nu < 1 || p->nv < 1 || !(p->du > 0 && p->dv > 0)) return -1;
+    if (p->spec_rows < 0 || (p->spec_rows > 1 && p->spec_rows != p->nu)) return -1;
     double emax = p->e0 + p->de * (p->n_e - 1);
     for (int k = 0; k < p->n_spec; ++k)
         if (!(p->spec_e[k] >= p->e0 && p->spec_e[k] <= emax)) return -1;
@@ -743,10 +759,11 @@ static int make_ctx(const or_problem* p, uint64_t seed, uint32_t job, int interp
 {
     memset(c, 0, sizeof(*c));
     setup_geometry(p, c);
-    c->cdf_e = (double*)malloc(sizeof(double) * (size_t)p->n_spec);
+    c->cdf_e = (double*)malloc(sizeof(double) * (size_t)spec_rows(p) * p->n_spec);
     c->cdf_f = (double*)malloc(sizeof(double) * (size_t)p->nu * p->nv);
     if (!c->cdf_e || !c->cdf_f) return -1;
-    if (build_cdf(p->spec_p, p->n_spec, c->cdf_e)) return -1;
+    for (int r = 0; r < spec_rows(p); ++r)
+        if (build_cdf(spec_row(p, r), p->n_spec, c->cdf_e + (size_t)r * p->n_spec)) return -1;
     if (build_cdf(p->fluence, p->nu * p->nv, c->cdf_f)) return -1;
     c->mbar = mbar;
     if (p->macro > 0 && build_macro(p, c)) return -1;
@@ -1016,7 +1033,8 @@ int or_rho_integrals(const or_problem* p, int32_t interp, const double* a, const
 /*
  * Expected primary tally E[P_hat] per pixel ([nv][nu], per source photon):
  *   sum_j phi_j W_p r(E_j) <exp(-int mu dl)>_p
- * where phi_j, W_p are the normalised spectrum and fluence weights and <.>_p
+ * where phi_j, W_p are the normalised spectrum (the row of the pixel's column
+ * for a joint source) and fluence weights and <.>_p
  * averages over the pixel (the aim point is uniform inside it) with an
  * nq x nq Gauss-Legendre rule.
  */
@@ -1044,8 +1062,7 @@ int or_primary_exact(const or_problem* p, int32_t interp, int32_t nq, double* ou
         gx[k] = 0.5 * (1.0 - z);
         gw[k] = 1.0 / ((1.0 - z * z) * dp * dp);
     }
-    double sp = 0.0, sf = 0.0;
-    for (int k = 0; k < p->n_spec; ++k) sp += p->spec_p[k];
+    double sf = 0.0;
     for (int k = 0; k < p->nu * p->nv; ++k) sf += p->fluence[k];
     double* ri = (double*)malloc(sizeof(double) * (size_t)p->n_mat);
     double* muj = (double*)malloc(sizeof(double) * (size_t)p->n_spec * p->n_mat);
@@ -1058,6 +1075,9 @@ int or_primary_exact(const or_problem* p, int32_t interp, int32_t nq, double* ou
         }
     for (int iv = 0; iv < p->nv; ++iv)
         for (int iu = 0; iu < p->nu; ++iu) {
+            const float* phi = spec_row(p, iu);
+            double sp = 0.0;
+            for (int k = 0; k < p->n_spec; ++k) sp += phi[k];
             double acc = 0.0;
             for (int qa = 0; qa < nq; ++qa)
                 for (int qb = 0; qb < nq; ++qb) {
@@ -1070,7 +1090,7 @@ int or_primary_exact(const or_problem* p, int32_t interp, int32_t nq, double* ou
                     for (int k = 0; k < p->n_spec; ++k) {
                         double li = 0.0;
                         for (int m = 0; m < p->n_mat; ++m) li += muj[(size_t)k * p->n_mat + m] * ri[m];
-                        e_sum += (p->spec_p[k] / sp) * response_at(p, p->spec_e[k]) * exp(-0.1 * li);
+                        e_sum += (phi[k] / sp) * response_at(p, p->spec_e[k]) * exp(-0.1 * li);
                     }
                     acc += gw[qa] * gw[qb] * e_sum;
                 }
@@ -1156,7 +1176,8 @@ int or_rho_integrals_many(const or_problem* p, int32_t interp, const double* a, 
 /* interpolation of the voxel attenuation coefficients rho_v mu_tot(m_v, E)  */
 /* on the lattice of voxel centres (clamped at the edges); with the          */
 /* interpolation off it is the containing voxel's value.  dl <= 0 selects    */
-/* half of the smallest voxel edge.  phi and w are normalised to sum 1.      */
+/* half of the smallest voxel edge.  phi and w are normalised to sum 1; for */
+/* a joint source phi is the row of the pixel's column.                      */
 /* Pixels: the m indices iv * nu + iu in pix, or all pixels when pix is      */
 /* NULL (out is then [nv][nu]).                                              */
 /* ------------------------------------------------------------------------ */
@@ -1179,10 +1200,14 @@ int or_primary_raytrace(const or_problem* p, int32_t interp, double dl, const in
     or_ctx c;
     memset(&c, 0, sizeof(c));
     setup_geometry(p, &c);
-    double sp = 0.0, sf = 0.0;
-    for (int k = 0; k < p->n_spec; ++k) sp += p->spec_p[k];
+    double sf = 0.0;
     for (int k = 0; k < p->nu * p->nv; ++k) sf += p->fluence[k];
-    if (!(sp > 0.0) || !(sf > 0.0)) return -1;
+    if (!(sf > 0.0)) return -1;
+    for (int r = 0; r < spec_rows(p); ++r) {
+        double sp = 0.0;
+        for (int k = 0; k < p->n_spec; ++k) sp += spec_row(p, r)[k];
+        if (!(sp > 0.0)) return -1;
+    }
     /* total mass attenuation of every material at every channel energy */
     double* mut = (double*)malloc(sizeof(double) * (size_t)p->n_spec * p->n_mat);
     if (!mut) return -1;
@@ -1242,9 +1267,11 @@ int or_primary_raytrace(const or_problem* p, int32_t interp, double dl, const in
                     }
                 }
             }
-            double acc = 0.0;
+            const float* phi = spec_row(p, iu);
+            double sp = 0.0, acc = 0.0;
+            for (int k = 0; k < p->n_spec; ++k) sp += phi[k];
             for (int k = 0; k < p->n_spec; ++k)       /* mm * 1/cm -> 0.1 */
-                acc += (p->spec_p[k] / sp) * response_at(p, p->spec_e[k]) * exp(-0.1 * L[k]);
+                acc += (phi[k] / sp) * response_at(p, p->spec_e[k]) * exp(-0.1 * L[k]);
             out[q] = ((double)p->fluence[id] / sf) * acc;
         }
         free(L);

@@ -19,7 +19,9 @@ synthetic and seeded:
 * spectrum: Kramers' thick-target law filtered by aluminium;
 * fluence map: an isotropic point source seen by the flat detector, optionally
   multiplied by a cosine-profile aluminium bowtie (the source is defined after
-  the bowtie, Sec. 2.1);
+  the bowtie, Sec. 2.1); optionally also the bowtie's hardening of the
+  spectrum column by column (a joint source phi(E|u), one spectrum per
+  detector column);
 * phantoms: a water sphere in air, and ellipsoid "pelvis-like" phantoms.
 """
 from __future__ import annotations
@@ -185,19 +187,48 @@ def fluence_map(geom: Geometry, bowtie_mm: float = 0.0, spectrum=None,
     if bowtie_mm > 0.0:
         if spectrum is None:
             raise ValueError("bowtie needs the spectrum it hardens")
-        e, p = spectrum
-        al = MATERIALS["aluminium"]
-        mu_al = mass_attenuation(al, np.asarray(e, np.float64)).sum(-1) * al.density * 0.1  # 1/mm
-        gmax = math.atan(0.5 * geom.nu * geom.du_mm / sdd)
-        gam = np.arctan(np.abs(uq) / sdd)                                # [nu][q]
-        thick = bowtie_mm * (1.0 - np.cos(0.5 * math.pi * gam / gmax))
-        trans = (np.asarray(p, np.float64)[None, None, :] *
-                 np.exp(-mu_al[None, None, :] * thick[..., None])).sum(-1)  # [nu][q]
+        trans = (np.asarray(spectrum[1], np.float64)[None, None, :] *
+                 _bowtie_transmission(geom, bowtie_mm, spectrum[0], uq)).sum(-1)  # [nu][q]
         geo = geo * trans[None, :, None, :]
     f = (geo * w[None, None, :, None] * w[None, None, None, :]).sum(axis=(2, 3))
     f = f * geom.du_mm * geom.dv_mm
     f /= f.sum()
     return f.astype(np.float32)
+
+
+def _bowtie_transmission(geom: Geometry, bowtie_mm: float, spec_e, uq: np.ndarray) -> np.ndarray:
+    """exp(-mu_Al(E) t(u)) at detector abscissae uq (any shape) for every
+    channel energy: [*uq.shape, n_spec].  t = bowtie_mm (1 - cos(pi g / (2 gmax)))
+    at fan angle g toward u; gmax is the fan angle of the detector edge."""
+    sdd = geom.sad_mm + geom.aid_mm
+    al = MATERIALS["aluminium"]
+    mu_al = mass_attenuation(al, np.asarray(spec_e, np.float64)).sum(-1) * al.density * 0.1  # 1/mm
+    gmax = math.atan(0.5 * geom.nu * geom.du_mm / sdd)
+    gam = np.arctan(np.abs(uq) / sdd)
+    thick = bowtie_mm * (1.0 - np.cos(0.5 * math.pi * gam / gmax))
+    return np.exp(-mu_al * thick[..., None])
+
+
+def bowtie_spectra(geom: Geometry, bowtie_mm: float, spectrum, quad: int = 4) -> np.ndarray:
+    """Joint source after a bowtie: the spectrum of the photons aimed at each
+    detector column, [nu][n_spec] float32, each row summing to 1.
+
+    Row iu is phi(E) times the bowtie transmission at E averaged over the
+    column (Gauss-Legendre in u, weighted by the point source's solid angle
+    integrated over v); the marginal of the aim pixel is `fluence_map` with
+    the same bowtie."""
+    sdd = geom.sad_mm + geom.aid_mm
+    t, w = np.polynomial.legendre.leggauss(quad)
+    w = w / 2.0
+    ue = (np.arange(geom.nu) - geom.nu / 2.0) * geom.du_mm
+    ve = (np.arange(geom.nv) - geom.nv / 2.0) * geom.dv_mm
+    uq = ue[:, None] + (0.5 * (t + 1.0))[None, :] * geom.du_mm          # [nu][q]
+    vq = (ve[:, None] + (0.5 * (t + 1.0))[None, :] * geom.dv_mm).ravel()
+    col = (sdd / (sdd**2 + uq[..., None]**2 + vq**2) ** 1.5) @ np.tile(w, geom.nv)   # [nu][q]
+    trans = _bowtie_transmission(geom, bowtie_mm, spectrum[0], uq)       # [nu][q][n_spec]
+    rows = np.asarray(spectrum[1], np.float64) * ((col * w)[..., None] * trans).sum(1)
+    rows /= rows.sum(1, keepdims=True)
+    return rows.astype(np.float32)
 
 
 # --- phantoms ----------------------------------------------------------------
@@ -308,7 +339,7 @@ def physics_for(ph: Phantom, grid: EnergyGrid = EnergyGrid(), response=None) -> 
 @dataclasses.dataclass
 class Source:
     spec_e: np.ndarray      # float32 [n_spec], keV
-    spec_p: np.ndarray      # float32 [n_spec]
+    spec_p: np.ndarray      # float32 [n_spec], or [nu][n_spec]: one spectrum per detector column
     fluence: np.ndarray     # float32 [nv][nu]
 
 
@@ -337,9 +368,13 @@ def sphere_problem(n_photons: int = 1_000_000) -> Problem:
     return Problem(ph, physics_for(ph), src, geom, n_photons, seed=1)
 
 
-def pelvis_source(geom: Geometry):
+def pelvis_source(geom: Geometry, joint: bool = False):
+    """120 kVp + 2.5 mm Al behind a 30 mm Al bowtie.  joint=False: one
+    spectrum for every direction (the bowtie only shapes the fluence map);
+    joint=True: one hardened spectrum per detector column."""
     spec = kramers_spectrum(120.0, 2.5, 1.0)
-    return Source(spec[0], spec[1], fluence_map(geom, bowtie_mm=30.0, spectrum=spec))
+    rows = bowtie_spectra(geom, 30.0, spec) if joint else spec[1]
+    return Source(spec[0], rows, fluence_map(geom, bowtie_mm=30.0, spectrum=spec))
 
 
 def pelvis_problem(n_photons: int = 100_000_000, shape=(160, 256, 256),
