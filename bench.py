@@ -127,6 +127,7 @@ TUNE_MODE = "auto"
 TUNE_CACHE = None
 MAJORANT = "local"
 CUBE_MM = 40.0
+SOURCE = "factorised"        # or "joint": one spectrum per detector column
 
 
 def apply_majorant(vol, margin):
@@ -157,10 +158,16 @@ def autotune_for(batch):
 # ---------------------------------------------------------------------------
 # workloads
 # ---------------------------------------------------------------------------
+SPECTRUM_DESC = {"factorised": "120 kVp Kramers + 2.5 mm Al, bowtie 30 mm Al",
+                 "joint": "120 kVp Kramers + 2.5 mm Al, bowtie 30 mm Al hardening each detector column's spectrum"}
+
+
 def build_workload(name, api, W, torch):
     """Returns dict(step=callable, fwd_histories, adj_histories, oracle_sample=callable, info)."""
     if name in ("c1", "c2"):
         prob = W.pelvis_problem(100_000_000)
+        if SOURCE == "joint":
+            prob.source = W.pelvis_source(prob.geom, joint=True)
         vol, phys, src = api.upload(prob)
         apply_majorant(vol, 2.0**-20)
         if name == "c1":
@@ -184,7 +191,7 @@ def build_workload(name, api, W, torch):
                     tallies=tallies,
                     config=dict(workload=name, phantom="256x256x160 @1.95x1.95x2.5mm ellipsoids",
                                 angles=len(jobs), photons_per_angle=jobs[0].n_photons,
-                                detector="256x192 @1.552mm", spectrum="120 kVp Kramers + 2.5 mm Al, bowtie 30 mm Al",
+                                detector="256x192 @1.552mm", spectrum=SPECTRUM_DESC[SOURCE],
                                 tuning=tune, majorant=majorant_desc([vol])))
     if name in ("c3", "c4"):
         if name == "c3":
@@ -203,7 +210,7 @@ def build_workload(name, api, W, torch):
                 plan.append((v, n_ang, nph))
             adj_vol, adj_jobs_every = 1, 4
         geom = W.Geometry(**W.PELVIS_DET)
-        srcw = W.pelvis_source(geom)
+        srcw = W.pelvis_source(geom, joint=SOURCE == "joint")
         physw = W.physics_for(phantoms[0][0])
         vols = [api.DeviceVolume(ph.density, ph.material, ph.spacing_mm) for ph, _ in phantoms]
         dphys = api.DevicePhysics(physw.mu_mass, physw.grid.e0_kev, physw.grid.de_kev)
@@ -260,7 +267,7 @@ def build_workload(name, api, W, torch):
                        job_id=jobs[adj_idx[0]].job_id, margin=0.1, macro=vols[adj_vol].macro)
         cfg = dict(workload=name, angles=len(jobs), adjoint_angles=len(adj_idx), tuning=tune,
                    majorant=majorant_desc(vols),
-                   detector="256x192 @1.552mm", spectrum="120 kVp Kramers + 2.5 mm Al, bowtie 30 mm Al",
+                   detector="256x192 @1.552mm", spectrum=SPECTRUM_DESC[SOURCE],
                    phantoms=[f"{'x'.join(map(str, ph.shape[::-1]))} @{ph.spacing_mm[0]}mm" for ph, _ in phantoms],
                    photons_per_angle=[p[2] for p in plan])
         def prob_of(k):
@@ -480,6 +487,9 @@ def main():
     ap.add_argument("--majorant", default="local", choices=["local", "global"],
                     help="local: bounds per cube of about --cube-mm (default); global: one per energy interval")
     ap.add_argument("--cube-mm", type=float, default=40.0)
+    ap.add_argument("--source", default="factorised", choices=["factorised", "joint"],
+                    help="factorised: one spectrum, the bowtie folded into the fluence map (default); joint: "
+                         "one bowtie-hardened spectrum per detector column")
     ap.add_argument("--no-global-reference", action="store_true",
                     help="with local majorants, skip the reference forward with the single majorant")
     ap.add_argument("--tune-cache", default=None,
@@ -503,8 +513,9 @@ def main():
               f"across GPUs with no exchange; see the design notes)", file=sys.stderr)
         sys.exit(2)
 
-    global TUNE_MODE, TUNE_CACHE, MAJORANT, CUBE_MM, TRAFFIC_PATH
+    global TUNE_MODE, TUNE_CACHE, MAJORANT, CUBE_MM, TRAFFIC_PATH, SOURCE
     TUNE_MODE = args.tune
+    SOURCE = args.source
     MAJORANT, CUBE_MM = args.majorant, args.cube_mm
     TRAFFIC_PATH = args.traffic
     from paper_1204_6367_amd import autotune as _at

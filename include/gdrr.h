@@ -104,13 +104,22 @@ typedef struct gdrr_physics {
 } gdrr_physics;
 
 /* Source of Sec. 2.1, defined after the bowtie: spectrum phi(E) and fluence
- * map w(u); both are normalised by the library (weights need only be >= 0). */
+ * map w(u); both are normalised by the library (weights need only be >= 0).
+ *
+ * Joint source (spec_rows = fu): spec_prob holds one spectrum per detector
+ * column, row iu being phi(E | column iu), the fuller description of a beam
+ * that a bowtie hardens more toward the edges of the fan.  A photon's aim
+ * pixel is drawn from w first and its energy from the row of that pixel's
+ * column, with the random numbers of the factorised source, so equal rows
+ * reproduce it history for history.  Every row needs a positive sum.
+ * rows * n_spec <= 2^24. */
 typedef struct gdrr_source {
     int32_t n_spec;            /* 1 <= n_spec <= 4096 energy channels */
-    const float* spec_e_kev;   /* [n_spec] channel energies within the physics grid */
-    const float* spec_prob;    /* [n_spec] weights */
+    const float* spec_e_kev;   /* [n_spec] channel energies within the physics grid (shared by all rows) */
+    const float* spec_prob;    /* [n_spec] weights, or [fu][n_spec] when spec_rows = fu */
     int32_t fu, fv;            /* fluence grid = the detector's pixel grid (fu = nu, fv = nv) */
     const float* fluence;      /* [fv][fu] weights */
+    int32_t spec_rows;         /* 0 or 1: one spectrum for every direction; fu: one per detector column */
 } gdrr_source;
 
 /* Geometry of Sec. 2.1 (Fig. 1). */

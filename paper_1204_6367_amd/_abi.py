@@ -43,7 +43,7 @@ class Physics(C.Structure):
 
 class Source(C.Structure):
     _fields_ = [("n_spec", C.c_int32), ("spec_e_kev", C.c_void_p), ("spec_prob", C.c_void_p),
-                ("fu", C.c_int32), ("fv", C.c_int32), ("fluence", C.c_void_p)]
+                ("fu", C.c_int32), ("fv", C.c_int32), ("fluence", C.c_void_p), ("spec_rows", C.c_int32)]
 
 
 class Geometry(C.Structure):

@@ -84,19 +84,25 @@ class DevicePhysics:
 
 
 class DeviceSource:
-    """Spectrum (energies, weights) and fluence map [nv][nu] weights."""
+    """Spectrum (energies, weights) and fluence map [nv][nu] weights.  Weights
+    of shape [nu][n_spec] make a joint source: one spectrum per detector column."""
 
     def __init__(self, spec_e, spec_p, fluence, device=None):
         dev = _dev(device)
         self.spec_e = _t(spec_e, torch.float32, dev)
         self.spec_p = _t(spec_p, torch.float32, dev)
         self.fluence = _t(fluence, torch.float32, dev)
-        assert self.fluence.dim() == 2
+        if self.fluence.dim() != 2:
+            raise ValueError("fluence must be [nv][nu]")
+        n, fu = self.spec_e.shape[0], self.fluence.shape[1]
+        if self.spec_p.shape not in (torch.Size([n]), torch.Size([fu, n])):
+            raise ValueError("spectrum weights must be [n_spec] or [nu][n_spec]")
 
     def struct(self) -> _abi.Source:
         fv, fu = self.fluence.shape
+        rows = fu if self.spec_p.dim() == 2 else 0
         return _abi.Source(self.spec_e.shape[0], self.spec_e.data_ptr(), self.spec_p.data_ptr(), fu, fv,
-                           self.fluence.data_ptr())
+                           self.fluence.data_ptr(), rows)
 
 
 def geometry_struct(g) -> _abi.Geometry:

@@ -77,6 +77,12 @@ struct Carver {
     }
 };
 
+// Rows of a source's spectrum table (one, or one per detector column); -1 if invalid.
+int spec_rows(const gdrr_source& s) {
+    if (s.spec_rows == 0 || s.spec_rows == 1) return 1;
+    return s.spec_rows == s.fu && s.fu > 1 ? s.spec_rows : -1;
+}
+
 uint32_t guide_size(int n) {
     uint32_t k = 1;
     while ((int)k < n && k < (1u << 20)) k <<= 1;
@@ -122,6 +128,8 @@ int check_source(const gdrr_source* s) {
     if (!s->spec_e_kev || !s->spec_prob || !s->fluence) return fail(GDRR_EINVAL, "source pointer is NULL");
     if (s->fu < 1 || s->fv < 1 || (long long)s->fu * s->fv > (1ll << 24))
         return fail(GDRR_EINVAL, "fluence grid must have 1 <= fu*fv <= 2^24");
+    if (spec_rows(*s) < 0) return fail(GDRR_EINVAL, "spec_rows must be 0, 1 or fu");
+    if ((long long)spec_rows(*s) * s->n_spec > (1ll << 24)) return fail(GDRR_EINVAL, "spec_rows * n_spec must be <= 2^24");
     return GDRR_OK;
 }
 
@@ -324,8 +332,9 @@ Layout carve(void* ws, const gdrr_volume* vols, const gdrr_physics* phys, const 
         const int npix = srcs[s].fu * srcs[s].fv;
         L.src[s].spec_k = guide_size(srcs[s].n_spec);
         L.src[s].flu_k = guide_size(npix);
-        L.src[s].spec_cdf = c.take<double>((size_t)srcs[s].n_spec);
-        L.src[s].spec_guide = c.take<uint32_t>(L.src[s].spec_k);
+        const size_t rows = (size_t)spec_rows(srcs[s]);
+        L.src[s].spec_cdf = c.take<double>(rows * srcs[s].n_spec);
+        L.src[s].spec_guide = c.take<uint32_t>(rows * L.src[s].spec_k);
         L.src[s].flu_cdf = c.take<double>((size_t)npix);
         L.src[s].flu_guide = c.take<uint32_t>(L.src[s].flu_k);
     }
@@ -597,10 +606,13 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     for (int s = 0; s < B.n_srcs; ++s) {
         const gdrr_source& S = B.srcs[s];
         const SrcArea& A = L.src[s];
-        SrcPrepParams sp{S.spec_prob, S.n_spec, A.spec_cdf, A.spec_guide, (int)A.spec_k, (unsigned int*)(L.counter + 1)};
-        ls.push_back(make_launch((const void*)&cdf_kernel, dim3(1), dim3(1024), 0, sp));
-        ls.push_back(make_launch((const void*)&guide_kernel, dim3((A.spec_k + 255) / 256), dim3(256), 0, sp));
-        SrcPrepParams fp{S.fluence, S.fu * S.fv, A.flu_cdf, A.flu_guide, (int)A.flu_k, (unsigned int*)(L.counter + 1)};
+        const int rows = spec_rows(S);
+        SrcPrepParams sp{S.spec_prob, S.n_spec, rows, A.spec_cdf, A.spec_guide, (int)A.spec_k,
+                         (unsigned int*)(L.counter + 1)};
+        ls.push_back(make_launch((const void*)&cdf_kernel, dim3(rows), dim3(1024), 0, sp));
+        const unsigned gk = (unsigned)std::min<size_t>((size_t)dev.cus * 8, ((size_t)rows * A.spec_k + 255) / 256);
+        ls.push_back(make_launch((const void*)&guide_kernel, dim3(gk), dim3(256), 0, sp));
+        SrcPrepParams fp{S.fluence, S.fu * S.fv, 1, A.flu_cdf, A.flu_guide, (int)A.flu_k, (unsigned int*)(L.counter + 1)};
         ls.push_back(make_launch((const void*)&cdf_kernel, dim3(1), dim3(1024), 0, fp));
         ls.push_back(make_launch((const void*)&guide_kernel, dim3((A.flu_k + 255) / 256), dim3(256), 0, fp));
     }
@@ -640,6 +652,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
         d.flu_cdf = L.src[s].flu_cdf;
         d.flu_guide = L.src[s].flu_guide;
         d.n_spec = B.srcs[s].n_spec;
+        d.spec_rows = spec_rows(B.srcs[s]);
         d.spec_k = (int)L.src[s].spec_k;
         d.npix = B.srcs[s].fu * B.srcs[s].fv;
         d.flu_k = (int)L.src[s].flu_k;
@@ -702,6 +715,8 @@ size_t batch_bytes(const gdrr_volume* vols, int n_vols, const gdrr_physics* phys
         return 0;
     for (int v = 0; v < n_vols; ++v)
         if (vols[v].nx < 1 || vols[v].ny < 1 || vols[v].nz < 1) return 0;
+    for (int s = 0; s < n_srcs; ++s)
+        if (srcs[s].n_spec < 1 || spec_rows(srcs[s]) < 0) return 0;
     return carve(nullptr, vols, phys, srcs, n_srcs, n_jobs, n_vols, tally_elems_of(jobs, n_jobs, srcs), need_maj).bytes +
            256;
 }
@@ -715,7 +730,7 @@ struct RtLayout {
     unsigned int* unit_first;
     unsigned int* unit_pref;
     long long* out_off;                  // [n_jobs]
-    float* coef[GDRR_MAX_SOURCES];       // [n_spec]
+    float* coef[GDRR_MAX_SOURCES];       // [rows][n_spec]
     float* tab[GDRR_MAX_SOURCES];        // [n_spec][n_mat]
     double* inv_wsum[GDRR_MAX_SOURCES];  // [1]
     CellRec* cells[GDRR_MAX_VOLUMES];    // volumes that some job uses
@@ -762,7 +777,7 @@ RtLayout rt_carve(void* ws, const gdrr_volume* vols, int n_vols, const gdrr_phys
     L.unit_pref = c.take<unsigned int>(units);
     L.out_off = c.take<long long>((size_t)n_jobs);
     for (int s = 0; s < n_srcs; ++s) {
-        L.coef[s] = c.take<float>((size_t)srcs[s].n_spec);
+        L.coef[s] = c.take<float>((size_t)spec_rows(srcs[s]) * srcs[s].n_spec);
         L.tab[s] = c.take<float>((size_t)srcs[s].n_spec * phys->n_mat);
         L.inv_wsum[s] = c.take<double>(1);
     }
@@ -917,8 +932,8 @@ int run_primary(const gdrr_volume* vols, int n_vols, const gdrr_physics* phys, c
         RtPrepParams pp{S.spec_e_kev, S.spec_prob, S.fluence, S.n_spec, S.fu * S.fv, phys->mu_mass, phys->response,
                         phys->n_mat, phys->n_e, (double)phys->e0_kev, (double)phys->de_kev, L.coef[s], L.tab[s],
                         L.inv_wsum[s]};
-        ls.push_back(make_launch((const void*)&raytrace_prep_kernel, dim3(1), dim3(256), 0, pp));
-        rp.src[s] = RtSource{S.fluence, L.coef[s], L.tab[s], L.inv_wsum[s], S.n_spec};
+        ls.push_back(make_launch((const void*)&raytrace_prep_kernel, dim3(spec_rows(S)), dim3(256), 0, pp));
+        rp.src[s] = RtSource{S.fluence, L.coef[s], L.tab[s], L.inv_wsum[s], S.n_spec, spec_rows(S)};
     }
     rp.jobs = L.jobs;
     rp.unit_job = L.unit_job;
@@ -1141,7 +1156,7 @@ size_t gdrr_primary_workspace(const gdrr_volume* vols, int32_t n_vols, const gdr
     for (int v = 0; v < n_vols; ++v)
         if (vols[v].nx < 1 || vols[v].ny < 1 || vols[v].nz < 1) return 0;
     for (int s = 0; s < n_srcs; ++s)
-        if (srcs[s].n_spec < 1) return 0;
+        if (srcs[s].n_spec < 1 || spec_rows(srcs[s]) < 0) return 0;
     return rt_carve(nullptr, vols, n_vols, phys, srcs, n_srcs, jobs, n_jobs).bytes + 256;
 }
 

@@ -105,11 +105,12 @@ struct DVolume {
 
 struct DSource {
     const float* spec_e;      // [n_spec]
-    const double* spec_cdf;   // [n_spec]
-    const uint32_t* spec_guide;  // [spec_k]
+    const double* spec_cdf;   // [rows][n_spec]
+    const uint32_t* spec_guide;  // [rows][spec_k]
     const double* flu_cdf;    // [npix]
     const uint32_t* flu_guide;   // [flu_k]
     int n_spec, spec_k, npix, flu_k;
+    int spec_rows;            // 1, or nu: the spectrum of detector column iu is row iu
 };
 
 // One job, as the kernels read it (global memory, 128 bytes).

@@ -178,8 +178,9 @@ struct Photon {
     float w;                   // adjoint weight of the history
 };
 
-// Source photon (Sec. 2.1/2.4): energy channel and aim pixel by inverse CDF,
-// aim point uniform inside the pixel, straight line from S to the phantom.
+// Source photon (Sec. 2.1/2.4): aim pixel and energy channel by inverse CDF
+// (the energy from the row of the pixel's column for a joint source), aim
+// point uniform inside the pixel, straight line from S to the phantom.
 // Returns true if the photon enters the phantom; otherwise it reaches its
 // aim pixel unscattered.
 __device__ __forceinline__ bool start_photon(const KParams& P, const Tables& T, const DVolume& V, int vol_off,
@@ -188,9 +189,11 @@ __device__ __forceinline__ bool start_photon(const KParams& P, const Tables& T, 
     const DSource& S = P.src[J.src];
     const Block b0 = philox(ph.pid, ph.jid, 0u, 0u, P.k0, P.k1);
     const Block b1 = philox(ph.pid, ph.jid, 0u, 1u, P.k0, P.k1);
-    const int ke = sample_cdf(S.spec_cdf, S.spec_guide, S.n_spec, S.spec_k, u53(b0.x, b0.y));
     const int kf = sample_cdf(S.flu_cdf, S.flu_guide, S.npix, S.flu_k, u53(b0.z, b0.w));
     const int iv = kf / J.nu, iu = kf - iv * J.nu;
+    const int row = S.spec_rows > 1 ? iu : 0;
+    const int ke = sample_cdf(S.spec_cdf + (size_t)row * S.n_spec, S.spec_guide + (size_t)row * S.spec_k, S.n_spec,
+                              S.spec_k, u53(b0.x, b0.y));
     const float uc = ((float)iu + u24(b1.x) - 0.5f * (float)J.nu) * J.du;
     const float vc = ((float)iv + u24(b1.y) - 0.5f * (float)J.nv) * J.dv;
     float dx = J.Px + uc * J.ux - J.Sx;
@@ -768,18 +771,18 @@ __global__ __launch_bounds__(256) void cells_kernel(CellParams C) {
 
 // ---------------------------------------------------------------------------
 // Source preparation: normalised CDFs (running float64 sum in index order,
-// divided by the total) and guide tables.
+// divided by the total) and guide tables, for `rows` tables of n weights.
 // ---------------------------------------------------------------------------
 struct SrcPrepParams {
-    const float* w;
-    int n;
-    double* cdf;
-    uint32_t* guide;
+    const float* w;           // [rows][n]
+    int n, rows;
+    double* cdf;              // [rows][n]
+    uint32_t* guide;          // [rows][k]
     int k;
     unsigned int* error;
 };
 
-// One workgroup of 1024 threads: each thread sums a contiguous segment in
+// One workgroup of 1024 threads per row: each thread sums a contiguous segment in
 // index order, the segment totals are scanned, and each thread writes its
 // segment's running sums divided by the total.  The sums are those of the
 // definition, accumulated in a different association (float64 rounding only).
@@ -787,13 +790,15 @@ __global__ __launch_bounds__(1024) void cdf_kernel(SrcPrepParams S) {
     __shared__ double part[1024];
     __shared__ int bad;
     const int t = threadIdx.x, nt = blockDim.x;
+    const float* w = S.w + (size_t)blockIdx.x * S.n;
+    double* cdf = S.cdf + (size_t)blockIdx.x * S.n;
     if (t == 0) bad = 0;
     const int per = (S.n + nt - 1) / nt;
     const int a = min(S.n, t * per), b = min(S.n, a + per);
     double s = 0.0;
     int mybad = 0;
     for (int i = a; i < b; ++i) {
-        const double x = (double)S.w[i];
+        const double x = (double)w[i];
         if (!(x >= 0.0) || isinf(x)) mybad = 1;
         s += x;
     }
@@ -809,21 +814,26 @@ __global__ __launch_bounds__(1024) void cdf_kernel(SrcPrepParams S) {
     const double total = part[nt - 1];
     double run = t > 0 ? part[t - 1] : 0.0;
     for (int i = a; i < b; ++i) {
-        run += (double)S.w[i];
-        S.cdf[i] = run / total;
+        run += (double)w[i];
+        cdf[i] = run / total;
     }
     if (t == 0 && (bad || !(total > 0.0))) atomicOr(S.error, 4u);
 }
 
 __global__ __launch_bounds__(256) void guide_kernel(SrcPrepParams S) {
-    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < S.k; g += gridDim.x * blockDim.x) {
+    const long long total = (long long)S.rows * S.k;
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+         e += (long long)gridDim.x * blockDim.x) {
+        const long long r = e / S.k;
+        const int g = (int)(e - r * S.k);
+        const double* cdf = S.cdf + r * S.n;
         const double t = (double)g / (double)S.k;
         int lo = 0, hi = S.n - 1;                 // smallest i with cdf[i] > t
         while (lo < hi) {
             const int mid = (lo + hi) >> 1;
-            if (S.cdf[mid] > t) hi = mid; else lo = mid + 1;
+            if (cdf[mid] > t) hi = mid; else lo = mid + 1;
         }
-        S.guide[g] = (uint32_t)lo;
+        S.guide[e] = (uint32_t)lo;
     }
 }
 

@@ -30,10 +30,10 @@ constexpr int kXcds = 8;          // workgroup i runs on XCD i mod 8
 
 struct RtSource {
     const float* fluence;         // [nv][nu] weights w(u) (unnormalised)
-    const float* coef;            // [n_spec] phi_k r(E_k) / sum phi
+    const float* coef;            // [rows][n_spec] phi_k r(E_k) / sum phi (row iu: detector column iu)
     const float* tab;             // [n_spec][n_mat] 0.1 mu_tot(m, E_k): mm of density-length -> optical depth
     const double* inv_wsum;       // 1 / sum_u w(u)
-    int n_spec;
+    int n_spec, rows;
 };
 
 struct RtParams {
@@ -181,6 +181,7 @@ __global__ __launch_bounds__(kRtBlock) void raytrace_kernel(RtParams P) {
 #pragma unroll
     for (int m = 0; m < GDRR_MAX_MATERIALS; ++m) Lr[m] = m < P.n_mat ? Lm[m * kRtBlock] : 0.0f;
     const RtSource& S = P.src[J.src];
+    const float* coef = S.coef + (S.rows > 1 ? iu * S.n_spec : 0);
     float sum = 0.0f;
     for (int k = 0; k < S.n_spec; ++k) {
         const float* row = S.tab + k * P.n_mat;
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(kRtBlock) void raytrace_kernel(RtParams P) {
 #pragma unroll
         for (int m = 0; m < GDRR_MAX_MATERIALS; ++m)
             if (m < P.n_mat) tau += row[m] * Lr[m];
-        sum += S.coef[k] * expf(-tau);
+        sum += coef[k] * expf(-tau);
     }
     const int pix = iv * J.nu + iu;
     const double val = (double)S.fluence[pix] * S.inv_wsum[0] * (double)sum;
@@ -196,11 +197,12 @@ __global__ __launch_bounds__(kRtBlock) void raytrace_kernel(RtParams P) {
     *o = P.accumulate ? *o + val : val;
 }
 
-// Per source: the channel weights phi_k r(E_k) / sum phi, the table
-// 0.1 mu_tot(m, E_k) (linear in E between grid points) and 1 / sum w.
+// Per source: the channel weights phi_k r(E_k) / sum phi (workgroup r: row r
+// of a joint source), the table 0.1 mu_tot(m, E_k) (linear in E between grid
+// points) and 1 / sum w (workgroup 0).
 struct RtPrepParams {
     const float* spec_e;
-    const float* spec_p;
+    const float* spec_p;          // [rows][n_spec]
     const float* fluence;
     int n_spec, npix;
     const float* mu_mass;         // [n_mat][n_e][3]
@@ -214,9 +216,13 @@ struct RtPrepParams {
 
 __global__ __launch_bounds__(256) void raytrace_prep_kernel(RtPrepParams R) {
     __shared__ double red[2][256];
+    const int row = blockIdx.x;
+    const float* phi = R.spec_p + (size_t)row * R.n_spec;
+    float* coef = R.coef + (size_t)row * R.n_spec;
     double sp = 0.0, sw = 0.0;
-    for (int k = threadIdx.x; k < R.n_spec; k += 256) sp += (double)R.spec_p[k];
-    for (int k = threadIdx.x; k < R.npix; k += 256) sw += (double)R.fluence[k];
+    for (int k = threadIdx.x; k < R.n_spec; k += 256) sp += (double)phi[k];
+    if (row == 0)
+        for (int k = threadIdx.x; k < R.npix; k += 256) sw += (double)R.fluence[k];
     red[0][threadIdx.x] = sp;
     red[1][threadIdx.x] = sw;
     __syncthreads();
@@ -228,7 +234,7 @@ __global__ __launch_bounds__(256) void raytrace_prep_kernel(RtPrepParams R) {
         __syncthreads();
     }
     const double psum = red[0][0], wsum = red[1][0];
-    if (threadIdx.x == 0) R.inv_wsum[0] = wsum > 0.0 ? 1.0 / wsum : 0.0;
+    if (row == 0 && threadIdx.x == 0) R.inv_wsum[0] = wsum > 0.0 ? 1.0 / wsum : 0.0;
     for (int k = threadIdx.x; k < R.n_spec; k += 256) {
         const double E = (double)R.spec_e[k];
         const double g = (E - R.e0) / R.de;
@@ -237,7 +243,8 @@ __global__ __launch_bounds__(256) void raytrace_prep_kernel(RtPrepParams R) {
         const double f = g - (double)j;
         double r = E;
         if (R.response) r = (double)R.response[j] + f * ((double)R.response[j + 1] - (double)R.response[j]);
-        R.coef[k] = psum > 0.0 ? (float)((double)R.spec_p[k] / psum * r) : 0.0f;
+        coef[k] = psum > 0.0 ? (float)((double)phi[k] / psum * r) : 0.0f;
+        if (row != 0) continue;
         for (int m = 0; m < R.n_mat; ++m) {
             const float* a = R.mu_mass + ((size_t)m * R.n_e + j) * 3;
             const double ta = (double)a[0] + (double)a[1] + (double)a[2];

@@ -50,7 +50,7 @@ int main(void) {
     printf("gdrr_tuning %zu\n", sizeof(gdrr_tuning));
     F(gdrr_volume, density) F(gdrr_volume, material) F(gdrr_volume, macro) F(gdrr_volume, macro_margin)
     F(gdrr_physics, mu_mass) F(gdrr_physics, response) F(gdrr_physics, rayleigh_x0_invA) F(gdrr_physics, e_cut_kev)
-    F(gdrr_source, spec_e_kev) F(gdrr_source, fu) F(gdrr_source, fluence)
+    F(gdrr_source, spec_e_kev) F(gdrr_source, fu) F(gdrr_source, fluence) F(gdrr_source, spec_rows)
     F(gdrr_job, geom) F(gdrr_job, n_photons) F(gdrr_job, job_id) F(gdrr_job, tally_offset)
     F(gdrr_tuning, defer) F(gdrr_tuning, scheme)
     return 0;
@@ -103,6 +103,10 @@ def _call(abi, vol, phys, src, geom, n=1000, ws_bytes=1 << 30, tally=0x2000):
     (lambda v, p, s, g: setattr(p, "e_cut_kev", 0.5), "e_cut"),
     (lambda v, p, s, g: setattr(s, "n_spec", 0), "n_spec"),
     (lambda v, p, s, g: setattr(s, "fu", 15), "fluence grid"),
+    (lambda v, p, s, g: setattr(s, "spec_rows", 15), "spec_rows"),
+    (lambda v, p, s, g: setattr(s, "spec_rows", -1), "spec_rows"),
+    (lambda v, p, s, g: (setattr(s, "n_spec", 4096), setattr(s, "spec_rows", 4097), setattr(s, "fu", 4097),
+                         setattr(s, "fv", 1), setattr(g, "nu", 4097), setattr(g, "nv", 1)), "2^24"),
     (lambda v, p, s, g: setattr(g, "aid_mm", 5.0), "between the source and the detector"),
     (lambda v, p, s, g: setattr(g, "du_mm", 0.0), "detector grid"),
 ])
@@ -129,6 +133,14 @@ def test_workspace_query_is_positive(abi):
     n = L.gdrr_mc_project_workspace(C.byref(vol), C.byref(phys), C.byref(src), C.byref(geom))
     assert n > 8 * 4 * 16 * 12 + 64 * 9 * 9 * 9
     assert L.gdrr_majorant_workspace() >= 2048
+    # a joint source (one spectrum per column) needs a CDF per row; a bad row count sizes nothing
+    src.n_spec = 64
+    n1 = L.gdrr_mc_project_workspace(C.byref(vol), C.byref(phys), C.byref(src), C.byref(geom))
+    src.spec_rows = 16
+    n2 = L.gdrr_mc_project_workspace(C.byref(vol), C.byref(phys), C.byref(src), C.byref(geom))
+    assert n2 >= n1 + 15 * 64 * 8
+    src.spec_rows = 7
+    assert L.gdrr_mc_project_workspace(C.byref(vol), C.byref(phys), C.byref(src), C.byref(geom)) == 0
     assert L.gdrr_version().decode().startswith("gdrr")
 
 
