@@ -284,7 +284,12 @@ def build_workload(name, api, W, torch):
 # per interval: position (3 FMA), lattice coordinates (6), floor/convert/clamp
 # (12), fractions (6), cell address (4), trilinear (14), accumulate (2), loop (5)
 SLOTS_RT_INTERVAL = 52
-BYTES_RT_INTERVAL = 8 * 4 + 8        # eight corner densities and materials
+# Compulsory memory traffic per image: the volume's density and material
+# (5 bytes per voxel, read once; an upper bound, as the cone may miss part of
+# the volume) and the float64 image.  Rays of one tile and successive intervals
+# of one ray share voxels, so bytes gathered per interval (40) are mostly cache hits.
+BYTES_RT_VOXEL = 5
+BYTES_RT_PIXEL = 8
 
 
 def rt_intervals(batch, dl_of):
@@ -332,7 +337,9 @@ def raytrace_leg(wl, api, torch, steps, cpu):
     rays = sum(j.geom.nu * j.geom.nv for j in batch.jobs)
     iv = rt_intervals(batch, dl_of)
     alu = iv * SLOTS_RT_INTERVAL / (kms * 1e-3) / 1e12
-    gbs = iv * BYTES_RT_INTERVAL / (kms * 1e-3) / 1e9
+    nbytes = sum(BYTES_RT_VOXEL * int(np.prod(batch.vols[j.volume].shape)) + BYTES_RT_PIXEL * j.geom.nu * j.geom.nv
+                 for j in batch.jobs)
+    gbs = nbytes / (kms * 1e-3) / 1e9
     tr = measured_traffic(TRAFFIC_PATH, wl["config"]["workload"], "raytrace_kernel")
     ra = dict(bound="alu", achieved=round(alu, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Tops/s",
               frac=round(alu / ALU_PEAK_TOPS, 4), traffic=tr)
@@ -340,7 +347,7 @@ def raytrace_leg(wl, api, torch, steps, cpu):
               frac=round(gbs / HBM_PEAK_GBS, 4), traffic=tr)
     out = dict(images=len(batch.jobs), kernel_ms=round(kms, 3), wall_ms=round(float(np.mean(walls)), 3),
                images_per_s=round(len(batch.jobs) / (kms * 1e-3), 1), rays_per_s=round(rays / (kms * 1e-3), 1),
-               intervals=iv, intervals_per_s=round(iv / (kms * 1e-3), 1),
+               intervals=iv, intervals_per_s=round(iv / (kms * 1e-3), 1), compulsory_bytes=nbytes,
                roofline=ra if ra["frac"] >= rh["frac"] else rh, roofline_other=rh if ra["frac"] >= rh["frac"] else ra)
     if cpu:
         import oracle
