@@ -437,14 +437,16 @@ int check_batch(const Batch& B) {
     return GDRR_OK;
 }
 
+// local: 0 single majorants, 1 local majorants with records in global memory, 2 with records in LDS
 template <int MODE>
-const void* mc_func(int scheme, bool local) {
+const void* mc_func(int scheme, int local) {
     if (scheme == 2) return reinterpret_cast<const void*>(&mc_queue_kernel<MODE>);
-    return local ? reinterpret_cast<const void*>(&mc_kernel<MODE, true>)
-                 : reinterpret_cast<const void*>(&mc_kernel<MODE, false>);
+    return local == 2 ? reinterpret_cast<const void*>(&mc_kernel<MODE, 2>)
+         : local == 1 ? reinterpret_cast<const void*>(&mc_kernel<MODE, 1>)
+                      : reinterpret_cast<const void*>(&mc_kernel<MODE, 0>);
 }
 
-const void* mc_func_for(int mode, int scheme, bool local) {
+const void* mc_func_for(int mode, int scheme, int local) {
     return mode == kModeForward ? mc_func<kModeForward>(scheme, local)
          : mode == kModeTrace ? mc_func<kModeTrace>(scheme, local) : mc_func<kModeBackward>(scheme, local);
 }
@@ -496,9 +498,10 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
                                    : lds_bytes(phys->n_mat, phys->n_e, B.n_vols, phys->response != nullptr) +
                                          (size_t)macro_lds_n * sizeof(uint2);
     if (lds > dev.lds_max) return fail(GDRR_ENOTSUP, "tables and queues exceed the LDS of a workgroup");
+    const int local_kind = !local ? 0 : (macro_lds_n > 0 ? 2 : 1);
     int per_cu = tune.blocks_per_cu;
     if (!per_cu) {
-        const void* f = mc_func_for(B.mode, scheme, local);
+        const void* f = mc_func_for(B.mode, scheme, local_kind);
         int nb = 0;
         GDRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, block, lds));
         per_cu = std::max(nb, 1);
@@ -685,7 +688,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     kp.grad = B.grad;
     for (int v = 0; v < kMaxVol; ++v) kp.macro_lds[v] = v < GDRR_MAX_VOLUMES ? macro_lds[v] : -1;
     kp.macro_lds_n = macro_lds_n;
-    const void* mf = mc_func_for(B.mode, scheme, local);
+    const void* mf = mc_func_for(B.mode, scheme, local_kind);
     int timed = -1;
     if (chunks > 0) {
         timed = (int)ls.size();

@@ -356,8 +356,10 @@ __device__ __forceinline__ bool flight(const KParams& P, const Tables& T, const 
 // tau = -ln(u) is spent cube by cube along the line, each cube at its own
 // bound mbar_B = (1 + margin) rho_max(B) max_{m in B} mu_tot(m, E); where tau
 // runs out the collision ladder runs against that cube's bound; leaving the
-// last cube is an escape.  Returns true after a null collision.
-template <int MODE>
+// last cube is an escape.  Returns true after a null collision.  REC_LDS:
+// the cube records are read from their LDS copy lds_rec (a separate
+// instantiation, so that the load is an LDS read, not a generic one).
+template <int MODE, bool REC_LDS>
 __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, const DVolume& V, int vo,
                                              bool interp, Photon& ph, uint32_t ra, uint32_t rb,
                                              const uint2* lds_rec) {
@@ -395,7 +397,7 @@ __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, 
     bool hit = false;
     for (;;) {
         const int ci = (bz * V.mny + by) * V.mnx + bx;
-        const uint2 rec = lds_rec ? lds_rec[ci] : V.macro[ci];
+        const uint2 rec = REC_LDS ? lds_rec[ci] : V.macro[ci];
         float tmax = 0.0f;
         for (uint32_t mask = rec.y; mask; mask &= mask - 1u) {
             const float2 tt = tot[(__builtin_ctz(mask)) * P.n_e];
@@ -507,15 +509,17 @@ __host__ __device__ inline size_t table_floats2(int n_mat, int n_e, int n_vols, 
     return (size_t)n_mat * n_e + (size_t)n_vols * (n_e - 1) + (resp ? (size_t)n_e : 0);
 }
 
-// LOCAL: some volume of the launch tracks with local majorants (a separate
-// instantiation, so that the single-majorant loop keeps its register budget).
-template <int MODE, bool LOCAL>
+// LOCAL: 0 = every volume has one majorant per energy interval; 1 = some
+// volume tracks with local majorants, cube records read from global memory;
+// 2 = the same with every such volume's records staged in LDS.  Separate
+// instantiations, so that the single-majorant loop keeps its register budget.
+template <int MODE, int LOCAL>
 __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
     extern __shared__ float2 lds[];
     const Tables T = stage_tables(P, lds);
     // local majorants small enough to stage: every volume's cube records after the tables
     uint2* lds_macro = reinterpret_cast<uint2*>(lds + table_floats2(P.n_mat, P.n_e, P.n_vols, P.response != nullptr));
-    if (LOCAL)
+    if (LOCAL == 2)
         for (int v = 0; v < P.n_vols; ++v) {
             if (P.macro_lds[v] < 0 || !P.vol[v].macro) continue;
             const int n = P.vol[v].mnx * P.vol[v].mny * P.vol[v].mnz;
@@ -606,10 +610,13 @@ __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
         if (ph.st == kFly) {
             ph.pair += 1u;
             const Block b = philox(ph.pid, ph.jid, ph.pair, 0u, P.k0, P.k1);
-            if (LOCAL && V.macro) {
-                const uint2* lr = P.macro_lds[w_vol] >= 0 ? lds_macro + P.macro_lds[w_vol] : nullptr;
-                if (flight_local<MODE>(P, T, V, vo, interp, ph, b.x, b.y, lr))
-                    flight_local<MODE>(P, T, V, vo, interp, ph, b.z, b.w, lr);
+            if (LOCAL == 2 && V.macro) {
+                const uint2* lr = lds_macro + P.macro_lds[w_vol];
+                if (flight_local<MODE, true>(P, T, V, vo, interp, ph, b.x, b.y, lr))
+                    flight_local<MODE, true>(P, T, V, vo, interp, ph, b.z, b.w, lr);
+            } else if (LOCAL == 1 && V.macro) {
+                if (flight_local<MODE, false>(P, T, V, vo, interp, ph, b.x, b.y, nullptr))
+                    flight_local<MODE, false>(P, T, V, vo, interp, ph, b.z, b.w, nullptr);
             } else if (flight<MODE>(P, T, V, vo, interp, ph, b.x, b.y)) {
                 flight<MODE>(P, T, V, vo, interp, ph, b.z, b.w);
             }
