@@ -61,7 +61,7 @@ __host__ __device__ inline size_t lds_bytes(int n_mat, int n_e, int n_vols, bool
 }
 
 struct Tables {
-    const float2* tot;    // [m][j] (tot_j, tot_j+1 - tot_j)
+    const float2* tot;    // [j][m] (tot_j, tot_j+1 - tot_j): the materials of one interval side by side
     const float2* maj;    // [v][j] (mbar, mean free path per unit of -ln u, mm)
     const float2* resp;   // [j] (r_j, r_j+1 - r_j)
 };
@@ -337,7 +337,7 @@ __device__ __forceinline__ bool flight(const KParams& P, const Tables& T, const 
     int m;
     const float rho = cell_density(V, interp, ph.px, ph.py, ph.pz, m);
     m = m < P.n_mat ? m : P.n_mat - 1;
-    const float2 tt = T.tot[m * P.n_e + ph.ec.j];
+    const float2 tt = T.tot[ph.ec.j * P.n_mat + m];
     const float tot = tt.x + ph.ec.f * tt.y;
     // one uniform on [0, mbar): real below mu = rho tot, then the type ladder
     const float ladder = u24(rb) * ph.ec.mbar;
@@ -392,35 +392,44 @@ __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, 
     float tmz = sz > 0 ? fminf((V.loz + (float)(bz + 1) * V.mez - ph.pz) * rz, bez)
               : (sz < 0 ? (V.loz + (float)bz * V.mez - ph.pz) * rz : INFINITY);
     const float dtx = V.mex * fabsf(rx), dty = V.mey * fabsf(ry), dtz = V.mez * fabsf(rz);
-    const float2* tot = T.tot + ph.ec.j;
+    const float2* tot = T.tot + ph.ec.j * P.n_mat;
+    // the cube index moves by one of these per crossing
+    const int cix = sx, ciy = sy * V.mnx, ciz = sz * V.mnx * V.mny;
+    int ci = (bz * V.mny + by) * V.mnx + bx;
     float mb = 0.0f, t = 0.0f;
     bool hit = false;
+    // (selects instead of fminf/fmaxf below: no NaN can occur, and these need
+    // no canonicalisation of their operands)
     for (;;) {
-        const int ci = (bz * V.mny + by) * V.mnx + bx;
         const uint2 rec = REC_LDS ? lds_rec[ci] : V.macro[ci];
         float tmax = 0.0f;
         for (uint32_t mask = rec.y; mask; mask &= mask - 1u) {
-            const float2 tt = tot[(__builtin_ctz(mask)) * P.n_e];
-            tmax = fmaxf(tmax, tt.x + ph.ec.f * tt.y);
+            const float2 tt = tot[__builtin_ctz(mask)];
+            const float tm = tt.x + ph.ec.f * tt.y;
+            tmax = tm > tmax ? tm : tmax;
         }
         mb = __uint_as_float(rec.x) * tmax;
         const float tnext = fminf(tmx, fminf(tmy, tmz));
-        const float need = 0.1f * mb * fmaxf(tnext - t, 0.0f);   // mbar in 1/cm, lengths in mm
+        const float span = tnext - t;
+        const float need = 0.1f * mb * (span > 0.0f ? span : 0.0f);   // mbar in 1/cm, lengths in mm
         if (mb > 0.0f && tau < need) {
             t += tau * fast_rcp(0.1f * mb);
             hit = true;
             break;
         }
         tau -= need;
-        t = fmaxf(t, tnext);
+        t = tnext > t ? tnext : t;
         const bool ax = tmx <= tmy && tmx <= tmz, ay = !ax && tmy <= tmz, az = !ax && !ay;
         bx += ax ? sx : 0;
         by += ay ? sy : 0;
         bz += az ? sz : 0;
-        tmx = ax ? fminf(tmx + dtx, bex) : tmx;
-        tmy = ay ? fminf(tmy + dty, bey) : tmy;
-        tmz = az ? fminf(tmz + dtz, bez) : tmz;
-        if (bx < 0 || bx >= V.mnx || by < 0 || by >= V.mny || bz < 0 || bz >= V.mnz) break;
+        ci += ax ? cix : (ay ? ciy : ciz);
+        const float nx = tmx + dtx, ny = tmy + dty, nz = tmz + dtz;
+        tmx = ax ? (nx < bex ? nx : bex) : tmx;
+        tmy = ay ? (ny < bey ? ny : bey) : tmy;
+        tmz = az ? (nz < bez ? nz : bez) : tmz;
+        if ((unsigned)bx >= (unsigned)V.mnx || (unsigned)by >= (unsigned)V.mny || (unsigned)bz >= (unsigned)V.mnz)
+            break;
     }
     ph.px += t * ph.dx;
     ph.py += t * ph.dy;
@@ -434,7 +443,7 @@ __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, 
     int m;
     const float rho = cell_density(V, interp, ph.px, ph.py, ph.pz, m);
     m = m < P.n_mat ? m : P.n_mat - 1;
-    const float2 tt = T.tot[m * P.n_e + ph.ec.j];
+    const float2 tt = T.tot[ph.ec.j * P.n_mat + m];
     const float tot_m = tt.x + ph.ec.f * tt.y;
     const float ladder = u24(rb) * mb;
     const bool real = ladder < rho * tot_m;
@@ -487,8 +496,8 @@ __device__ __forceinline__ Tables stage_tables(const KParams& P, float2* lds) {
     float2* s_maj = s_tot + P.n_mat * P.n_e;
     float2* s_resp = s_maj + P.n_vols * (P.n_e - 1);
     for (int i = threadIdx.x; i < P.n_mat * P.n_e; i += blockDim.x) {
-        const int j = i % P.n_e;
-        const float* a = P.mu_mass + (size_t)i * 3;
+        const int j = i / P.n_mat, m = i - j * P.n_mat;
+        const float* a = P.mu_mass + ((size_t)m * P.n_e + j) * 3;
         const float* b = j + 1 < P.n_e ? a + 3 : a;
         const float t0 = a[0] + a[1] + a[2], t1 = b[0] + b[1] + b[2];
         s_tot[i] = make_float2(t0, t1 - t0);
