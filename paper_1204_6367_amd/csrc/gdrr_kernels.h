@@ -486,7 +486,7 @@ __device__ __forceinline__ void collide(const KParams& P, const Tables& T, const
         ph.st = kDead;
         return;
     }
-    ph.trem = box_exit(V, ph.px, ph.py, ph.pz, ph.dx, ph.dy, ph.dz);
+    if (!V.macro) ph.trem = box_exit(V, ph.px, ph.py, ph.pz, ph.dx, ph.dy, ph.dz);   // local majorants walk cubes instead
     ph.st = kFly;
 }
 
