@@ -197,52 +197,30 @@ __device__ __forceinline__ bool box_entry(const DVolume& V, float sx, float sy, 
     return t0 < t1;
 }
 
-// Compton scattering, free-electron Klein-Nishina: tau = E'/E drawn from the
-// mixture of densities ~1/tau (weight ln(1+2k)) and ~tau (weight (1-tau0^2)/2)
-// on [tau0, 1], kept with probability 1 - tau sin^2/(1+tau^2).  One Philox
-// block (photon, job, step, 1 + try) per try; the accepted try's fourth word
-// is the azimuth (in revolutions).  Returns cos(theta); E *= tau.
-__device__ __forceinline__ float compton(uint32_t pid, uint32_t job, uint32_t step, uint32_t k0, uint32_t k1,
-                                         float& E, float& az) {
+// Scattering angle of a Compton or a Rayleigh event, both by rejection with
+// one Philox block (photon, job, step, 1 + try) per try; the try's fourth word
+// is the azimuth (in revolutions).  Returns cos(theta) (1 if every try is
+// rejected).  The two samplers share the loop and its Philox block, so that a
+// wavefront holding both kinds of event generates each try's block once.
+//
+// Compton, free-electron Klein-Nishina: tau = E'/E drawn from the mixture of
+// densities ~1/tau (weight ln(1+2k)) and ~tau (weight (1-tau0^2)/2) on
+// [tau0, 1], kept with probability 1 - tau sin^2/(1+tau^2); E *= tau.
+//
+// Rayleigh with F(x) = Z exp(-x/x0), x = sin(theta/2)/lambda in [0, 1/lambda]:
+// x from Gamma(2, x0/2) truncated at 1/lambda when 1/lambda >= x0, else from
+// the density ~x on [0, 1/lambda] kept with probability exp(-2x/x0); then kept
+// with probability (1 + cos^2)/2.
+__device__ __forceinline__ float scatter_angle(bool is_rayleigh, uint32_t pid, uint32_t job, uint32_t step,
+                                               uint32_t k0, uint32_t k1, float& E, float x0, float& az) {
+    // Compton constants
     const float k = E * (1.0f / kMeC2);
     const float tau0 = fast_rcp(1.0f + 2.0f * k);
     const float a1 = fast_log(1.0f + 2.0f * k);
     const float ik = fast_rcp(k);
     const float omt02 = 1.0f - tau0 * tau0;
     const float a2 = 0.5f * omt02;
-    for (int t = 0; t < kMaxTries; ++t) {
-        const Block b = philox(pid, job, step, 1u + (uint32_t)t, k0, k1);
-        const float b0 = u24(b.x), b1 = u24(b.y), b2 = u24(b.z);
-        float tau, omt;   // tau and 1 - tau, the latter without cancellation
-        if (b0 * (a1 + a2) < a1) {
-            const float e = -a1 * b1;               // in [-ln 3, 0]; |e| <= 0.47 for E <= 150 keV
-            omt = one_minus_exp(e);
-            tau = 1.0f - omt;
-        } else {
-            const float t2 = tau0 * tau0 + omt02 * b1;
-            tau = sqrtf(t2);
-            omt = omt02 * (1.0f - b1) * fast_rcp(1.0f + tau);
-        }
-        const float itau = fast_rcp(tau);
-        const float omc = omt * ik * itau;          // 1 - cos(theta)
-        const float ct = 1.0f - omc;
-        const float sin2 = omc * (2.0f - omc);
-        const float g = 1.0f - tau * sin2 * fast_rcp(1.0f + tau * tau);
-        az = u24(b.w);
-        if (b2 <= g) {
-            E *= tau;
-            return ct;
-        }
-    }
-    return 1.0f;
-}
-
-// Rayleigh scattering with F(x) = Z exp(-x/x0), x = sin(theta/2)/lambda in
-// [0, 1/lambda]: x from Gamma(2, x0/2) truncated at 1/lambda when 1/lambda >=
-// x0, else from the density ~x on [0, 1/lambda] kept with probability
-// exp(-2x/x0); then kept with probability (1 + cos^2)/2.
-__device__ __forceinline__ float rayleigh(uint32_t pid, uint32_t job, uint32_t step, uint32_t k0, uint32_t k1,
-                                          float E, float x0, float& az) {
+    // Rayleigh constants
     const float xmax = E * (1.0f / kHc);
     const float ixmax = kHc * fast_rcp(E);
     const float m2ix0 = -2.0f * fast_rcp(x0);
@@ -250,17 +228,40 @@ __device__ __forceinline__ float rayleigh(uint32_t pid, uint32_t job, uint32_t s
         const Block b = philox(pid, job, step, 1u + (uint32_t)t, k0, k1);
         const float b0 = u24(b.x), b1 = u24(b.y), b2 = u24(b.z);
         az = u24(b.w);
-        float xx;
-        if (xmax >= x0) {
-            xx = -0.5f * x0 * (fast_log(b0) + fast_log(b1));
-            if (xx > xmax) continue;
+        if (is_rayleigh) {
+            float xx;
+            bool ok;
+            if (xmax >= x0) {
+                xx = -0.5f * x0 * (fast_log(b0) + fast_log(b1));
+                ok = xx <= xmax;
+            } else {
+                xx = xmax * sqrtf(b0);
+                ok = b1 <= fast_exp(m2ix0 * xx);
+            }
+            const float r = xx * ixmax;
+            const float ct = 1.0f - 2.0f * r * r;
+            if (ok && b2 <= 0.5f * (1.0f + ct * ct)) return ct;
         } else {
-            xx = xmax * sqrtf(b0);
-            if (b1 > fast_exp(m2ix0 * xx)) continue;
+            float tau, omt;   // tau and 1 - tau, the latter without cancellation
+            if (b0 * (a1 + a2) < a1) {
+                const float e = -a1 * b1;               // in [-ln 3, 0]; |e| <= 0.47 for E <= 150 keV
+                omt = one_minus_exp(e);
+                tau = 1.0f - omt;
+            } else {
+                const float t2 = tau0 * tau0 + omt02 * b1;
+                tau = sqrtf(t2);
+                omt = omt02 * (1.0f - b1) * fast_rcp(1.0f + tau);
+            }
+            const float itau = fast_rcp(tau);
+            const float omc = omt * ik * itau;          // 1 - cos(theta)
+            const float ct = 1.0f - omc;
+            const float sin2 = omc * (2.0f - omc);
+            const float g = 1.0f - tau * sin2 * fast_rcp(1.0f + tau * tau);
+            if (b2 <= g) {
+                E *= tau;
+                return ct;
+            }
         }
-        const float r = xx * ixmax;
-        const float ct = 1.0f - 2.0f * r * r;
-        if (b2 <= 0.5f * (1.0f + ct * ct)) return ct;
     }
     return 1.0f;
 }

@@ -467,18 +467,19 @@ __device__ __forceinline__ void collide(const KParams& P, const Tables& T, const
     const float R = a[0] + ph.ec.f * (a[3] - a[0]);
     const float C = a[1] + ph.ec.f * (a[4] - a[1]);
     const float sel = ph.sel;
-    float ct, az = 0.0f;
-    if (sel < R) {
-        ct = rayleigh(ph.pid, ph.jid, ph.step, P.k0, P.k1, ph.E, P.x0, az);
-        ph.nsc += 1u << 16;
-    } else if (sel < R + C) {
-        ct = compton(ph.pid, ph.jid, ph.step, P.k0, P.k1, ph.E, az);
-        ph.nsc += 1u;
-        ph.ec = energy_cache(P, T, vo, ph.E);
-    } else {
+    if (!(sel < R + C)) {
         if (MODE == kModeTrace) trace_out<MODE>(P, ph, kAbsorbed, -1);
         ph.st = kDead;
         return;
+    }
+    const bool is_rayleigh = sel < R;
+    float az = 0.0f;
+    const float ct = scatter_angle(is_rayleigh, ph.pid, ph.jid, ph.step, P.k0, P.k1, ph.E, P.x0, az);
+    if (is_rayleigh) {
+        ph.nsc += 1u << 16;
+    } else {
+        ph.nsc += 1u;
+        ph.ec = energy_cache(P, T, vo, ph.E);
     }
     rotate(ph.dx, ph.dy, ph.dz, ct, az);
     if (ph.E < P.e_cut) {
