@@ -142,7 +142,7 @@ def majorant_desc(vols):
     return f"local, cubes of {[v.macro for v in vols]} voxels (~{CUBE_MM:g} mm)"
 
 
-def autotune_for(batch):
+def autotune_for(batch, mode="forward", volume=0):
     """Launch shape from the autotuner's cache for this workload class, or (not
     cached) from a fresh search on 2 % of the photons; untimed setup either way."""
     from paper_1204_6367_amd import autotune
@@ -150,8 +150,8 @@ def autotune_for(batch):
         return None
     t = time.time()
     best = autotune.autotune(batch, fraction=0.02, min_photons=200_000, cache=TUNE_CACHE,
-                             force=TUNE_MODE == "search")
-    log(f"autotune {best} in {time.time() - t:.1f}s")
+                             force=TUNE_MODE == "search", mode=mode, volume=volume)
+    log(f"autotune ({mode}) {best} in {time.time() - t:.1f}s")
     return best
 
 
@@ -243,6 +243,7 @@ def build_workload(name, api, W, torch):
         adjh = sum(jobs[k].n_photons for k in adj_idx)
         state = {}
         tune = autotune_for(batch)
+        adj_tune = autotune_for(adj_batch, mode="backward", volume=adj_vol)
 
         def step():
             maj = torch.stack([api.majorant(v, dphys, True, margins[k]) for k, v in enumerate(vols)])
@@ -252,7 +253,7 @@ def build_workload(name, api, W, torch):
             s_now = torch.stack([views[k][2] for k in adj_idx])
             adj = torch.zeros(len(adj_idx), 2, geom.nv, geom.nu, dtype=torch.float64, device="cuda")
             adj[:, 1] = s_now - s_target                       # d(0.5||S - S*||^2)/dS
-            adj_batch.backward(adj, maj, volume=adj_vol, seed=1, grad=grad, tune=tune)
+            adj_batch.backward(adj, maj, volume=adj_vol, seed=1, grad=grad, tune=adj_tune)
             ms_b = api.last_kernel_ms()
             state["loss"] = 0.5 * float(((s_now - s_target) ** 2).sum())
             return [ms_f, ms_b]
@@ -265,7 +266,7 @@ def build_workload(name, api, W, torch):
                             jobs[k].job_id, vols[v].macro, vols[v].macro_margin))
         adjoint = dict(problem=W.Problem(phantoms[adj_vol][0], physw, srcw, jobs[adj_idx[0]].geom, 1),
                        job_id=jobs[adj_idx[0]].job_id, margin=0.1, macro=vols[adj_vol].macro)
-        cfg = dict(workload=name, angles=len(jobs), adjoint_angles=len(adj_idx), tuning=tune,
+        cfg = dict(workload=name, angles=len(jobs), adjoint_angles=len(adj_idx), tuning=tune, adjoint_tuning=adj_tune,
                    majorant=majorant_desc(vols),
                    detector="256x192 @1.552mm", spectrum=SPECTRUM_DESC[SOURCE],
                    phantoms=[f"{'x'.join(map(str, ph.shape[::-1]))} @{ph.spacing_mm[0]}mm" for ph, _ in phantoms],

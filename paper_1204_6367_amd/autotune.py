@@ -12,6 +12,8 @@ import json
 import os
 from typing import Dict, Iterable, List, Optional
 
+import torch
+
 from . import api
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
@@ -22,10 +24,11 @@ CANDIDATES: List[Dict[str, int]] = [
 ]
 
 
-def workload_key(batch: "api.Batch") -> str:
+def workload_key(batch: "api.Batch", mode: str = "forward") -> str:
     vols = ";".join("x".join(map(str, v.shape)) + (f"/m{v.macro}" if v.macro else "") for v in batch.vols)
     dets = sorted({(j.geom.nu, j.geom.nv) for j in batch.jobs})
-    return f"vols={vols}|det={dets}|jobs={len(batch.jobs)}"
+    key = f"vols={vols}|det={dets}|jobs={len(batch.jobs)}"
+    return key if mode == "forward" else f"{key}|{mode}"
 
 
 def _reduced(batch: "api.Batch", fraction: float, min_photons: int) -> "api.Batch":
@@ -36,9 +39,14 @@ def _reduced(batch: "api.Batch", fraction: float, min_photons: int) -> "api.Batc
 
 def autotune(batch: "api.Batch", candidates: Optional[Iterable[Dict[str, int]]] = None,
              fraction: float = 0.05, min_photons: int = 100_000, repeats: int = 2,
-             cache: Optional[str] = DEFAULT_CACHE, force: bool = False, interp: bool = True) -> Dict[str, int]:
-    """Returns the fastest tuning dict for `batch` (cached by workload class)."""
-    key = workload_key(batch)
+             cache: Optional[str] = DEFAULT_CACHE, force: bool = False, interp: bool = True,
+             mode: str = "forward", volume: int = 0) -> Dict[str, int]:
+    """Returns the fastest tuning dict for `batch` (cached by workload class).
+    mode "backward" times the adjoint of `volume` (adjoint weights 1 on the
+    scatter images, so that every scored scatter history is replayed)."""
+    if mode not in ("forward", "backward"):
+        raise ValueError("mode must be 'forward' or 'backward'")
+    key = workload_key(batch, mode)
     table = {}
     if cache and os.path.exists(cache):
         try:
@@ -49,12 +57,17 @@ def autotune(batch: "api.Batch", candidates: Optional[Iterable[Dict[str, int]]] 
         return dict(table[key]["tuning"])
     small = _reduced(batch, fraction, min_photons)
     maj = small.majorants(interp)
+    adj = None
+    if mode == "backward":
+        g = small.jobs[0].geom
+        adj = torch.zeros(len(small.jobs), 2, g.nv, g.nu, dtype=torch.float64, device=maj.device)
+        adj[:, 1] = 1.0
     api.enable_timing(True)
     results = []
     for cand in (candidates or CANDIDATES):
         try:
-            small.project(seed=1, interp=interp, sumsq=False, majorants=maj, tune=cand)   # warm-up / graph build
-            ms = min(_timed(small, maj, cand, interp) for _ in range(repeats))
+            _timed(small, maj, cand, interp, adj, volume)                 # warm-up / graph build
+            ms = min(_timed(small, maj, cand, interp, adj, volume) for _ in range(repeats))
         except api._abi.GdrrError:
             continue
         results.append((ms, cand))
@@ -72,6 +85,9 @@ def autotune(batch: "api.Batch", candidates: Optional[Iterable[Dict[str, int]]] 
     return dict(best)
 
 
-def _timed(batch, maj, cand, interp) -> float:
-    batch.project(seed=1, interp=interp, sumsq=False, majorants=maj, tune=cand)
+def _timed(batch, maj, cand, interp, adj=None, volume=0) -> float:
+    if adj is None:
+        batch.project(seed=1, interp=interp, sumsq=False, majorants=maj, tune=cand)
+    else:
+        batch.backward(adj, maj, volume=volume, seed=1, interp=interp, tune=cand)
     return api.last_kernel_ms()

@@ -441,14 +441,27 @@ int check_batch(const Batch& B) {
 template <int MODE>
 const void* mc_func(int scheme, int local) {
     if (scheme == 2) return reinterpret_cast<const void*>(&mc_queue_kernel<MODE>);
-    return local == 2 ? reinterpret_cast<const void*>(&mc_kernel<MODE, 2>)
-         : local == 1 ? reinterpret_cast<const void*>(&mc_kernel<MODE, 1>)
-                      : reinterpret_cast<const void*>(&mc_kernel<MODE, 0>);
+    if constexpr (MODE == kModeBackward)
+        return local == 2 ? reinterpret_cast<const void*>(&mc_adjoint_kernel<2>)
+             : local == 1 ? reinterpret_cast<const void*>(&mc_adjoint_kernel<1>)
+                          : reinterpret_cast<const void*>(&mc_adjoint_kernel<0>);
+    else
+        return local == 2 ? reinterpret_cast<const void*>(&mc_kernel<MODE, 2>)
+             : local == 1 ? reinterpret_cast<const void*>(&mc_kernel<MODE, 1>)
+                          : reinterpret_cast<const void*>(&mc_kernel<MODE, 0>);
 }
 
 const void* mc_func_for(int mode, int scheme, int local) {
     return mode == kModeForward ? mc_func<kModeForward>(scheme, local)
          : mode == kModeTrace ? mc_func<kModeTrace>(scheme, local) : mc_func<kModeBackward>(scheme, local);
+}
+
+// Does some job of the launch trace photons in volume v?
+bool batch_uses(const Batch& B, int v) {
+    for (int k = 0; k < B.n_jobs; ++k)
+        if (B.jobs[k].volume == v && B.jobs[k].n_photons > 0 && (B.only_volume < 0 || v == B.only_volume))
+            return true;
+    return false;
 }
 
 int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
@@ -476,19 +489,20 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     bool local = false;
     for (int v = 0; v < B.n_vols; ++v) local |= B.vols[v].macro > 0;
     const int block = tune.block ? tune.block : (scheme == 2 ? 512 : 256);
-    // local majorants go to LDS (after the tables) while all volumes' records fit in kMacroLdsMax
+    // local majorants go to LDS (after the tables) while the records of all volumes that the
+    // launch traces fit in kMacroLdsMax
     int macro_lds[GDRR_MAX_VOLUMES];
     int macro_lds_n = 0;
     for (int v = 0; v < GDRR_MAX_VOLUMES; ++v) macro_lds[v] = -1;
     if (local && scheme != 2) {
         size_t n = 0;
         for (int v = 0; v < B.n_vols; ++v)
-            if (B.vols[v].macro > 0)
+            if (B.vols[v].macro > 0 && batch_uses(B, v))
                 n += (size_t)cubes(B.vols[v].nx, B.vols[v].macro) * cubes(B.vols[v].ny, B.vols[v].macro) *
                      cubes(B.vols[v].nz, B.vols[v].macro);
         if (n * sizeof(uint2) <= kMacroLdsMax)
             for (int v = 0; v < B.n_vols; ++v)
-                if (B.vols[v].macro > 0) {
+                if (B.vols[v].macro > 0 && batch_uses(B, v)) {
                     macro_lds[v] = macro_lds_n;
                     macro_lds_n += cubes(B.vols[v].nx, B.vols[v].macro) * cubes(B.vols[v].ny, B.vols[v].macro) *
                                    cubes(B.vols[v].nz, B.vols[v].macro);
@@ -585,10 +599,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     }
     // ---- cell records of every volume that has photons ----
     for (int v = 0; v < B.n_vols; ++v) {
-        bool used = false;
-        for (int k = 0; k < B.n_jobs; ++k)
-            used |= B.jobs[k].volume == v && B.jobs[k].n_photons > 0 && (B.only_volume < 0 || v == B.only_volume);
-        if (!used) continue;
+        if (!batch_uses(B, v)) continue;
         const gdrr_volume& V = B.vols[v];
         CellParams cp{V.density, V.material, V.nx, V.ny, V.nz, L.cells[v]};
         const size_t nc = cell_count(V);

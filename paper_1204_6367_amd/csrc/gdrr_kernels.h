@@ -524,7 +524,7 @@ __host__ __device__ inline size_t table_floats2(int n_mat, int n_e, int n_vols, 
 // 2 = the same with every such volume's records staged in LDS.  Separate
 // instantiations, so that the single-majorant loop keeps its register budget.
 template <int MODE, int LOCAL>
-__global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
+__device__ __forceinline__ void mc_body(const KParams& P) {
     extern __shared__ float2 lds[];
     const Tables T = stage_tables(P, lds);
     // local majorants small enough to stage: every volume's cube records after the tables
@@ -639,6 +639,18 @@ __global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
             if (ph.st == kColl) collide<MODE>(P, T, V, vo, ph);
         }
     }
+}
+
+template <int MODE, int LOCAL>
+__global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
+    mc_body<MODE, LOCAL>(P);
+}
+
+// The adjoint: at most 96 VGPRs (5 wavefronts per SIMD), where it would
+// otherwise take 97 and drop to 4.
+template <int LOCAL>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void mc_adjoint_kernel(KParams P) {
+    mc_body<kModeBackward, LOCAL>(P);
 }
 
 // ---------------------------------------------------------------------------
