@@ -1016,8 +1016,9 @@ int run_denoise(const double* shat, long long stride, int n_img, int nv, int nu,
         d.omega = omega;
         d.inv_beta = 1.0f / beta;
         d.s_floor = s_floor;
-        ls.push_back(make_launch((const void*)&denoise_kernel, dim3((unsigned)(n_img * tiles_u * tiles_v)),
-                                 dim3(kDnBlock), 0, d));
+        const bool inside = nv >= kDnWaves * kDnRows && nu >= kDnCols;
+        ls.push_back(make_launch(inside ? (const void*)&denoise_inside_kernel : (const void*)&denoise_kernel,
+                                 dim3((unsigned)(n_img * tiles_u * tiles_v)), dim3(kDnBlock), 0, d));
     }
     TimeEvents* ev = nullptr;
     {

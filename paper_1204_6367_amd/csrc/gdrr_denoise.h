@@ -36,6 +36,78 @@ struct DnParams {
     float omega, inv_beta, s_floor;
 };
 
+// Neighbours in the row from the lanes on either side (DPP whole-wavefront
+// shifts: lane i reads lane i - 1, resp. i + 1); lane 0, resp. 63, keeps its
+// own value, the missing neighbour at the region's edge.
+__device__ __forceinline__ float dn_left(float x) {
+    const int v = __float_as_int(x);
+    return __int_as_float(__builtin_amdgcn_update_dpp(v, v, 0x138, 0xf, 0xf, false));   // wave_shr:1
+}
+__device__ __forceinline__ float dn_right(float x) {
+    const int v = __float_as_int(x);
+    return __int_as_float(__builtin_amdgcn_update_dpp(v, v, 0x130, 0xf, 0xf, false));   // wave_shl:1
+}
+
+// Images of at least kDnWaves * kDnRows rows and kDnCols columns: the region
+// of each tile is shifted to lie inside the image (toward the interior at
+// the borders).  Where a region edge then falls on the image's edge the
+// missing neighbour is the pixel itself, as the definition wants there; every
+// other region edge is at least kDnHalo pixels from the tile's own pixels.
+// No pixel of the region needs a bounds test.
+__global__ __launch_bounds__(kDnBlock) void denoise_inside_kernel(DnParams D) {
+    __shared__ float edge[2][kDnWaves][64];
+    const int per_img = D.tiles_u * D.tiles_v;
+    const int img = blockIdx.x / per_img, t = blockIdx.x % per_img;
+    const int ty = (t / D.tiles_u) * kDnTileV, tx = (t % D.tiles_u) * kDnTileU;   // the tile's first row, column
+    const int y0 = min(max(ty - kDnHalo, 0), D.nv - kDnWaves * kDnRows);
+    const int x0 = min(max(tx - kDnHalo, 0), D.nu - kDnCols);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int band = wave * kDnRows;
+    const size_t npix = (size_t)D.nv * D.nu;
+    const double* H = D.shat + (size_t)img * D.shat_stride + (size_t)(y0 + band) * D.nu + (x0 + lane);
+    const float* Sin = D.s_in ? D.s_in + (size_t)img * npix + (size_t)(y0 + band) * D.nu + (x0 + lane) : nullptr;
+    float s[kDnRows], h[kDnRows];
+#pragma unroll
+    for (int k = 0; k < kDnRows; ++k) {
+        h[k] = (float)H[(size_t)k * D.nu];
+        s[k] = Sin ? Sin[(size_t)k * D.nu] : fmaxf(h[k], D.s_floor);
+    }
+    const float w1 = 1.0f - D.omega, qw = 0.25f * D.omega;
+    for (int it = 0; it < D.iters; ++it) {
+        edge[0][wave][lane] = s[0];
+        edge[1][wave][lane] = s[kDnRows - 1];
+        __syncthreads();
+        const float above = wave > 0 ? edge[1][wave - 1][lane] : s[0];
+        const float below = wave < kDnWaves - 1 ? edge[0][wave + 1][lane] : s[kDnRows - 1];
+        __syncthreads();
+        float prev = above;                              // old value of the row above
+#pragma unroll
+        for (int k = 0; k < kDnRows; ++k) {
+            const float sk = s[k];
+            const float dn = k + 1 < kDnRows ? s[k + 1] : below;
+            const float hk = h[k];
+            // 1 - h/s with the hardware reciprocal (about 1 ulp)
+            const float data = hk == 0.0f ? 1.0f : 1.0f - hk * __builtin_amdgcn_rcpf(sk);
+            const float v = w1 * sk + qw * ((prev + dn + dn_left(sk) + dn_right(sk)) - data * D.inv_beta);
+            prev = sk;
+            s[k] = fmaxf(v, D.s_floor);
+        }
+    }
+    // the tile's own pixels
+    const int col = x0 + lane;
+    if (col < tx || col >= tx + kDnTileU) return;
+#pragma unroll
+    for (int k = 0; k < kDnRows; ++k) {
+        const int row = y0 + band + k;
+        if (row < ty || row >= ty + kDnTileV || row >= D.nv) continue;
+        const size_t p = (size_t)img * npix + (size_t)row * D.nu + col;
+        if (D.out) D.out[p] = (double)s[k];
+        else D.s_out[p] = s[k];
+    }
+}
+
+// Any image size: the region may stick out of the image; rows and columns
+// outside it are masked.
 __global__ __launch_bounds__(kDnBlock) void denoise_kernel(DnParams D) {
     __shared__ float edge[2][kDnWaves][64];              // first / last row of each band
     const int per_img = D.tiles_u * D.tiles_v;

@@ -1,8 +1,10 @@
 """GPU parity of the scatter denoising (Sec. 2.5, Eq. 5) and the noise
 assembly (Sec. 2.6) against the CPU oracle on the same images: iteration
 counts across the LDS passes (0, 1, one pass, one pass + 1, many), ragged
-image sizes over several tiles, zeros in the data, strided input (plane 2 of
-a batch's tallies), and the full detector of the benchmark."""
+image sizes over several tiles, both kernels (images smaller than a region,
+and images whose regions are shifted inside them), zeros in the data,
+strided input (plane 2 of a batch's tallies), and the full detector of the
+benchmark."""
 import sys
 
 import numpy as np
@@ -49,6 +51,24 @@ def test_denoise_matches_oracle(gpu, iters):
     shat = poisson_images(iters + 1, 3, 70, 150)
     shat[1, 10:14, 20:30] = 0.0
     log("denoise iters", iters)
+    g = gpu.denoise(torch.tensor(shat, device="cuda"), beta=0.05, iters=iters, s_floor=1e-3).cpu().numpy()
+    o = oracle.denoise(shat, 0.05, iters, s_floor=1e-3)
+    err = np.abs(g - o).max()
+    log("max abs err", err, "tol", tol_of(o, iters))
+    assert err <= tol_of(o, iters)
+
+
+@pytest.mark.parametrize("nv,nu,iters", [(80, 64, 9), (97, 130, 0), (97, 130, 1), (97, 130, 40), (150, 70, 8),
+                                         (81, 200, 17)])
+def test_denoise_regions_inside_the_image(gpu, nv, nu, iters):
+    """Images of at least 80 rows and 64 columns take the kernel whose regions
+    are shifted inside the image; ragged sizes, the minimum size, regions
+    clamped at both ends and iteration counts around the pass length."""
+    import torch
+    import oracle
+    shat = poisson_images(nv + nu + iters, 2, nv, nu)
+    shat[0, :3, :5] = 0.0                                  # zeros at a corner
+    log("denoise inside", nv, nu, iters)
     g = gpu.denoise(torch.tensor(shat, device="cuda"), beta=0.05, iters=iters, s_floor=1e-3).cpu().numpy()
     o = oracle.denoise(shat, 0.05, iters, s_floor=1e-3)
     err = np.abs(g - o).max()
