@@ -112,25 +112,34 @@ __global__ __launch_bounds__(kRtBlock) void raytrace_kernel(RtParams P) {
         const float lox = V.lox, loy = V.loy, loz = V.loz, idx = V.idx, idy = V.idy, idz = V.idz;
         const int n_mat = P.n_mat;
         const bool interp = P.interp != 0;
-        // one interval of slack on both sides; empty parts are skipped
-        const int j0 = (int)floorf(t0 / dl) - 1, j1 = (int)ceilf(t1 / dl) + 1;
         float acc = 0.0f;
         int cur = -1;
-        for (int j = j0; j < j1; ++j) {
+        // Interval j: its length inside the box h (<= 0 outside the ray's part
+        // in the box), the lattice cell (ix, iy, iz) of its midpoint (clamped)
+        // and the fractions there.
+        auto interval = [&](int j, float& h, float& fx, float& fy, float& fz, int& ix, int& iy, int& iz) {
             const float a = fmaxf((float)j * dl, t0), e = fminf((float)(j + 1) * dl, t1);
-            if (!(e > a)) continue;
-            const float h = e - a, t = 0.5f * (a + e);
+            h = e - a;
+            const float t = 0.5f * (a + e);
             const float px = J.Sx + t * dx, py = J.Sy + t * dy, pz = J.Sz + t * dz;
             const float gx = (px - lox) * idx - 0.5f, gy = (py - loy) * idy - 0.5f,
                         gz = (pz - loz) * idz - 0.5f;
             const float fx0 = floorf(gx), fy0 = floorf(gy), fz0 = floorf(gz);
-            const int ix = min(max((int)fx0, -1), nx - 1);
-            const int iy = min(max((int)fy0, -1), ny - 1);
-            const int iz = min(max((int)fz0, -1), nz - 1);
-            const float fx = fminf(fmaxf(gx - fx0, 0.0f), 1.0f);
-            const float fy = fminf(fmaxf(gy - fy0, 0.0f), 1.0f);
-            const float fz = fminf(fmaxf(gz - fz0, 0.0f), 1.0f);
-            if (!interp) {
+            ix = min(max((int)fx0, -1), nx - 1);
+            iy = min(max((int)fy0, -1), ny - 1);
+            iz = min(max((int)fz0, -1), nz - 1);
+            fx = fminf(fmaxf(gx - fx0, 0.0f), 1.0f);
+            fy = fminf(fmaxf(gy - fy0, 0.0f), 1.0f);
+            fz = fminf(fmaxf(gz - fz0, 0.0f), 1.0f);
+        };
+        // one interval of slack on both sides (rounding of t / dl); empty ones have h <= 0
+        const int jb = (int)floorf(t0 / dl) - 1, je = (int)ceilf(t1 / dl) + 1;
+        if (!interp) {
+            for (int j = jb; j < je; ++j) {
+                float h, fx, fy, fz;
+                int ix, iy, iz;
+                interval(j, h, fx, fy, fz, ix, iy, iz);
+                if (!(h > 0.0f)) continue;
                 // containing voxel: the cell corner nearest to the point
                 const int vx = min(max(ix + (fx >= 0.5f ? 1 : 0), 0), nx - 1);
                 const int vy = min(max(iy + (fy >= 0.5f ? 1 : 0), 0), ny - 1);
@@ -143,35 +152,53 @@ __global__ __launch_bounds__(kRtBlock) void raytrace_kernel(RtParams P) {
                     acc = 0.0f;
                 }
                 acc += h * dens[v];
-                continue;
             }
-            const CellRec* r = cells + ((iz + 1) * cxy + (iy + 1) * cx + (ix + 1));
-            const float4 d0 = *reinterpret_cast<const float4*>(&r->d[0]);
-            const float4 d1 = *reinterpret_cast<const float4*>(&r->d[4]);
-            const uint2 mm = *reinterpret_cast<const uint2*>(&r->m[0]);
-            const uint32_t m0 = mm.x & 0xFFu;
-            if (mm.x == mm.y && mm.x == m0 * 0x01010101u) {
-                const float a00 = d0.x + fx * (d0.y - d0.x), a01 = d0.z + fx * (d0.w - d0.z);
-                const float a10 = d1.x + fx * (d1.y - d1.x), a11 = d1.z + fx * (d1.w - d1.z);
-                const float b0 = a00 + fy * (a01 - a00), b1 = a10 + fy * (a11 - a10);
-                const int m = min((int)m0, n_mat - 1);
-                if (m != cur) {
-                    if (cur >= 0) Lm[cur * kRtBlock] += acc;
-                    cur = m;
-                    acc = 0.0f;
-                }
-                acc += h * (b0 + fz * (b1 - b0));
-            } else {
-                const float gx0 = 1.0f - fx, gy0 = 1.0f - fy, gz0 = 1.0f - fz;
-                const float wz0 = h * gz0, wz1 = h * fz;
-                const float cd[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+        } else {
+            // software-pipelined: the next interval's cell record is read while
+            // this one is summed
+            float h, fx, fy, fz;
+            int ix, iy, iz;
+            interval(jb, h, fx, fy, fz, ix, iy, iz);
+            const int cell = (iz + 1) * cxy + (iy + 1) * cx + (ix + 1);
+            float4 d0 = *reinterpret_cast<const float4*>(&cells[cell].d[0]);
+            float4 d1 = *reinterpret_cast<const float4*>(&cells[cell].d[4]);
+            uint2 mm = *reinterpret_cast<const uint2*>(&cells[cell].m[0]);
+            for (int j = jb; j < je; ++j) {
+                float hn, fxn, fyn, fzn;
+                int jx, jy, jz;
+                interval(j + 1, hn, fxn, fyn, fzn, jx, jy, jz);
+                const int celln = (jz + 1) * cxy + (jy + 1) * cx + (jx + 1);
+                const float4 n0 = *reinterpret_cast<const float4*>(&cells[celln].d[0]);
+                const float4 n1 = *reinterpret_cast<const float4*>(&cells[celln].d[4]);
+                const uint2 nm = *reinterpret_cast<const uint2*>(&cells[celln].m[0]);
+                if (h > 0.0f) {
+                    const uint32_t m0 = mm.x & 0xFFu;
+                    if (mm.x == mm.y && mm.x == m0 * 0x01010101u) {
+                        const float a00 = d0.x + fx * (d0.y - d0.x), a01 = d0.z + fx * (d0.w - d0.z);
+                        const float a10 = d1.x + fx * (d1.y - d1.x), a11 = d1.z + fx * (d1.w - d1.z);
+                        const float b0 = a00 + fy * (a01 - a00), b1 = a10 + fy * (a11 - a10);
+                        const int m = min((int)m0, n_mat - 1);
+                        if (m != cur) {
+                            if (cur >= 0) Lm[cur * kRtBlock] += acc;
+                            cur = m;
+                            acc = 0.0f;
+                        }
+                        acc += h * (b0 + fz * (b1 - b0));
+                    } else {
+                        const float gx0 = 1.0f - fx, gy0 = 1.0f - fy, gz0 = 1.0f - fz;
+                        const float wz0 = h * gz0, wz1 = h * fz;
+                        const float cd[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
 #pragma unroll
-                for (int c = 0; c < 8; ++c) {
-                    const uint32_t word = c < 4 ? mm.x : mm.y;
-                    const int m = min((int)((word >> (8 * (c & 3))) & 0xFFu), n_mat - 1);
-                    const float wc = (c & 1 ? fx : gx0) * (c & 2 ? fy : gy0) * (c & 4 ? wz1 : wz0);
-                    Lm[m * kRtBlock] += wc * cd[c];
+                        for (int c = 0; c < 8; ++c) {
+                            const uint32_t word = c < 4 ? mm.x : mm.y;
+                            const int m = min((int)((word >> (8 * (c & 3))) & 0xFFu), n_mat - 1);
+                            const float wc = (c & 1 ? fx : gx0) * (c & 2 ? fy : gy0) * (c & 4 ? wz1 : wz0);
+                            Lm[m * kRtBlock] += wc * cd[c];
+                        }
+                    }
                 }
+                h = hn; fx = fxn; fy = fyn; fz = fzn;
+                d0 = n0; d1 = n1; mm = nm;
             }
         }
         if (cur >= 0) Lm[cur * kRtBlock] += acc;
