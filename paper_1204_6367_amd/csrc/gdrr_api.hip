@@ -1003,7 +1003,30 @@ int run_denoise(const double* shat, long long stride, int n_img, int nv, int nu,
     char* wsa = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
     float* pp[2] = {(float*)wsa, (float*)(wsa + buf)};
     std::vector<Launch> ls;
-    const int passes = std::max(1, (iters + kDnHalo - 1) / kDnHalo);
+    // whole images in one workgroup's registers: 64 C columns, R rows per wavefront
+    const void* image_kernel = nullptr;
+    int image_waves = 0;
+    const int img_c[3] = {4, 2, 1}, img_r[3] = {12, 24, 48};
+    const void* img_k[3] = {(const void*)&denoise_image_kernel<4, 12>, (const void*)&denoise_image_kernel<2, 24>,
+                            (const void*)&denoise_image_kernel<1, 48>};
+    for (int q = 0; q < 3 && !image_kernel; ++q)
+        if (nu == 64 * img_c[q] && nv % img_r[q] == 0 && nv / img_r[q] <= 16) {
+            image_kernel = img_k[q];
+            image_waves = nv / img_r[q];
+        }
+    const int passes = image_kernel ? 0 : std::max(1, (iters + kDnHalo - 1) / kDnHalo);
+    if (image_kernel) {
+        DnParams d{};
+        d.shat = shat;
+        d.shat_stride = stride;
+        d.out = out;
+        d.n_img = n_img; d.nv = nv; d.nu = nu;
+        d.iters = iters;
+        d.omega = omega;
+        d.inv_beta = 1.0f / beta;
+        d.s_floor = s_floor;
+        ls.push_back(make_launch(image_kernel, dim3((unsigned)n_img), dim3(64 * image_waves), 0, d));
+    }
     for (int p = 0; p < passes; ++p) {
         DnParams d{};
         d.shat = shat;

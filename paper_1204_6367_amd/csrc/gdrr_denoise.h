@@ -106,6 +106,79 @@ __global__ __launch_bounds__(kDnBlock) void denoise_inside_kernel(DnParams D) {
     }
 }
 
+// Whole images that fit one workgroup's registers (nu = 64 C, nv = R x the
+// number of wavefronts, at most 16): lane l of wavefront w holds the C x R
+// block of columns [l C, l C + C) and rows [w R, w R + R), and all the sweeps
+// run in one launch, with no halo and no pass through memory between sweeps.
+// Neighbours inside the block are registers; across lanes the first/last
+// column comes from the neighbouring lane by a DPP whole-wavefront shift (at
+// the image's left/right edge a lane keeps its own pixel); across wavefronts
+// the first/last row goes through LDS (at the top/bottom edge the pixel
+// itself).  One workgroup per image.
+template <int C, int R>
+__global__ __launch_bounds__(1024) void denoise_image_kernel(DnParams D) {
+    __shared__ float edge[2][16][64 * C];                 // first and last row of each wavefront's band
+    const int img = blockIdx.x;
+    const int waves = blockDim.x >> 6;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const size_t npix = (size_t)D.nv * D.nu;
+    const int r0 = wave * R, c0 = lane * C;
+    const double* H = D.shat + (size_t)img * D.shat_stride + (size_t)r0 * D.nu + c0;
+    float s[R][C], h[R][C];
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            h[k][c] = (float)H[(size_t)k * D.nu + c];
+            s[k][c] = fmaxf(h[k][c], D.s_floor);
+        }
+    const float w1 = 1.0f - D.omega, qw = 0.25f * D.omega;
+    for (int it = 0; it < D.iters; ++it) {
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            edge[0][wave][c0 + c] = s[0][c];
+            edge[1][wave][c0 + c] = s[R - 1][c];
+        }
+        __syncthreads();
+        float above[C], below[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            above[c] = wave > 0 ? edge[1][wave - 1][c0 + c] : s[0][c];
+            below[c] = wave < waves - 1 ? edge[0][wave + 1][c0 + c] : s[R - 1][c];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            // the row's old values and its neighbours outside this lane's block
+            float row[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) row[c] = s[k][c];
+            const float left = __int_as_float(__builtin_amdgcn_update_dpp(
+                __float_as_int(row[0]), __float_as_int(row[C - 1]), 0x138, 0xf, 0xf, false));   // wave_shr:1
+            const float right = __int_as_float(__builtin_amdgcn_update_dpp(
+                __float_as_int(row[C - 1]), __float_as_int(row[0]), 0x130, 0xf, 0xf, false));  // wave_shl:1
+#pragma unroll
+            for (int c = 0; c < C; ++c) {
+                const float sk = row[c];
+                const float up = above[c];
+                const float dn = k + 1 < R ? s[k + 1][c] : below[c];
+                const float lf = c > 0 ? row[c - 1] : left;
+                const float rt = c + 1 < C ? row[c + 1] : right;
+                const float hk = h[k][c];
+                const float data = hk == 0.0f ? 1.0f : 1.0f - hk * __builtin_amdgcn_rcpf(sk);
+                const float v = w1 * sk + qw * ((up + dn + lf + rt) - data * D.inv_beta);
+                s[k][c] = fmaxf(v, D.s_floor);
+                above[c] = sk;                            // old value, the next row's upper neighbour
+            }
+        }
+    }
+    double* out = D.out + (size_t)img * npix + (size_t)r0 * D.nu + c0;
+#pragma unroll
+    for (int k = 0; k < R; ++k)
+#pragma unroll
+        for (int c = 0; c < C; ++c) out[(size_t)k * D.nu + c] = (double)s[k][c];
+}
+
 // Any image size: the region may stick out of the image; rows and columns
 // outside it are masked.
 __global__ __launch_bounds__(kDnBlock) void denoise_kernel(DnParams D) {

@@ -1,8 +1,9 @@
 """GPU parity of the scatter denoising (Sec. 2.5, Eq. 5) and the noise
 assembly (Sec. 2.6) against the CPU oracle on the same images: iteration
 counts across the LDS passes (0, 1, one pass, one pass + 1, many), ragged
-image sizes over several tiles, both kernels (images smaller than a region,
-and images whose regions are shifted inside them), zeros in the data,
+image sizes over several tiles, the three kernels (images smaller than a
+region, images whose regions are shifted inside them, whole images in one
+workgroup), zeros in the data,
 strided input (plane 2 of a batch's tallies), and the full detector of the
 benchmark."""
 import sys
@@ -69,6 +70,23 @@ def test_denoise_regions_inside_the_image(gpu, nv, nu, iters):
     shat = poisson_images(nv + nu + iters, 2, nv, nu)
     shat[0, :3, :5] = 0.0                                  # zeros at a corner
     log("denoise inside", nv, nu, iters)
+    g = gpu.denoise(torch.tensor(shat, device="cuda"), beta=0.05, iters=iters, s_floor=1e-3).cpu().numpy()
+    o = oracle.denoise(shat, 0.05, iters, s_floor=1e-3)
+    err = np.abs(g - o).max()
+    log("max abs err", err, "tol", tol_of(o, iters))
+    assert err <= tol_of(o, iters)
+
+
+@pytest.mark.parametrize("nv,nu,iters", [(192, 256, 37), (36, 256, 8), (48, 128, 1), (96, 64, 19), (12, 256, 0)])
+def test_denoise_whole_images_in_one_workgroup(gpu, nv, nu, iters):
+    """Images whose width is 64, 128 or 256 and whose height is a multiple of
+    48, 24 or 12 rows (at most 16 of them) take the kernel that holds the
+    whole image in one workgroup and runs every sweep in one launch."""
+    import torch
+    import oracle
+    shat = poisson_images(nv * 3 + nu + iters, 3, nv, nu)
+    shat[1, -2:, -3:] = 0.0                                # zeros at a corner
+    log("denoise whole image", nv, nu, iters)
     g = gpu.denoise(torch.tensor(shat, device="cuda"), beta=0.05, iters=iters, s_floor=1e-3).cpu().numpy()
     o = oracle.denoise(shat, 0.05, iters, s_floor=1e-3)
     err = np.abs(g - o).max()
