@@ -107,7 +107,7 @@ def measured_traffic(path, workload, kernel=None):
     """Memory-side bytes per launch of a kernel from rocprofv3 FETCH_SIZE +
     WRITE_SIZE (scaled by the copy calibration), if they were taken on the
     current kernel sources.  `kernel` selects a secondary record
-    (e.g. "raytrace_kernel") of the workload."""
+    ("raytrace", "denoise") of the workload."""
     if not path or not os.path.exists(path):
         return None
     try:
@@ -341,7 +341,7 @@ def raytrace_leg(wl, api, torch, steps, cpu):
     nbytes = sum(BYTES_RT_VOXEL * int(np.prod(batch.vols[j.volume].shape)) + BYTES_RT_PIXEL * j.geom.nu * j.geom.nv
                  for j in batch.jobs)
     gbs = nbytes / (kms * 1e-3) / 1e9
-    tr = measured_traffic(TRAFFIC_PATH, wl["config"]["workload"], "raytrace_kernel")
+    tr = measured_traffic(TRAFFIC_PATH, wl["config"]["workload"], "raytrace")
     ra = dict(bound="alu", achieved=round(alu, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Tops/s",
               frac=round(alu / ALU_PEAK_TOPS, 4), traffic=tr)
     rh = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -411,7 +411,7 @@ def denoise_leg(wl, api, torch, steps, rt_images, cpu):
                pixel_sweeps_per_s=round(px * DENOISE_ITERS / (kms * 1e-3), 1),
                roofline=dict(bound="alu", achieved=round(slots, 3), peak=round(ALU_PEAK_TOPS, 2), unit="Tops/s",
                              frac=round(slots / ALU_PEAK_TOPS, 4),
-                             traffic=measured_traffic(TRAFFIC_PATH, wl["config"]["workload"], "denoise_kernel")),
+                             traffic=measured_traffic(TRAFFIC_PATH, wl["config"]["workload"], "denoise")),
                noise=dict(wall_ms=round(nms, 3), alpha=round(alpha, 6),
                           roofline=dict(bound="hbm", achieved=round(px * BYTES_NOISE / (nms * 1e-3) / 1e9, 1),
                                         peak=HBM_PEAK_GBS, unit="GB/s",
