@@ -88,6 +88,37 @@ def test_mixed_batch_equals_single_projections(gpu):
         assert torch.equal(t, one)
 
 
+def test_untraced_volumes_do_not_change_results(gpu):
+    """Cube records are staged only for the volumes a launch traces: a batch
+    whose jobs use one of three local-majorant volumes gives bitwise the
+    tallies of that volume alone, and the adjoint of one volume of a batch
+    equals that of a batch holding it alone (float64 atomics: to 1e-12)."""
+    import torch
+    a = body_problem(200_000)
+    c = body_problem(200_000, seed=9, shape=(30, 40, 44))
+    va, pa, sa = gpu.upload(a)
+    vc = gpu.DeviceVolume(c.phantom.density, c.phantom.material, c.phantom.spacing_mm)
+    vd = gpu.DeviceVolume(c.phantom.density[::-1].copy(), c.phantom.material[::-1].copy(), c.phantom.spacing_mm)
+    for v, m in ((va, 5), (vc, 4), (vd, 7)):
+        v.local_majorants(m, margin=0.1)
+    jobs = [gpu.JobSpec(a.geom.replace(phi_rad=p), 200_000, k, volume=1) for k, p in enumerate([0.3, 1.7])]
+    three = gpu.Batch([vc, va, vd], pa, [sa], jobs)
+    alone = gpu.Batch([va], pa, [sa], [gpu.JobSpec(j.geom, j.n_photons, j.job_id) for j in jobs])
+    log("untraced volumes: forward")
+    t3 = three.tally_views(three.project(seed=5))
+    t1 = alone.tally_views(alone.project(seed=5))
+    for x, y in zip(t3, t1):
+        assert torch.equal(x, y)
+    log("untraced volumes: adjoint")
+    rng = np.random.default_rng(4)
+    adj = torch.tensor(rng.normal(size=(len(jobs), 2, a.geom.nv, a.geom.nu)), device="cuda")
+    g3 = three.backward(adj, three.majorants(True, 0.1), volume=1, seed=2)
+    g1 = alone.backward(adj, alone.majorants(True, 0.1), volume=0, seed=2)
+    rel = float((g3 - g1).norm() / g1.norm())
+    log("adjoint rel diff", rel)
+    assert rel < 1e-12
+
+
 @pytest.mark.parametrize("idx,macro", [(0, 16), (1, 8), (2, 4)])
 def test_full_size_sampled_histories(gpu, idx, macro):
     import torch
