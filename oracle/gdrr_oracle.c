@@ -5,7 +5,7 @@
  *
  * TEST INFRASTRUCTURE ONLY.  This file is a plain, slow, double-precision
  * restatement of what the method computes, used by the tests, by the smoke
- * check and by the benchmark's CPU-baseline leg to judge the GPU library.  The
+ * check and by the benchmark's CPU-baseline leg to check the GPU library.  The
  * product path never links, loads or calls it, and it shares no code, header
  * or table with the GPU library: the two meet only in the seeded input arrays.
  *
