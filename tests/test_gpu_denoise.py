@@ -108,6 +108,19 @@ def test_denoise_strided_tally_planes(gpu):
     assert torch.equal(one, a[2])
 
 
+def test_denoise_whole_image_strided_planes(gpu):
+    """The whole-image kernel on plane 2 of [n][4][nv][nu] tallies equals the contiguous copy."""
+    import torch
+    shat = poisson_images(5, 3, 48, 128, mean=90.0)
+    t = torch.zeros(3, 4, 48, 128, dtype=torch.float64, device="cuda")
+    t[:, 2] = torch.tensor(shat, device="cuda")
+    t[:, 0] = 1e9                                          # must not be read
+    t[:, 3] = -1.0
+    a = gpu.denoise(t[:, 2], beta=0.1, iters=30)
+    b = gpu.denoise(t[:, 2].contiguous(), beta=0.1, iters=30)
+    assert torch.equal(a, b)
+
+
 def test_denoise_full_detector(gpu):
     """The benchmark's detector (256 x 192), 40 images, 64 sweeps; 3 checked in the oracle."""
     import torch
