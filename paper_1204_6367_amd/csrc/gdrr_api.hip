@@ -379,6 +379,10 @@ struct Batch {
     bool use_graph;
 };
 
+// Host staging of the per-call tables.  It is pageable memory: a host-to-device
+// hipMemcpyAsync from pageable memory returns only once the source has been
+// copied out (into the runtime's own staging for the DMA), so the buffer can be
+// refilled by the next call while the previous copy is still in flight.
 thread_local std::vector<char> g_staging;
 
 // Geometry part of a job record (Sec. 2.1), evaluated in double and stored as float.
