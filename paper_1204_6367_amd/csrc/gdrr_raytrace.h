@@ -28,6 +28,52 @@ namespace gdrr {
 constexpr int kRtBlock = 256;     // 16 x 16 pixels; each wavefront an 8 x 8 quadrant
 constexpr int kXcds = 8;          // workgroup i runs on XCD i mod 8
 
+// The ray tracer's lattice cells, 32 bytes: the eight corner densities, whose
+// sign bits (densities are >= 0) carry the materials -- d[0]'s sign set: the
+// corners' materials differ (they are then read from the voxel array); else
+// the signs of d[1..4] hold the corners' common material, clamped to n_mat-1
+// (n_mat <= 16).  Half the bytes of the transport's records in one pair of
+// loads.
+struct alignas(32) RtCell {
+    float d[8];
+};
+
+struct RtCellParams {
+    const float* density;
+    const uint8_t* material;
+    int nx, ny, nz, n_mat;
+    RtCell* cells;
+};
+
+__global__ __launch_bounds__(256) void rt_cells_kernel(RtCellParams C) {
+    const long long cx = C.nx + 1, cy = C.ny + 1, n = cx * cy * (long long)(C.nz + 1);
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(t % cx) - 1, j = (int)((t / cx) % cy) - 1, k = (int)(t / (cx * cy)) - 1;
+        uint32_t d[8];
+        uint32_t m0 = 0u;
+        bool same = true;
+        for (int c = 0; c < 8; ++c) {
+            const int x = min(max(i + (c & 1), 0), C.nx - 1);
+            const int y = min(max(j + ((c >> 1) & 1), 0), C.ny - 1);
+            const int z = min(max(k + (c >> 2), 0), C.nz - 1);
+            const long long v = ((long long)z * C.ny + y) * C.nx + x;
+            d[c] = __float_as_uint(C.density[v]) & 0x7FFFFFFFu;
+            const uint32_t m = C.material[v];
+            if (c == 0) m0 = m;
+            same = same && m == m0;
+        }
+        if (!same) {
+            d[0] |= 0x80000000u;
+        } else {
+            const uint32_t mc = min(m0, (uint32_t)(C.n_mat - 1));
+            for (int b = 0; b < 4; ++b) d[1 + b] |= ((mc >> b) & 1u) << 31;
+        }
+        float4* out = reinterpret_cast<float4*>(C.cells + t);
+        out[0] = make_float4(__uint_as_float(d[0]), __uint_as_float(d[1]), __uint_as_float(d[2]), __uint_as_float(d[3]));
+        out[1] = make_float4(__uint_as_float(d[4]), __uint_as_float(d[5]), __uint_as_float(d[6]), __uint_as_float(d[7]));
+    }
+}
+
 struct RtSource {
     const float* fluence;         // [nv][nu] weights w(u) (unnormalised)
     const float* coef;            // [rows][n_spec] phi_k r(E_k) / sum phi (row iu: detector column iu)
@@ -38,6 +84,7 @@ struct RtSource {
 
 struct RtParams {
     DVolume vol[GDRR_MAX_VOLUMES];
+    const RtCell* rcells[GDRR_MAX_VOLUMES];      // with interpolation: cells of each volume that some job uses
     RtSource src[GDRR_MAX_SOURCES];
     float dl[GDRR_MAX_VOLUMES];   // interval length per volume, mm
     const DJob* jobs;
@@ -105,7 +152,7 @@ __global__ __launch_bounds__(kRtBlock) void raytrace_kernel(RtParams P) {
     if (t0 < t1) {
         const float dl = P.dl[J.vol];
         // the volume's fields in registers for the march
-        const CellRec* __restrict__ cells = V.cells;
+        const RtCell* __restrict__ cells = P.rcells[J.vol];
         const float* __restrict__ dens = V.density;
         const uint8_t* __restrict__ mats = V.material;
         const int nx = V.nx, ny = V.ny, nz = V.nz, nxy = V.nxy, cx = V.cx, cxy = V.cxy;
@@ -162,7 +209,6 @@ __global__ __launch_bounds__(kRtBlock) void raytrace_kernel(RtParams P) {
             const int cell = (iz + 1) * cxy + (iy + 1) * cx + (ix + 1);
             float4 d0 = *reinterpret_cast<const float4*>(&cells[cell].d[0]);
             float4 d1 = *reinterpret_cast<const float4*>(&cells[cell].d[4]);
-            uint2 mm = *reinterpret_cast<const uint2*>(&cells[cell].m[0]);
             for (int j = jb; j < je; ++j) {
                 float hn, fxn, fyn, fzn;
                 int jx, jy, jz;
@@ -170,14 +216,17 @@ __global__ __launch_bounds__(kRtBlock) void raytrace_kernel(RtParams P) {
                 const int celln = (jz + 1) * cxy + (jy + 1) * cx + (jx + 1);
                 const float4 n0 = *reinterpret_cast<const float4*>(&cells[celln].d[0]);
                 const float4 n1 = *reinterpret_cast<const float4*>(&cells[celln].d[4]);
-                const uint2 nm = *reinterpret_cast<const uint2*>(&cells[celln].m[0]);
                 if (h > 0.0f) {
-                    const uint32_t m0 = mm.x & 0xFFu;
-                    if (mm.x == mm.y && mm.x == m0 * 0x01010101u) {
-                        const float a00 = d0.x + fx * (d0.y - d0.x), a01 = d0.z + fx * (d0.w - d0.z);
-                        const float a10 = d1.x + fx * (d1.y - d1.x), a11 = d1.z + fx * (d1.w - d1.z);
+                    const uint32_t s0 = __float_as_uint(d0.x), s1 = __float_as_uint(d0.y), s2 = __float_as_uint(d0.z),
+                                   s3 = __float_as_uint(d0.w), s4 = __float_as_uint(d1.x);
+                    // the densities without their flag bits
+                    const float c0 = fabsf(d0.x), c1 = fabsf(d0.y), c2 = fabsf(d0.z), c3 = fabsf(d0.w);
+                    const float c4 = fabsf(d1.x), c5 = d1.y, c6 = d1.z, c7 = d1.w;
+                    if (!(s0 >> 31)) {
+                        const float a00 = c0 + fx * (c1 - c0), a01 = c2 + fx * (c3 - c2);
+                        const float a10 = c4 + fx * (c5 - c4), a11 = c6 + fx * (c7 - c6);
                         const float b0 = a00 + fy * (a01 - a00), b1 = a10 + fy * (a11 - a10);
-                        const int m = min((int)m0, n_mat - 1);
+                        const int m = (int)((s1 >> 31) | ((s2 >> 30) & 2u) | ((s3 >> 29) & 4u) | ((s4 >> 28) & 8u));
                         if (m != cur) {
                             if (cur >= 0) Lm[cur * kRtBlock] += acc;
                             cur = m;
@@ -187,18 +236,21 @@ __global__ __launch_bounds__(kRtBlock) void raytrace_kernel(RtParams P) {
                     } else {
                         const float gx0 = 1.0f - fx, gy0 = 1.0f - fy, gz0 = 1.0f - fz;
                         const float wz0 = h * gz0, wz1 = h * fz;
-                        const float cd[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
+                        const float cd[8] = {c0, c1, c2, c3, c4, c5, c6, c7};
 #pragma unroll
                         for (int c = 0; c < 8; ++c) {
-                            const uint32_t word = c < 4 ? mm.x : mm.y;
-                            const int m = min((int)((word >> (8 * (c & 3))) & 0xFFu), n_mat - 1);
+                            const int x = min(max(ix + (c & 1), 0), nx - 1);
+                            const int y = min(max(iy + ((c >> 1) & 1), 0), ny - 1);
+                            const int z = min(max(iz + (c >> 2), 0), nz - 1);
+                            const int m = min((int)mats[(long long)z * nxy + (long long)y * nx + x], n_mat - 1);
                             const float wc = (c & 1 ? fx : gx0) * (c & 2 ? fy : gy0) * (c & 4 ? wz1 : wz0);
                             Lm[m * kRtBlock] += wc * cd[c];
                         }
                     }
                 }
                 h = hn; fx = fxn; fy = fyn; fz = fzn;
-                d0 = n0; d1 = n1; mm = nm;
+                ix = jx; iy = jy; iz = jz;
+                d0 = n0; d1 = n1;
             }
         }
         if (cur >= 0) Lm[cur * kRtBlock] += acc;
