@@ -605,7 +605,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     for (int v = 0; v < B.n_vols; ++v) {
         if (!batch_uses(B, v)) continue;
         const gdrr_volume& V = B.vols[v];
-        CellParams cp{V.density, V.material, V.nx, V.ny, V.nz, L.cells[v]};
+        CellParams cp{V.density, V.material, V.nx, V.ny, V.nz, phys->n_mat, L.cells[v]};
         const size_t nc = cell_count(V);
         ls.push_back(make_launch((const void*)&cells_kernel,
                                  dim3((unsigned)std::max<size_t>(1, std::min<size_t>((size_t)dev.cus * 16, (nc + 255) / 256))),
@@ -751,7 +751,7 @@ struct RtLayout {
     float* coef[GDRR_MAX_SOURCES];       // [rows][n_spec]
     float* tab[GDRR_MAX_SOURCES];        // [n_spec][n_mat]
     double* inv_wsum[GDRR_MAX_SOURCES];  // [1]
-    RtCell* cells[GDRR_MAX_VOLUMES];     // volumes that some job uses
+    CellRec* cells[GDRR_MAX_VOLUMES];    // volumes that some job uses
     size_t bytes;
 };
 
@@ -800,7 +800,7 @@ RtLayout rt_carve(void* ws, const gdrr_volume* vols, int n_vols, const gdrr_phys
         L.inv_wsum[s] = c.take<double>(1);
     }
     for (int v = 0; v < n_vols; ++v)
-        L.cells[v] = volume_used(jobs, n_jobs, v) ? c.take<RtCell>(cell_count(vols[v])) : nullptr;
+        L.cells[v] = volume_used(jobs, n_jobs, v) ? c.take<CellRec>(cell_count(vols[v])) : nullptr;
     L.bytes = c.off + 256;
     return L;
 }
@@ -929,8 +929,7 @@ int run_primary(const gdrr_volume* vols, int n_vols, const gdrr_physics* phys, c
         DVolume& d = rp.vol[v];
         d.density = V.density;
         d.material = V.material;
-        d.cells = nullptr;
-        rp.rcells[v] = interp ? L.cells[v] : nullptr;
+        d.cells = interp ? L.cells[v] : nullptr;
         d.cx = V.nx + 1;
         d.cxy = (V.nx + 1) * (V.ny + 1);
         d.nx = V.nx; d.ny = V.ny; d.nz = V.nz; d.nxy = V.nx * V.ny;
@@ -939,9 +938,9 @@ int run_primary(const gdrr_volume* vols, int n_vols, const gdrr_physics* phys, c
         d.loz = (float)(-0.5 * V.nz * V.dz_mm); d.hiz = -d.loz;
         d.idx = (float)(1.0 / V.dx_mm); d.idy = (float)(1.0 / V.dy_mm); d.idz = (float)(1.0 / V.dz_mm);
         if (interp && L.cells[v]) {
-            RtCellParams cp{V.density, V.material, V.nx, V.ny, V.nz, phys->n_mat, L.cells[v]};
+            CellParams cp{V.density, V.material, V.nx, V.ny, V.nz, phys->n_mat, L.cells[v]};
             const size_t nc = cell_count(V);
-            ls.push_back(make_launch((const void*)&rt_cells_kernel,
+            ls.push_back(make_launch((const void*)&cells_kernel,
                                      dim3((unsigned)std::max<size_t>(1, std::min<size_t>((size_t)dev.cus * 16, (nc + 255) / 256))),
                                      dim3(256), 0, cp));
         }

@@ -78,12 +78,14 @@ __device__ __forceinline__ float cos_rev(float r) { return __builtin_amdgcn_cosf
 // One record per cell of the lattice of voxel centres: cell (i, j, k),
 // i in [-1, nx-1], has the voxel centres i and i+1 (clamped into the volume)
 // as corners along x, likewise along y and z; corner c = bx + 2 by + 4 bz.
-// The record holds the eight corner densities and materials, so the stencil
-// of a free flight is one aligned 64-byte line.
-struct alignas(64) CellRec {
+// The record holds the eight corner densities in 32 bytes; their sign bits
+// (densities are >= 0) carry the materials: d[0]'s sign set means the
+// corners' materials differ (they are then read from the voxel array),
+// otherwise the signs of d[1..4] hold the corners' common material, clamped
+// to n_mat - 1 (n_mat <= 16).  The stencil of a free flight is one pair of
+// 16-byte loads.
+struct alignas(32) CellRec {
     float d[8];
-    uint8_t m[8];
-    uint32_t spare[6];
 };
 
 struct DVolume {

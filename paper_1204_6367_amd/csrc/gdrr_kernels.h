@@ -126,7 +126,8 @@ __device__ __forceinline__ float density_at(const DVolume& V, bool interp, float
     return b0 + fz * (b1 - b0);
 }
 
-// The same density and material from the cell records: one 64-byte line.
+// The same density and material from the cell records (one 32-byte record;
+// the voxel array only for the material of a cell whose corners differ).
 // The containing voxel is corner (f >= 1/2) of the cell along each axis.
 __device__ __forceinline__ float cell_density(const DVolume& V, bool interp, float px, float py, float pz,
                                               int& mat) {
@@ -141,17 +142,26 @@ __device__ __forceinline__ float cell_density(const DVolume& V, bool interp, flo
     const CellRec* r = V.cells + ((iz + 1) * V.cxy + (iy + 1) * V.cx + (ix + 1));
     const float4 lo4 = *reinterpret_cast<const float4*>(&r->d[0]);
     const float4 hi4 = *reinterpret_cast<const float4*>(&r->d[4]);
-    const uint2 mm = *reinterpret_cast<const uint2*>(&r->m[0]);
     const int bits = (fx >= 0.5f ? 1 : 0) | (fy >= 0.5f ? 2 : 0) | (fz >= 0.5f ? 4 : 0);
-    const uint32_t mw = bits & 4 ? mm.y : mm.x;
-    mat = (int)((mw >> ((bits & 3) * 8)) & 0xFFu);
-    if (!interp) {
-        const float4 q = bits & 4 ? hi4 : lo4;
-        const int b2 = bits & 3;
-        return b2 == 0 ? q.x : (b2 == 1 ? q.y : (b2 == 2 ? q.z : q.w));
+    const uint32_t s0 = __float_as_uint(lo4.x);
+    if (!(s0 >> 31)) {
+        mat = (int)((__float_as_uint(lo4.y) >> 31) | ((__float_as_uint(lo4.z) >> 30) & 2u) |
+                    ((__float_as_uint(lo4.w) >> 29) & 4u) | ((__float_as_uint(hi4.x) >> 28) & 8u));
+    } else {
+        const int vx = min(max(ix + (bits & 1), 0), V.nx - 1);
+        const int vy = min(max(iy + ((bits >> 1) & 1), 0), V.ny - 1);
+        const int vz = min(max(iz + (bits >> 2), 0), V.nz - 1);
+        mat = V.material[vz * V.nxy + vy * V.nx + vx];
     }
-    const float a00 = lo4.x + fx * (lo4.y - lo4.x), a01 = lo4.z + fx * (lo4.w - lo4.z);
-    const float a10 = hi4.x + fx * (hi4.y - hi4.x), a11 = hi4.z + fx * (hi4.w - hi4.z);
+    const float c0 = fabsf(lo4.x), c1 = fabsf(lo4.y), c2 = fabsf(lo4.z), c3 = fabsf(lo4.w);
+    const float c4 = fabsf(hi4.x), c5 = hi4.y, c6 = hi4.z, c7 = hi4.w;
+    if (!interp) {
+        const int b2 = bits & 3;
+        return bits & 4 ? (b2 == 0 ? c4 : (b2 == 1 ? c5 : (b2 == 2 ? c6 : c7)))
+                        : (b2 == 0 ? c0 : (b2 == 1 ? c1 : (b2 == 2 ? c2 : c3)));
+    }
+    const float a00 = c0 + fx * (c1 - c0), a01 = c2 + fx * (c3 - c2);
+    const float a10 = c4 + fx * (c5 - c4), a11 = c6 + fx * (c7 - c6);
     const float b0 = a00 + fy * (a01 - a00), b1 = a10 + fy * (a11 - a10);
     return b0 + fz * (b1 - b0);
 }
@@ -771,7 +781,7 @@ __global__ __launch_bounds__(256) void macro_kernel(MacroParams M) {
 struct CellParams {
     const float* density;
     const uint8_t* material;
-    int nx, ny, nz;
+    int nx, ny, nz, n_mat;
     CellRec* cells;
 };
 
@@ -779,22 +789,28 @@ __global__ __launch_bounds__(256) void cells_kernel(CellParams C) {
     const long long cx = C.nx + 1, cy = C.ny + 1, n = cx * cy * (long long)(C.nz + 1);
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
         const int i = (int)(t % cx) - 1, j = (int)((t / cx) % cy) - 1, k = (int)(t / (cx * cy)) - 1;
-        float d[8];
-        uint32_t mlo = 0u, mhi = 0u;
+        uint32_t d[8];
+        uint32_t m0 = 0u;
+        bool same = true;
         for (int c = 0; c < 8; ++c) {
             const int x = min(max(i + (c & 1), 0), C.nx - 1);
             const int y = min(max(j + ((c >> 1) & 1), 0), C.ny - 1);
             const int z = min(max(k + (c >> 2), 0), C.nz - 1);
             const long long v = ((long long)z * C.ny + y) * C.nx + x;
-            d[c] = C.density[v];
+            d[c] = __float_as_uint(C.density[v]) & 0x7FFFFFFFu;
             const uint32_t m = C.material[v];
-            if (c < 4) mlo |= m << (8 * c); else mhi |= m << (8 * (c - 4));
+            if (c == 0) m0 = m;
+            same = same && m == m0;
+        }
+        if (!same) {
+            d[0] |= 0x80000000u;
+        } else {
+            const uint32_t mc = min(m0, (uint32_t)(C.n_mat - 1));
+            for (int b = 0; b < 4; ++b) d[1 + b] |= ((mc >> b) & 1u) << 31;
         }
         float4* out = reinterpret_cast<float4*>(C.cells + t);
-        out[0] = make_float4(d[0], d[1], d[2], d[3]);
-        out[1] = make_float4(d[4], d[5], d[6], d[7]);
-        out[2] = make_float4(__uint_as_float(mlo), __uint_as_float(mhi), 0.0f, 0.0f);
-        out[3] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        out[0] = make_float4(__uint_as_float(d[0]), __uint_as_float(d[1]), __uint_as_float(d[2]), __uint_as_float(d[3]));
+        out[1] = make_float4(__uint_as_float(d[4]), __uint_as_float(d[5]), __uint_as_float(d[6]), __uint_as_float(d[7]));
     }
 }
 

@@ -28,52 +28,6 @@ namespace gdrr {
 constexpr int kRtBlock = 256;     // 16 x 16 pixels; each wavefront an 8 x 8 quadrant
 constexpr int kXcds = 8;          // workgroup i runs on XCD i mod 8
 
-// The ray tracer's lattice cells, 32 bytes: the eight corner densities, whose
-// sign bits (densities are >= 0) carry the materials -- d[0]'s sign set: the
-// corners' materials differ (they are then read from the voxel array); else
-// the signs of d[1..4] hold the corners' common material, clamped to n_mat-1
-// (n_mat <= 16).  Half the bytes of the transport's records in one pair of
-// loads.
-struct alignas(32) RtCell {
-    float d[8];
-};
-
-struct RtCellParams {
-    const float* density;
-    const uint8_t* material;
-    int nx, ny, nz, n_mat;
-    RtCell* cells;
-};
-
-__global__ __launch_bounds__(256) void rt_cells_kernel(RtCellParams C) {
-    const long long cx = C.nx + 1, cy = C.ny + 1, n = cx * cy * (long long)(C.nz + 1);
-    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(t % cx) - 1, j = (int)((t / cx) % cy) - 1, k = (int)(t / (cx * cy)) - 1;
-        uint32_t d[8];
-        uint32_t m0 = 0u;
-        bool same = true;
-        for (int c = 0; c < 8; ++c) {
-            const int x = min(max(i + (c & 1), 0), C.nx - 1);
-            const int y = min(max(j + ((c >> 1) & 1), 0), C.ny - 1);
-            const int z = min(max(k + (c >> 2), 0), C.nz - 1);
-            const long long v = ((long long)z * C.ny + y) * C.nx + x;
-            d[c] = __float_as_uint(C.density[v]) & 0x7FFFFFFFu;
-            const uint32_t m = C.material[v];
-            if (c == 0) m0 = m;
-            same = same && m == m0;
-        }
-        if (!same) {
-            d[0] |= 0x80000000u;
-        } else {
-            const uint32_t mc = min(m0, (uint32_t)(C.n_mat - 1));
-            for (int b = 0; b < 4; ++b) d[1 + b] |= ((mc >> b) & 1u) << 31;
-        }
-        float4* out = reinterpret_cast<float4*>(C.cells + t);
-        out[0] = make_float4(__uint_as_float(d[0]), __uint_as_float(d[1]), __uint_as_float(d[2]), __uint_as_float(d[3]));
-        out[1] = make_float4(__uint_as_float(d[4]), __uint_as_float(d[5]), __uint_as_float(d[6]), __uint_as_float(d[7]));
-    }
-}
-
 struct RtSource {
     const float* fluence;         // [nv][nu] weights w(u) (unnormalised)
     const float* coef;            // [rows][n_spec] phi_k r(E_k) / sum phi (row iu: detector column iu)
@@ -84,7 +38,6 @@ struct RtSource {
 
 struct RtParams {
     DVolume vol[GDRR_MAX_VOLUMES];
-    const RtCell* rcells[GDRR_MAX_VOLUMES];      // with interpolation: cells of each volume that some job uses
     RtSource src[GDRR_MAX_SOURCES];
     float dl[GDRR_MAX_VOLUMES];   // interval length per volume, mm
     const DJob* jobs;
@@ -152,7 +105,7 @@ __global__ __launch_bounds__(kRtBlock) void raytrace_kernel(RtParams P) {
     if (t0 < t1) {
         const float dl = P.dl[J.vol];
         // the volume's fields in registers for the march
-        const RtCell* __restrict__ cells = P.rcells[J.vol];
+        const CellRec* __restrict__ cells = V.cells;       // 32-byte records, materials in the sign bits
         const float* __restrict__ dens = V.density;
         const uint8_t* __restrict__ mats = V.material;
         const int nx = V.nx, ny = V.ny, nz = V.nz, nxy = V.nxy, cx = V.cx, cxy = V.cxy;

@@ -131,7 +131,7 @@ def test_workspace_query_is_positive(abi):
     vol, phys, src, geom = _valid_structs(abi)
     L = abi.lib()
     n = L.gdrr_mc_project_workspace(C.byref(vol), C.byref(phys), C.byref(src), C.byref(geom))
-    assert n > 8 * 4 * 16 * 12 + 64 * 9 * 9 * 9
+    assert n > 8 * 4 * 16 * 12 + 32 * 9 * 9 * 9      # tallies and a 32-byte record per lattice cell
     assert L.gdrr_majorant_workspace() >= 2048
     # a joint source (one spectrum per column) needs a CDF per row; a bad row count sizes nothing
     src.n_spec = 64
