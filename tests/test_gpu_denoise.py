@@ -77,7 +77,8 @@ def test_denoise_regions_inside_the_image(gpu, nv, nu, iters):
     assert err <= tol_of(o, iters)
 
 
-@pytest.mark.parametrize("nv,nu,iters", [(192, 256, 37), (36, 256, 8), (48, 128, 1), (96, 64, 19), (12, 256, 0)])
+@pytest.mark.parametrize("nv,nu,iters", [(192, 256, 37), (36, 256, 8), (48, 128, 1), (96, 64, 19), (12, 256, 0),
+                                         (12, 256, 5), (48, 64, 3)])
 def test_denoise_whole_images_in_one_workgroup(gpu, nv, nu, iters):
     """Images whose width is 64, 128 or 256 and whose height is a multiple of
     48, 24 or 12 rows (at most 16 of them) take the kernel that holds the
