@@ -156,6 +156,27 @@ def test_joint_adjoint_matches_oracle(gpu):
     assert rel <= 0.02
 
 
+@pytest.mark.parametrize("interp", [True, False])
+def test_joint_local_first_order_tallies(gpu, interp):
+    """The variants together: a joint source, local majorants, the first-order
+    and first-order-Compton scatter tallies, interpolation on and off, against
+    the oracle's tallies (pooled rel L2, totals)."""
+    import oracle
+    prob = joint_problem(600_000, random_rows=True)
+    vol, phys, src = gpu.upload(prob)
+    vol.local_majorants(6)
+    p = oracle.Problem.from_workload(prob).local_majorants(6)
+    n = prob.n_photons
+    for flag, mode in ((gpu.SCATTER_FIRST, 1), (gpu.SCATTER_FIRST_COMPTON, 2)):
+        log("joint local first order", flag, interp)
+        tg = gpu.project(vol, phys, src, prob.geom, n, seed=12, flags=flag, interp=interp).cpu().numpy()
+        to = oracle.mc_project(p, 12, n, mode=mode, interp=interp)["tally"]
+        r = tally_parity(tg, to, n, pool=8)
+        log(r)
+        assert r["P"]["rel_l2"] <= 0.01 and r["S"]["rel_l2"] <= 0.03
+        assert abs(tg[2].sum() - to[2].sum()) <= 0.01 * to[2].sum()
+
+
 def test_full_size_pelvis_joint_source(gpu):
     """The pelvis workload (256 x 256 x 160, 256 x 192 detector, 1e8 photons)
     with the bowtie-hardened joint source: 3000 sampled histories against the
