@@ -1,0 +1,67 @@
+"""Host-side logic of the benchmark (CPU only): the one-GPU guard, the
+measured-traffic records (used only while they match the kernel sources),
+and the per-history work model built from the oracle's counts."""
+import json
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+
+
+def test_measured_traffic_follows_the_kernel_sources(tmp_path):
+    sha = bench.kernel_sources_sha()
+    rec = {"c4": {"kernel_sha": sha, "fetch_bytes": 1000, "write_bytes": 24,
+                  "others": {"raytrace": {"fetch_bytes": 7, "write_bytes": 3}}}}
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps(rec))
+    assert bench.measured_traffic(str(p), "c4") == 1024
+    assert bench.measured_traffic(str(p), "c4", "raytrace") == 10
+    assert bench.measured_traffic(str(p), "c4", "denoise") is None
+    assert bench.measured_traffic(str(p), "c1") is None
+    rec["c4"]["kernel_sha"] = "0" * 16                     # taken on other sources: not used
+    p.write_text(json.dumps(rec))
+    assert bench.measured_traffic(str(p), "c4") is None
+    assert bench.measured_traffic(str(tmp_path / "missing.json"), "c4") is None
+    p.write_text("not json")
+    assert bench.measured_traffic(str(p), "c4") is None
+
+
+def test_shipped_traffic_record_names_its_summary():
+    rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["c4"]
+    assert os.path.exists(os.path.join(ROOT, rec["summary"]))
+    assert rec["fetch_bytes"] > 0 and rec["write_bytes"] > 0
+    assert set(rec["others"]) == {"raytrace", "denoise"}
+
+
+def test_work_model_composition():
+    """Slots and bytes per history add up from the oracle's counts as stated."""
+    n = 1000
+    stats = dict(steps=7000.0, real=2500.0, tries=2900.0, compton=2000.0, rayleigh=100.0, crossings=11000.0,
+                 classes=dict(primary=3.0, scatter=2.0, absorbed=600.0, cut=0.0, missed=395.0, lost=0.0))
+    w = bench.work_per_history(stats, n)
+    assert w["flights"] == pytest.approx(7.0)
+    assert w["inbox_flights"] == pytest.approx(7.0 - 0.4)
+    assert w["cube_visits"] == pytest.approx(11.0 + 7.0)
+    pairs = 0.5 * (7.0 + 2.5)
+    slots = (pairs * bench.SLOTS_PHILOX + 6.6 * bench.SLOTS_FLIGHT_IN + 0.4 * bench.SLOTS_FLIGHT_OUT
+             + 2.9 * bench.SLOTS_TRY + 2.5 * 6 + 2.1 * (bench.SLOTS_COLLISION - 6) + bench.SLOTS_SOURCE
+             + 18.0 * bench.SLOTS_CUBE)
+    assert w["slots"] == pytest.approx(slots)
+    nbytes = 6.6 * bench.BYTES_FLIGHT_IN + bench.BYTES_SOURCE + 0.005 * bench.BYTES_SCORE + 18.0 * bench.BYTES_CUBE
+    assert w["bytes"] == pytest.approx(nbytes)
+    # without cube crossings (the single majorant) no cube visits are counted
+    stats["crossings"] = 0.0
+    assert bench.work_per_history(stats, n)["cube_visits"] == 0.0
