@@ -241,3 +241,27 @@ def test_interpolation_off_matches_oracle(gpu):
     frac, _ = compare_histories(g, o)
     log("interp off identical", frac)
     assert frac >= 0.995
+
+
+def test_largest_spectrum_matches_oracle(gpu):
+    """4096 energy channels (the largest spectrum): the CDF, its guide table
+    and the ray tracer's channel sum at full size, against the oracle."""
+    import oracle
+    prob = W.pelvis_problem(200_000, shape=(40, 48, 48), spacing=(6.0, 6.0, 6.0))
+    rng = np.random.default_rng(17)
+    e = np.sort(rng.uniform(12.0, 149.0, 4096)).astype(np.float32)
+    w = (rng.uniform(0.0, 1.0, 4096) * (e < 120.0)).astype(np.float32)
+    prob.source = W.Source(e, w, prob.source.fluence)
+    vol, phys, src = gpu.upload(prob)
+    log("spectrum of 4096 channels")
+    g = gpu.trace(vol, phys, src, prob.geom, prob.n_photons, seed=3)
+    p = oracle_problem(prob)
+    o = oracle.mc_project(p, 3, prob.n_photons, trace=True)
+    frac, _ = compare_histories(g, o)
+    log("identical histories", frac)
+    assert frac >= 0.999
+    img = gpu.primary(vol, phys, src, prob.geom).cpu().numpy()
+    ref = oracle.primary_raytrace(p)
+    err = float(np.abs(img - ref).max() / ref.max())
+    log("ray tracer max rel err", err)
+    assert err < 1e-4
