@@ -766,21 +766,25 @@ unsigned long long rt_tiles(const gdrr_geometry& g) {
     return (unsigned long long)((g.nu + 15) / 16) * (unsigned long long)((g.nv + 15) / 16);
 }
 
-// Work units: a job's tiles in runs of `run` (whole jobs when there are
-// enough of them to fill every XCD several times).
+// Work units: pieces of one tile row of one job, `run` tiles long (whole
+// rows once there are enough of them to fill every XCD several times).
 unsigned long long rt_run_length(const gdrr_job* jobs, int n_jobs) {
-    unsigned long long total = 0, most = 1;
+    unsigned long long total = 0, widest = 1;
     for (int k = 0; k < n_jobs; ++k) {
         total += rt_tiles(jobs[k].geom);
-        most = std::max(most, rt_tiles(jobs[k].geom));
+        widest = std::max(widest, (unsigned long long)((jobs[k].geom.nu + 15) / 16));
     }
-    return std::min(most, std::max<unsigned long long>(4, total / (8ull * kXcds)));
+    return std::min(widest, std::max<unsigned long long>(4, total / (8ull * kXcds)));
+}
+
+unsigned long long rt_row_units(const gdrr_geometry& g, unsigned long long run) {
+    return (unsigned long long)((g.nv + 15) / 16) * (((unsigned long long)((g.nu + 15) / 16) + run - 1) / run);
 }
 
 size_t rt_max_units(const gdrr_job* jobs, int n_jobs) {
     const unsigned long long run = rt_run_length(jobs, n_jobs);
     size_t u = 0;
-    for (int k = 0; k < n_jobs; ++k) u += (size_t)((rt_tiles(jobs[k].geom) + run - 1) / run);
+    for (int k = 0; k < n_jobs; ++k) u += (size_t)rt_row_units(jobs[k].geom, run);
     return u;
 }
 
@@ -871,26 +875,32 @@ int run_primary(const gdrr_volume* vols, int n_vols, const gdrr_physics* phys, c
         tiles += rt_tiles(jobs[k].geom);
         if (tiles > kRtMaxTiles) return fail(GDRR_EINVAL, "too many pixels in one call (2^32 lanes)");
     }
-    // Units to XCDs, in job order, each to the XCD with the least estimated
-    // work so far (tiles x intervals across the job's phantom): every XCD gets
-    // a share of every phantom, and walks its units in order, so the tiles in
-    // flight on it belong to one or two projections.
+    // Units in row-band order: for each phantom, tile row by tile row, that
+    // row of every job on the phantom, dealt to the XCDs in turn.  All XCDs
+    // then work through the same band of detector rows -- the same slab of
+    // the phantom -- across all its projections at once, so the slab is read
+    // from HBM about once and served from the last-level cache after that.
     const unsigned long long run = rt_run_length(jobs, n_jobs);
     std::vector<int> u_job[kXcds];
     std::vector<unsigned int> u_first[kXcds];
-    double load[kXcds] = {0};
+    std::vector<std::vector<int>> band[GDRR_MAX_VOLUMES];    // [volume][tile row] -> jobs in order
     for (size_t k = 0; k < nj; ++k) {
-        const gdrr_volume& V = vols[jobs[k].volume];
-        const double span = std::sqrt((double)V.nx * V.dx_mm * V.nx * V.dx_mm + (double)V.ny * V.dy_mm * V.ny * V.dy_mm +
-                                      (double)V.nz * V.dz_mm * V.nz * V.dz_mm) / rp.dl[jobs[k].volume];
-        const unsigned long long tk = rt_tiles(jobs[k].geom);
-        for (unsigned long long f = 0; f < tk; f += run) {
-            const int x = (int)(std::min_element(load, load + kXcds) - load);
-            u_job[x].push_back((int)k);
-            u_first[x].push_back((unsigned int)f);
-            load[x] += (double)std::min(run, tk - f) * (span + 64.0);
-        }
+        std::vector<std::vector<int>>& b = band[jobs[k].volume];
+        const size_t rows = (size_t)((jobs[k].geom.nv + 15) / 16);
+        if (b.size() < rows) b.resize(rows);
+        for (size_t r = 0; r < rows; ++r) b[r].push_back((int)k);
     }
+    int deal = 0;
+    for (int v = 0; v < n_vols; ++v)
+        for (size_t r = 0; r < band[v].size(); ++r)
+            for (const int k : band[v][r]) {
+                const unsigned long long tu = (unsigned long long)((jobs[k].geom.nu + 15) / 16);
+                for (unsigned long long c = 0; c < tu; c += run) {
+                    u_job[deal].push_back(k);
+                    u_first[deal].push_back((unsigned int)(r * tu + c));
+                    deal = (deal + 1) % kXcds;
+                }
+            }
     std::vector<int> ujob;
     std::vector<unsigned int> ufirst, upref;
     unsigned int most = 0;
@@ -902,7 +912,8 @@ int run_primary(const gdrr_volume* vols, int n_vols, const gdrr_physics* phys, c
             ujob.push_back(k);
             ufirst.push_back(u_first[x][i]);
             upref.push_back(acc);
-            acc += (unsigned int)std::min<unsigned long long>(run, rt_tiles(jobs[k].geom) - u_first[x][i]);
+            const unsigned long long tu = (unsigned long long)((jobs[k].geom.nu + 15) / 16);
+            acc += (unsigned int)std::min<unsigned long long>(run, tu - u_first[x][i] % tu);
         }
         rp.xcd_tiles[x] = acc;
         most = std::max(most, acc);

@@ -41,7 +41,8 @@ struct RtParams {
     RtSource src[GDRR_MAX_SOURCES];
     float dl[GDRR_MAX_VOLUMES];   // interval length per volume, mm
     const DJob* jobs;
-    // Work units (runs of consecutive tiles of one job), listed XCD by XCD:
+    // Work units (runs of consecutive tiles within one tile row of one job),
+    // listed XCD by XCD:
     // XCD x owns units [xcd_start[x], xcd_start[x+1]); unit_pref is the
     // running tile count within its XCD's list.
     const int* unit_job;
@@ -68,9 +69,10 @@ __device__ __forceinline__ void rt_slab(float s, float d, float lo, float hi, fl
 __global__ __launch_bounds__(kRtBlock) void raytrace_kernel(RtParams P) {
     extern __shared__ float rt_lds[];          // [n_mat][kRtBlock]: the lanes' L_m
     // Workgroups are dealt to the XCDs in turn; each XCD walks its own list of
-    // units in order, so the tiles in flight on an XCD are those of one or two
-    // projections: their rays advance together through the phantom and share
-    // that XCD's L2.  The host balances the lists by estimated work.
+    // units in order.  The host orders the units by phantom, then tile row,
+    // then job, and deals them round the XCDs, so at any time the whole chip
+    // traces one band of detector rows -- one slab of the phantom -- over all
+    // that phantom's projections.
     const unsigned int x = blockIdx.x % kXcds, slot = blockIdx.x / kXcds;
     if (slot >= P.xcd_tiles[x]) return;         // whole workgroup; no barrier in this kernel
     int lo = (int)P.xcd_start[x], hi = (int)P.xcd_start[x + 1] - 1;
