@@ -42,19 +42,29 @@ METRIC = "photon histories/sec (fwd, batched angles) + adjoint histories/sec, 1Ã
 HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # 32-bit VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 
-# Work model of one history (algorithmic units; see the design notes):
-# 32-bit VALU issue slots (quarter-rate integer multiplies and transcendentals
-# count 4) and bytes the algorithm must gather.
-SLOTS_PHILOX = 10 * (4 * 4 + 2)          # 2 mul_hi + 2 mul_lo (quarter rate) + 2 xor3 per round
+# Work model of one history (algorithmic units; see the design notes), in
+# 32-bit VALU issue slots at the full rate, with the costs of the other
+# instruction kinds as measured on gfx950 by paper_1204_6367_amd/calib/issue_rate
+# (against a chain of float32 FMAs): 32x32-bit integer products (v_mul_hi_u32,
+# v_mad_u64_u32) issue at about the full rate, transcendentals (log, exp, rcp,
+# rsq, sqrt, sin, cos) at about half of it.
+SLOTS_IMUL = 1
+SLOTS_TRANS = 2
+SLOTS_PHILOX = 10 * (2 * SLOTS_IMUL + 4)       # per round: two 32x32->64 products, four xors
+T = SLOTS_TRANS
 # free flights come in pairs sharing one Philox block (counted per history below)
-SLOTS_FLIGHT_IN = 3 + 7 + 4 + 24 + 7                   # uniforms, -ln u, move, cell-record trilinear, lookup+ladder
-SLOTS_FLIGHT_OUT = 3 + 7 + 30                          # the escaping flight: detector intersection
-SLOTS_TRY = SLOTS_PHILOX + 9 + 30                      # one angular-sampler try
-SLOTS_COLLISION = 6 + 55 + 40 + 10                     # type select, rotation, box exit, energy cache
-SLOTS_SOURCE = 2 * SLOTS_PHILOX + 40 + 34 + 45         # two blocks, CDFs (fp64), aim point, box entry
-# local majorants: every cube a flight visits (its first, and one per face crossed): record
-# address and load, bound from the material mask (~1.5 materials), exit-face distances, spend
-# or stop, advance, step the cube index
+SLOTS_FLIGHT_IN = 3 + (3 + T) + 4 + 24 + 7             # uniforms, -ln u, move, cell-record trilinear, lookup+ladder
+SLOTS_FLIGHT_OUT = 3 + (3 + T) + (28 + T)              # the escaping flight: detector intersection
+SLOTS_TRY = SLOTS_PHILOX + 9 + (24 + 3 * T)            # one angular-sampler try (KN: sqrt or none, two rcp)
+SLOTS_ROTATION = 45 + 5 * T                            # sqrt, sin, cos, two rsq
+SLOTS_BOX_EXIT = 34 + 3 * T                            # single majorant only: three rcp
+SLOTS_COLLISION = 6 + SLOTS_ROTATION + 10 + (10 + 5 * T)   # type select, rotation, energy cache, sampler constants
+SLOTS_SOURCE = 2 * SLOTS_PHILOX + 40 + (32 + T) + (33 + 3 * T)   # two blocks, CDFs (fp64), aim point, box entry
+# local majorants: every flight first sets up its walk (cube coordinates, three
+# reciprocals, steps, exit-face distances), then visits cubes (its first, and
+# one per face crossed): record address and load, bound from the material mask
+# (~1.5 materials), spend or stop, advance, step the cube index
+SLOTS_WALK = 72 + 3 * T
 SLOTS_CUBE = 50
 BYTES_CUBE = 8
 BYTES_FLIGHT_IN = 8 * 4 + 1                            # eight density corners + the containing voxel's material
@@ -78,8 +88,10 @@ def work_per_history(stats, n):
     pairs = 0.5 * (flights + real)                     # a real collision ends a pair early
     crossings = stats.get("crossings", 0.0) / h
     cubes = (crossings + flights) if crossings > 0 else 0.0
+    local = crossings > 0
     slots = (pairs * SLOTS_PHILOX + inbox * SLOTS_FLIGHT_IN + escapes * SLOTS_FLIGHT_OUT + tries * SLOTS_TRY
-             + real * 6 + scatter_events * (SLOTS_COLLISION - 6) + SLOTS_SOURCE + cubes * SLOTS_CUBE)
+             + real * 6 + scatter_events * (SLOTS_COLLISION - 6 + (0 if local else SLOTS_BOX_EXIT))
+             + SLOTS_SOURCE + (flights * SLOTS_WALK + cubes * SLOTS_CUBE if local else 0.0))
     nbytes = inbox * BYTES_FLIGHT_IN + BYTES_SOURCE + scored * BYTES_SCORE + cubes * BYTES_CUBE
     return dict(slots=slots, bytes=nbytes, flights=flights, inbox_flights=inbox, real=real, tries=tries,
                 cube_visits=cubes)
@@ -375,7 +387,7 @@ def raytrace_leg(wl, api, torch, steps, cpu):
 # Scatter denoising (Eq. 5) and noise assembly (Sec. 2.6) of the step's tallies
 # ---------------------------------------------------------------------------
 DENOISE_ITERS = 256
-SLOTS_DN_SWEEP = 13            # per pixel and sweep: 3 adds, reciprocal (4), mul, sub, 2 FMA, mul, max
+SLOTS_DN_SWEEP = 9 + SLOTS_TRANS   # per pixel and sweep: 3 adds, reciprocal, mul, sub, 2 FMA, mul, max
 BYTES_NOISE = 6 * 8            # Phat, P, Shat, S read; noise, image written
 
 

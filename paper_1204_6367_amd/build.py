@@ -21,6 +21,11 @@ HIPCC_FLAGS = [
 ]
 
 
+# the issue-rate calibration program behind the benchmark's work model (not part of the library)
+CALIB_SRC = os.path.join(HERE, "calib", "issue_rate.hip")
+CALIB_EXE = os.path.join(HERE, "calib", "issue_rate")
+
+
 def build(force: bool = True, verbose: bool = False) -> str:
     if not force and os.path.exists(LIB) and \
             os.path.getmtime(LIB) >= max(os.path.getmtime(d) for d in DEPS):
@@ -34,7 +39,18 @@ def build(force: bool = True, verbose: bool = False) -> str:
     return LIB
 
 
+def build_calibration(verbose: bool = False) -> str:
+    flags = [f for f in HIPCC_FLAGS if f not in ("-shared", "-fPIC", "-munsafe-fp-atomics")]
+    cmd = ["hipcc", *flags, CALIB_SRC, "-o", CALIB_EXE + ".tmp"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(CALIB_EXE + ".tmp", CALIB_EXE)
+    return CALIB_EXE
+
+
 if __name__ == "__main__":
     build(verbose=True)
+    build_calibration(verbose=True)
     print(LIB)
     sys.exit(0)

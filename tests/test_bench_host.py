@@ -56,12 +56,23 @@ def test_work_model_composition():
     assert w["inbox_flights"] == pytest.approx(7.0 - 0.4)
     assert w["cube_visits"] == pytest.approx(11.0 + 7.0)
     pairs = 0.5 * (7.0 + 2.5)
-    slots = (pairs * bench.SLOTS_PHILOX + 6.6 * bench.SLOTS_FLIGHT_IN + 0.4 * bench.SLOTS_FLIGHT_OUT
-             + 2.9 * bench.SLOTS_TRY + 2.5 * 6 + 2.1 * (bench.SLOTS_COLLISION - 6) + bench.SLOTS_SOURCE
-             + 18.0 * bench.SLOTS_CUBE)
-    assert w["slots"] == pytest.approx(slots)
+    base = (pairs * bench.SLOTS_PHILOX + 6.6 * bench.SLOTS_FLIGHT_IN + 0.4 * bench.SLOTS_FLIGHT_OUT
+            + 2.9 * bench.SLOTS_TRY + 2.5 * 6 + 2.1 * (bench.SLOTS_COLLISION - 6) + bench.SLOTS_SOURCE)
+    # local majorants: a walk set-up per flight and the cube visits, no box exit after a collision
+    assert w["slots"] == pytest.approx(base + 7.0 * bench.SLOTS_WALK + 18.0 * bench.SLOTS_CUBE)
     nbytes = 6.6 * bench.BYTES_FLIGHT_IN + bench.BYTES_SOURCE + 0.005 * bench.BYTES_SCORE + 18.0 * bench.BYTES_CUBE
     assert w["bytes"] == pytest.approx(nbytes)
-    # without cube crossings (the single majorant) no cube visits are counted
+    # the single majorant: no cube walk, and every scattering recomputes the distance to the box
     stats["crossings"] = 0.0
-    assert bench.work_per_history(stats, n)["cube_visits"] == 0.0
+    w0 = bench.work_per_history(stats, n)
+    assert w0["cube_visits"] == 0.0
+    assert w0["slots"] == pytest.approx(base + 2.1 * bench.SLOTS_BOX_EXIT)
+
+
+def test_work_model_prices_measured_issue_costs():
+    """A Philox4x32-10 block is ten rounds of two 32x32->64 products and four
+    xors; integer products are priced at the full rate and transcendentals at
+    twice it, the costs the calibration program measures on gfx950."""
+    assert bench.SLOTS_IMUL == 1 and bench.SLOTS_TRANS == 2
+    assert bench.SLOTS_PHILOX == 60
+    assert bench.SLOTS_DN_SWEEP == 11
