@@ -43,29 +43,38 @@ HBM_PEAK_GBS = 8000.0
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12      # 32-bit VALU lane-ops/s: 256 CUs x 64 lanes x 2.4 GHz
 
 # Work model of one history (algorithmic units; see the design notes), in
-# 32-bit VALU issue slots at the full rate, with the costs of the other
-# instruction kinds as measured on gfx950 by paper_1204_6367_amd/calib/issue_rate
-# (against a chain of float32 FMAs): 32x32-bit integer products (v_mul_hi_u32,
-# v_mad_u64_u32) issue at about the full rate, transcendentals (log, exp, rcp,
-# rsq, sqrt, sin, cos) at about half of it.
-SLOTS_IMUL = 1
-SLOTS_TRANS = 2
-SLOTS_PHILOX = 10 * (2 * SLOTS_IMUL + 4)       # per round: two 32x32->64 products, four xors
-T = SLOTS_TRANS
+# slots of a full-rate 32-bit integer VALU lane operation (the 39.3 T/s peak).
+# Costs of the instruction classes as measured on gfx950 by
+# paper_1204_6367_amd/calib/issue_rate (relative to a chain of float32 FMAs):
+# integer operations, 32x32-bit products (v_mul_hi_u32, v_mad_u64_u32)
+# included, 1 slot; float32 add, mul, fma, min, compare with vector operands
+# 0.6 (they issue at about twice the integer rate; 1.05 when an operand is a
+# scalar register); transcendentals (log, exp, rcp, rsq, sqrt, sin, cos) 2.3.
+SLOTS_INT = 1.0
+SLOTS_F32 = 0.6
+SLOTS_TRANS = 2.3
+
+
+def slots(i=0, f=0, t=0):
+    """Slots of i integer, f float32 and t transcendental operations."""
+    return i * SLOTS_INT + f * SLOTS_F32 + t * SLOTS_TRANS
+
+
+SLOTS_PHILOX = slots(i=10 * (2 + 4))                  # per round: two 32x32->64 products, four xors
 # free flights come in pairs sharing one Philox block (counted per history below)
-SLOTS_FLIGHT_IN = 3 + (3 + T) + 4 + 24 + 7             # uniforms, -ln u, move, cell-record trilinear, lookup+ladder
-SLOTS_FLIGHT_OUT = 3 + (3 + T) + (28 + T)              # the escaping flight: detector intersection
-SLOTS_TRY = SLOTS_PHILOX + 9 + (24 + 3 * T)            # one angular-sampler try (KN: sqrt or none, two rcp)
-SLOTS_ROTATION = 45 + 5 * T                            # sqrt, sin, cos, two rsq
-SLOTS_BOX_EXIT = 34 + 3 * T                            # single majorant only: three rcp
-SLOTS_COLLISION = 6 + SLOTS_ROTATION + 10 + (10 + 5 * T)   # type select, rotation, energy cache, sampler constants
-SLOTS_SOURCE = 2 * SLOTS_PHILOX + 40 + (32 + T) + (33 + 3 * T)   # two blocks, CDFs (fp64), aim point, box entry
+SLOTS_FLIGHT_IN = slots(i=10, f=31, t=1)              # uniforms, -ln u, move, cell-record trilinear, lookup+ladder
+SLOTS_FLIGHT_OUT = slots(i=7, f=27, t=2)              # the escaping flight: -ln u, detector intersection
+SLOTS_TRY = SLOTS_PHILOX + slots(i=8, f=25, t=3)      # one angular-sampler try (KN: sqrt or none, two rcp)
+SLOTS_SELECT = slots(i=2, f=4)                        # interaction type, at every real collision
+SLOTS_COLLISION = SLOTS_SELECT + slots(i=11, f=54, t=10)   # + sampler constants, rotation, energy cache
+SLOTS_BOX_EXIT = slots(i=6, f=28, t=3)                # single majorant only: distance to the box
+SLOTS_SOURCE = 2 * SLOTS_PHILOX + slots(i=50, f=55, t=4)   # two blocks, CDFs (fp64), aim point, box entry
 # local majorants: every flight first sets up its walk (cube coordinates, three
 # reciprocals, steps, exit-face distances), then visits cubes (its first, and
 # one per face crossed): record address and load, bound from the material mask
 # (~1.5 materials), spend or stop, advance, step the cube index
-SLOTS_WALK = 72 + 3 * T
-SLOTS_CUBE = 50
+SLOTS_WALK = slots(i=30, f=42, t=3)
+SLOTS_CUBE = slots(i=25, f=25)
 BYTES_CUBE = 8
 BYTES_FLIGHT_IN = 8 * 4 + 1                            # eight density corners + the containing voxel's material
 BYTES_SOURCE = 2 * (2 * 8 + 4) + 4                     # CDF + guide reads for energy and pixel, energy
@@ -90,7 +99,7 @@ def work_per_history(stats, n):
     cubes = (crossings + flights) if crossings > 0 else 0.0
     local = crossings > 0
     slots = (pairs * SLOTS_PHILOX + inbox * SLOTS_FLIGHT_IN + escapes * SLOTS_FLIGHT_OUT + tries * SLOTS_TRY
-             + real * 6 + scatter_events * (SLOTS_COLLISION - 6 + (0 if local else SLOTS_BOX_EXIT))
+             + real * SLOTS_SELECT + scatter_events * (SLOTS_COLLISION - SLOTS_SELECT + (0 if local else SLOTS_BOX_EXIT))
              + SLOTS_SOURCE + (flights * SLOTS_WALK + cubes * SLOTS_CUBE if local else 0.0))
     nbytes = inbox * BYTES_FLIGHT_IN + BYTES_SOURCE + scored * BYTES_SCORE + cubes * BYTES_CUBE
     return dict(slots=slots, bytes=nbytes, flights=flights, inbox_flights=inbox, real=real, tries=tries,
@@ -296,7 +305,7 @@ def build_workload(name, api, W, torch):
 # ---------------------------------------------------------------------------
 # per interval: position (3 FMA), lattice coordinates (6), floor/convert/clamp
 # (12), fractions (6), cell address (4), trilinear (14), accumulate (2), loop (5)
-SLOTS_RT_INTERVAL = 52
+SLOTS_RT_INTERVAL = slots(i=13, f=39)
 # Compulsory memory traffic per image: the volume's density and material
 # (5 bytes per voxel, read once; an upper bound, as the cone may miss part of
 # the volume) and the float64 image.  Rays of one tile and successive intervals
@@ -387,7 +396,7 @@ def raytrace_leg(wl, api, torch, steps, cpu):
 # Scatter denoising (Eq. 5) and noise assembly (Sec. 2.6) of the step's tallies
 # ---------------------------------------------------------------------------
 DENOISE_ITERS = 256
-SLOTS_DN_SWEEP = 9 + SLOTS_TRANS   # per pixel and sweep: 3 adds, reciprocal, mul, sub, 2 FMA, mul, max
+SLOTS_DN_SWEEP = slots(f=9, t=1)   # per pixel and sweep: 3 adds, reciprocal, mul, sub, 2 FMA, mul, max
 BYTES_NOISE = 6 * 8            # Phat, P, Shat, S read; noise, image written
 
 

@@ -60,6 +60,9 @@ const float kInitScale = 1e-7f;
 
 RATE_KERNEL_F(k_fma, float, F_INIT, __builtin_fmaf(a[c], 0.999f, s))
 RATE_KERNEL_F(k_add, float, F_INIT, a[c] + s)
+// the same with a per-lane (vector register) operand instead of the scalar s
+RATE_KERNEL_F(k_addv, float, F_INIT, a[c] + (s + (float)threadIdx.x * 1e-30f))
+RATE_KERNEL_F(k_fmas, float, F_INIT, __builtin_fmaf(a[c], s, 0.25f))
 RATE_KERNEL_F(k_mul, float, F_INIT, a[c] * s)
 RATE_KERNEL_F(k_min, float, F_INIT, __builtin_fminf(a[c] + s, 3.0f))
 RATE_KERNEL_F(k_floor, float, F_INIT, __builtin_floorf(a[c]) + s)
@@ -77,6 +80,36 @@ RATE_KERNEL_U(k_cvt, threadIdx.x * kChains + c + k, (uint32_t)((float)a[c] * 0.7
 RATE_KERNEL_U(k_mulhi, threadIdx.x * kChains + c + k, __umulhi(a[c], 0xD2511F53u) ^ k)
 RATE_KERNEL_U(k_mad64, threadIdx.x * kChains + c + k,
               (uint32_t)(((uint64_t)a[c] * 0xD2511F53ull) >> 32) ^ (uint32_t)((uint64_t)a[c] * 0xD2511F53ull))
+
+
+// integer chains with per-lane (vector register) operands read from memory
+__global__ __launch_bounds__(kBlock) void k_xadv(uint32_t* out, float s) {
+    uint32_t a[kChains];
+    const uint32_t kv = out[blockIdx.x * kBlock + threadIdx.x] | 1u;
+    const uint32_t kw = kv * 3u;
+    _Pragma("unroll") for (int c = 0; c < kChains; ++c) a[c] = threadIdx.x * kChains + c + __float_as_uint(s);
+    for (int i = 0; i < kIters; ++i) {
+        _Pragma("unroll") for (int c = 0; c < kChains; ++c) a[c] = (a[c] ^ kv) + kw;   // one v_xad_u32
+    }
+    uint32_t r = 0;
+    _Pragma("unroll") for (int c = 0; c < kChains; ++c) r ^= a[c];
+    out[blockIdx.x * kBlock + threadIdx.x] = r;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mad64v(uint32_t* out, float s) {
+    uint32_t a[kChains];
+    const uint32_t kv = out[blockIdx.x * kBlock + threadIdx.x] | 1u;
+    _Pragma("unroll") for (int c = 0; c < kChains; ++c) a[c] = threadIdx.x * kChains + c + __float_as_uint(s);
+    for (int i = 0; i < kIters; ++i) {
+        _Pragma("unroll") for (int c = 0; c < kChains; ++c) {
+            const uint64_t p = (uint64_t)a[c] * kv;
+            a[c] = (uint32_t)(p >> 32) ^ (uint32_t)p;
+        }
+    }
+    uint32_t r = 0;
+    _Pragma("unroll") for (int c = 0; c < kChains; ++c) r ^= a[c];
+    out[blockIdx.x * kBlock + threadIdx.x] = r;
+}
 
 struct Kind {
     const char* name;
@@ -96,17 +129,21 @@ int main() {
     CHECK(hipEventCreate(&e0));
     CHECK(hipEventCreate(&e1));
     const Kind kinds[] = {
-        {"fma_f32", k_fma, "v_fma_f32 (the unit)"},
-        {"add_f32", k_add, "v_add_f32"},
-        {"mul_f32", k_mul, "v_mul_f32"},
+        {"fma_f32", k_fma, "v_fma_f32 (vector operands and a literal; the unit)"},
+        {"add_f32", k_add, "v_add_f32 (scalar-register operand)"},
+        {"add_f32_v", k_addv, "v_add_f32 (vector operands)"},
+        {"fma_f32_s", k_fmas, "v_fma_f32 (scalar-register operand)"},
+        {"mul_f32", k_mul, "v_mul_f32 (scalar-register operand)"},
         {"min_f32", k_min, "v_min_f32 + v_add_f32"},
         {"floor_f32", k_floor, "v_floor_f32 + v_add_f32"},
         {"cmp_cnd_f32", k_sel, "v_cmp_f32 + v_cndmask_b32 + v_mul_f32 + v_add_f32"},
         {"xor_add_u32", k_xor, "v_xor_b32 + v_add_u32"},
         {"mul_lo_u32", k_mullo, "v_mul_lo_u32 + v_xor_b32"},
         {"cvt_f32_u32", k_cvt, "v_cvt_f32_u32 + v_mul_f32 + v_cvt_u32_f32"},
+        {"xad_u32_v", k_xadv, "v_xad_u32 (vector operands)"},
         {"mul_hi_u32", k_mulhi, "v_mul_hi_u32 + v_xor_b32"},
         {"mad_u64_u32", k_mad64, "v_mad_u64_u32 (32x32->64 product) + v_xor_b32"},
+        {"mad_u64_u32_v", k_mad64v, "v_mad_u64_u32 (vector multiplier) + v_xor_b32"},
         {"log_f32", k_log, "v_log_f32 + v_add_f32"},
         {"exp_f32", k_exp, "v_exp_f32 + v_add_f32"},
         {"rcp_f32", k_rcp, "v_rcp_f32 + v_add_f32"},

@@ -57,7 +57,8 @@ def test_work_model_composition():
     assert w["cube_visits"] == pytest.approx(11.0 + 7.0)
     pairs = 0.5 * (7.0 + 2.5)
     base = (pairs * bench.SLOTS_PHILOX + 6.6 * bench.SLOTS_FLIGHT_IN + 0.4 * bench.SLOTS_FLIGHT_OUT
-            + 2.9 * bench.SLOTS_TRY + 2.5 * 6 + 2.1 * (bench.SLOTS_COLLISION - 6) + bench.SLOTS_SOURCE)
+            + 2.9 * bench.SLOTS_TRY + 2.5 * bench.SLOTS_SELECT + 2.1 * (bench.SLOTS_COLLISION - bench.SLOTS_SELECT)
+            + bench.SLOTS_SOURCE)
     # local majorants: a walk set-up per flight and the cube visits, no box exit after a collision
     assert w["slots"] == pytest.approx(base + 7.0 * bench.SLOTS_WALK + 18.0 * bench.SLOTS_CUBE)
     nbytes = 6.6 * bench.BYTES_FLIGHT_IN + bench.BYTES_SOURCE + 0.005 * bench.BYTES_SCORE + 18.0 * bench.BYTES_CUBE
@@ -70,9 +71,13 @@ def test_work_model_composition():
 
 
 def test_work_model_prices_measured_issue_costs():
-    """A Philox4x32-10 block is ten rounds of two 32x32->64 products and four
-    xors; integer products are priced at the full rate and transcendentals at
-    twice it, the costs the calibration program measures on gfx950."""
-    assert bench.SLOTS_IMUL == 1 and bench.SLOTS_TRANS == 2
+    """Instruction classes at the costs the calibration program measures on
+    gfx950, in slots of a full-rate integer operation: integer operations and
+    32x32-bit products 1, float32 arithmetic with vector operands 0.6,
+    transcendentals 2.3.  A Philox4x32-10 block is ten rounds of two products
+    and four xors."""
+    assert (bench.SLOTS_INT, bench.SLOTS_F32, bench.SLOTS_TRANS) == (1.0, 0.6, 2.3)
+    assert bench.slots(i=3, f=5, t=2) == pytest.approx(3 + 3.0 + 4.6)
     assert bench.SLOTS_PHILOX == 60
-    assert bench.SLOTS_DN_SWEEP == 11
+    assert bench.SLOTS_DN_SWEEP == pytest.approx(9 * 0.6 + 2.3)
+    assert bench.SLOTS_RT_INTERVAL == pytest.approx(13 + 39 * 0.6)

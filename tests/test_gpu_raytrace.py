@@ -136,6 +136,39 @@ def test_batch_equals_single_calls(gpu):
         assert torch.allclose(x, 2.0 * y, rtol=1e-15, atol=0)
 
 
+def test_batch_of_mixed_detector_sizes(gpu):
+    """Work units are pieces of tile rows dealt in row-band order across the
+    jobs of each phantom: jobs of different detector sizes (ragged tile rows
+    and columns, a detector narrower than one tile, one wider than a unit) on
+    two phantoms, in a small batch (units shorter than a row) and a large one
+    (whole rows), each image bitwise equal to its single call."""
+    import torch
+    a = mixed_problem(seed=11, nu=40, nv=27)
+    b = mixed_problem(seed=12, shape=(16, 18, 22), spacing=(4.0, 3.0, 3.5), nu=40, nv=27)
+    va, pa, _ = gpu.upload(a)
+    vb, _, _ = gpu.upload(b)
+    rng = np.random.default_rng(13)
+    sizes = [(40, 27), (17, 50), (100, 9), (5, 5)]
+    e = np.linspace(20.0, 118.3, 24).astype(np.float32)
+    srcs = [gpu.DeviceSource(e, rng.uniform(0.2, 1.0, 24).astype(np.float32),
+                             rng.uniform(0.5, 1.5, (nv, nu)).astype(np.float32)) for nu, nv in sizes]
+    vols = [va, vb]
+
+    def job(k, n_sizes):
+        nu, nv = sizes[k % n_sizes]
+        g = a.geom.replace(phi_rad=0.37 * k, nu=nu, nv=nv)
+        return gpu.JobSpec(g, 0, k, volume=(k // n_sizes) % 2, source=k % n_sizes)
+
+    for label, jobs in (("small batch", [job(k, 4) for k in range(12)]),
+                        ("large batch", [job(k, 1) for k in range(80)])):
+        log("raytrace", label, len(jobs), "jobs")
+        imgs = gpu.Batch(vols, pa, srcs, jobs).primary(interp=True)
+        for j, img in zip(jobs, imgs):
+            assert img.shape == (j.geom.nv, j.geom.nu)
+            one = gpu.primary(vols[j.volume], pa, srcs[j.source], j.geom, interp=True)
+            assert torch.equal(img, one), (label, j.job_id)
+
+
 def test_empty_phantom_gives_the_unattenuated_signal(gpu):
     prob = mixed_problem(seed=8)
     prob.phantom.density[:] = 0.0
