@@ -122,6 +122,44 @@ def kernel_sources_sha() -> str:
 
 
 TRAFFIC_PATH = None
+GATHER_PATH = os.path.join(ROOT, "profiles", "gather_rates_gfx950.json")
+GATHER_RECORD = 32                 # bytes of one cell record: the gather of a free flight inside a phantom
+
+
+def gather_peak(rates, ws_bytes):
+    """Measured random-gather rate (GB/s) of records of one size for a
+    working set: the rate at the smallest measured working set that holds it
+    (the largest measured one beyond)."""
+    pts = sorted(rates)
+    for ws, gbs in pts:
+        if ws >= ws_bytes:
+            return gbs
+    return pts[-1][1]
+
+
+def gather_roofline(path, batch, inbox_flights, histories_per_s):
+    """The transport's cell-record gathers against the random-gather rate
+    measured at each phantom's working set (its cell records), the rates
+    combined harmonically with the photons each phantom gets; None without
+    the measurement."""
+    try:
+        rates = json.load(open(path))["rates"][str(GATHER_RECORD)]
+    except (OSError, ValueError, KeyError):
+        return None
+    photons = {}
+    for j in batch.jobs:
+        photons[j.volume] = photons.get(j.volume, 0) + j.n_photons
+    total = float(sum(photons.values()))
+    inv, sets = 0.0, []
+    for v, n in sorted(photons.items()):
+        nz, ny, nx = batch.vols[v].density.shape
+        ws = (nx + 1) * (ny + 1) * (nz + 1) * GATHER_RECORD
+        sets.append(round(ws / 1e9, 3))
+        inv += n / total / gather_peak(rates, ws)
+    peak = 1.0 / inv
+    ach = inbox_flights * GATHER_RECORD * histories_per_s / 1e9
+    return dict(bound="gather", achieved=round(ach, 1), peak=round(peak, 1), unit="GB/s", frac=round(ach / peak, 4),
+                record_bytes=GATHER_RECORD, working_sets_gb=sets)
 
 
 def measured_traffic(path, workload, kernel=None):
@@ -608,6 +646,9 @@ def main():
         roof = alu if alu["frac"] >= hbm["frac"] else hbm
         extra["roofline_other"] = hbm if roof is alu else alu
         extra["work_per_history"] = {k: round(v, 3) for k, v in w.items()}
+        rg = gather_roofline(GATHER_PATH, wl["batch"], w["inbox_flights"], wl["fwd"] / (fwd_ms * 1e-3))
+        if rg is not None:
+            extra["roofline_gather"] = rg
         cores = cpu["threads"]
         if wl["adj"]:
             cval = hist_step / (wl["fwd"] / cpu["fwd_rate"] + wl["adj"] / cpu["adj_rate"])

@@ -21,9 +21,9 @@ HIPCC_FLAGS = [
 ]
 
 
-# the issue-rate calibration program behind the benchmark's work model (not part of the library)
-CALIB_SRC = os.path.join(HERE, "calib", "issue_rate.hip")
-CALIB_EXE = os.path.join(HERE, "calib", "issue_rate")
+# calibration programs behind the benchmark's rooflines (not part of the library): instruction
+# issue costs and random-gather throughput
+CALIB = ["issue_rate", "gather_rate"]      # paper_1204_6367_amd/calib/<name>.hip -> <name>
 
 
 def build(force: bool = True, verbose: bool = False) -> str:
@@ -39,14 +39,18 @@ def build(force: bool = True, verbose: bool = False) -> str:
     return LIB
 
 
-def build_calibration(verbose: bool = False) -> str:
+def build_calibration(verbose: bool = False) -> list:
     flags = [f for f in HIPCC_FLAGS if f not in ("-shared", "-fPIC", "-munsafe-fp-atomics")]
-    cmd = ["hipcc", *flags, CALIB_SRC, "-o", CALIB_EXE + ".tmp"]
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    subprocess.run(cmd, check=True)
-    os.replace(CALIB_EXE + ".tmp", CALIB_EXE)
-    return CALIB_EXE
+    built = []
+    for name in CALIB:
+        exe = os.path.join(HERE, "calib", name)
+        cmd = ["hipcc", *flags, os.path.join(HERE, "calib", name + ".hip"), "-o", exe + ".tmp"]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+        os.replace(exe + ".tmp", exe)
+        built.append(exe)
+    return built
 
 
 if __name__ == "__main__":

@@ -81,3 +81,27 @@ def test_work_model_prices_measured_issue_costs():
     assert bench.SLOTS_PHILOX == 60
     assert bench.SLOTS_DN_SWEEP == pytest.approx(9 * 0.6 + 2.3)
     assert bench.SLOTS_RT_INTERVAL == pytest.approx(13 + 39 * 0.6)
+
+
+def test_gather_roofline_from_measured_rates(tmp_path):
+    """The transport's gather roofline: one 32-byte cell record per free flight
+    inside a phantom, against the random-gather rate measured at the smallest
+    working set that holds each phantom's cell records, the rates combined
+    harmonically by photons."""
+    import types
+    rates = {"32": [[1 << 21, 8000.0], [1 << 27, 2000.0], [1 << 32, 1500.0]]}
+    p = tmp_path / "g.json"
+    p.write_text(json.dumps({"rates": rates}))
+    assert bench.gather_peak(rates["32"], 1 << 20) == 8000.0
+    assert bench.gather_peak(rates["32"], (1 << 21) + 1) == 2000.0
+    assert bench.gather_peak(rates["32"], 1 << 40) == 1500.0
+    vol = lambda shape: types.SimpleNamespace(density=types.SimpleNamespace(shape=shape))
+    job = lambda v, n: types.SimpleNamespace(volume=v, n_photons=n)
+    # cell records: 9x9x9 x 32 B (23 KB, within 2 MiB) and 257^3 x 32 B (543 MB, beyond 128 MiB)
+    b = types.SimpleNamespace(vols=[vol((8, 8, 8)), vol((256, 256, 256))], jobs=[job(0, 300), job(1, 100)])
+    r = bench.gather_roofline(str(p), b, inbox_flights=5.0, histories_per_s=1e9)
+    peak = 1.0 / (0.75 / 8000.0 + 0.25 / 1500.0)
+    assert r["peak"] == pytest.approx(peak, abs=0.1)
+    assert r["achieved"] == pytest.approx(5.0 * 32 * 1e9 / 1e9)
+    assert r["frac"] == pytest.approx(160.0 / peak, abs=1e-4)
+    assert bench.gather_roofline(str(tmp_path / "missing.json"), b, 5.0, 1e9) is None
