@@ -341,9 +341,10 @@ def build_workload(name, api, W, torch):
 # ---------------------------------------------------------------------------
 # Ray-tracing primary (Eq. 1) over the same jobs: measured beside the step
 # ---------------------------------------------------------------------------
-# per interval: position (3 FMA), lattice coordinates (6), floor/convert/clamp
-# (12), fractions (6), cell address (4), trilinear (14), accumulate (2), loop (5)
-SLOTS_RT_INTERVAL = slots(i=13, f=39)
+# per interval: bounds and midpoint (5), lattice coordinates (3 FMA),
+# floor/convert/clamp (12), fractions (6), cell address (4), trilinear (14),
+# accumulate (2), loop (2)
+SLOTS_RT_INTERVAL = slots(i=13, f=33)
 # Compulsory memory traffic per image: the volume's density and material
 # (5 bytes per voxel, read once; an upper bound, as the cone may miss part of
 # the volume) and the float64 image.  Rays of one tile and successive intervals

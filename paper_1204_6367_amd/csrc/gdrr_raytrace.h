@@ -111,7 +111,11 @@ __global__ __launch_bounds__(kRtBlock) void raytrace_kernel(RtParams P) {
         const float* __restrict__ dens = V.density;
         const uint8_t* __restrict__ mats = V.material;
         const int nx = V.nx, ny = V.ny, nz = V.nz, nxy = V.nxy, cx = V.cx, cxy = V.cxy;
-        const float lox = V.lox, loy = V.loy, loz = V.loz, idx = V.idx, idy = V.idy, idz = V.idz;
+        // the ray in lattice coordinates (voxel units, cell corners at integers):
+        // g(t) = g0 + t gd per axis, one FMA per axis and interval
+        const float g0x = (J.Sx - V.lox) * V.idx - 0.5f, g0y = (J.Sy - V.loy) * V.idy - 0.5f,
+                    g0z = (J.Sz - V.loz) * V.idz - 0.5f;
+        const float gdx = dx * V.idx, gdy = dy * V.idy, gdz = dz * V.idz;
         const int n_mat = P.n_mat;
         const bool interp = P.interp != 0;
         float acc = 0.0f;
@@ -123,9 +127,7 @@ __global__ __launch_bounds__(kRtBlock) void raytrace_kernel(RtParams P) {
             const float a = fmaxf((float)j * dl, t0), e = fminf((float)(j + 1) * dl, t1);
             h = e - a;
             const float t = 0.5f * (a + e);
-            const float px = J.Sx + t * dx, py = J.Sy + t * dy, pz = J.Sz + t * dz;
-            const float gx = (px - lox) * idx - 0.5f, gy = (py - loy) * idy - 0.5f,
-                        gz = (pz - loz) * idz - 0.5f;
+            const float gx = g0x + t * gdx, gy = g0y + t * gdy, gz = g0z + t * gdz;
             const float fx0 = floorf(gx), fy0 = floorf(gy), fz0 = floorf(gz);
             ix = min(max((int)fx0, -1), nx - 1);
             iy = min(max((int)fy0, -1), ny - 1);

@@ -80,7 +80,7 @@ def test_work_model_prices_measured_issue_costs():
     assert bench.slots(i=3, f=5, t=2) == pytest.approx(3 + 3.0 + 4.6)
     assert bench.SLOTS_PHILOX == 60
     assert bench.SLOTS_DN_SWEEP == pytest.approx(9 * 0.6 + 2.3)
-    assert bench.SLOTS_RT_INTERVAL == pytest.approx(13 + 39 * 0.6)
+    assert bench.SLOTS_RT_INTERVAL == pytest.approx(13 + 33 * 0.6)
 
 
 def test_gather_roofline_from_measured_rates(tmp_path):
