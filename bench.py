@@ -521,7 +521,22 @@ def cpu_baseline(wl, budget_s=20.0):
                 else:
                     stats_acc[k] += v
     fwd_rate = done / spent
-    out = dict(fwd_rate=fwd_rate, fwd_sample=done, stats=stats_acc, threads=nthreads)
+    # the same jobs on one thread, about a second each: the oracle's rate per core
+    done1, spent1 = 0, 0.0
+    for prob, phi, jid, macro, margin in wl["samples"]:
+        p = oracle.Problem.from_workload(prob, phi_rad=phi).local_majorants(macro, margin)
+        n = 5000
+        while True:
+            t = time.time()
+            oracle.mc_project(p, 1, n, job_id=jid, nthreads=1)
+            dt = time.time() - t
+            if dt > 1.0 or n >= 1 << 22:
+                break
+            n *= 2
+        done1 += n
+        spent1 += dt
+    out = dict(fwd_rate=fwd_rate, fwd_sample=done, stats=stats_acc, threads=nthreads,
+               fwd_rate_1=done1 / spent1, fwd_sample_1=done1)
     if wl["adjoint"] is not None:
         a = wl["adjoint"]
         p = oracle.Problem.from_workload(a["problem"]).local_majorants(a["macro"], a["margin"])
@@ -658,7 +673,9 @@ def main():
         else:
             cval = cpu["fwd_rate"]
             sample = f"{cpu['fwd_sample']} forward histories over {len(wl['samples'])} jobs of the same workload"
-        cpu = dict(value=round(cval, 1), unit="histories/s", cores=cores, kind="oracle", sample=sample)
+        cpu = dict(value=round(cval, 1), unit="histories/s", cores=cores, kind="oracle", sample=sample,
+                   single_thread=dict(value=round(cpu["fwd_rate_1"], 1), unit="forward histories/s", cores=1,
+                                      sample=f"{cpu['fwd_sample_1']} forward histories over {len(wl['samples'])} jobs"))
     line = dict(metric=METRIC, value=round(value, 1), unit="histories/s", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=round(ms_step, 2), higher_is_better=True, scaling="weak",
                 vs_baseline=None, dtype="f32", data="synthetic",
