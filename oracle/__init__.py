@@ -16,21 +16,30 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gdrr_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# GDRR_ORACLE_LIB points the loader at another build of the same source (the
+# sanitizer build of the CPU tests)
+_LIB = os.environ.get("GDRR_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 
 CLASS_NAMES = ["primary", "scatter", "absorbed", "cut", "missed", "lost"]
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, OpenMP, strict IEEE: no fast-math)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp"
+SANITIZE_FLAGS = ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-fno-omit-frame-pointer",
+                  "-g"]
+
+
+def build(force: bool = True, out: Optional[str] = None, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP, strict IEEE: no fast-math).
+    sanitize: an AddressSanitizer + UndefinedBehaviorSanitizer build (host
+    code only) at `out`, for the CPU tests."""
+    lib_path = out or _LIB
+    if force or not os.path.exists(lib_path) or os.path.getmtime(lib_path) < os.path.getmtime(_SRC):
+        tmp = lib_path + ".tmp"
         cmd = ["gcc", "-O2", "-std=c11", "-D_DEFAULT_SOURCE", "-fopenmp", "-fPIC", "-shared",
                "-ffp-contract=off", "-Wall", "-Wextra", "-Wno-unused-parameter",
-               _SRC, "-o", tmp, "-lm"]
+               *(SANITIZE_FLAGS if sanitize else []), _SRC, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, lib_path)
+    return lib_path
 
 
 class _Problem(C.Structure):

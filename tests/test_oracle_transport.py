@@ -335,7 +335,8 @@ def test_sphere_symmetry(oracle_lib):
 # with Phi(x) = f |D-S|^2/cos(a) T_in(x, E) / |x-S|^2 the fluence per source
 # photon (f the aim-point density per area), p_k the angular pdf per sr.
 # ---------------------------------------------------------------------------
-def single_scatter_expectation(geom, half, table_grid, mu_tab, f_area, field_half, nvq=8, nq=4, rho=1.0):
+def single_scatter_expectation(geom, half, table_grid, mu_tab, f_area, field_half, nvq=8, nq=4, rho=1.0,
+                               kinds=("rayleigh", "compton")):
     S, P, n, eu, ev = geo_frame(geom.phi_rad, geom.theta_rad, geom.sad_mm, geom.aid_mm)
     E = 60.0
     egrid = table_grid.energies()
@@ -386,7 +387,8 @@ def single_scatter_expectation(geom, half, table_grid, mu_tab, f_area, field_hal
             e_c = E / (1 + kap * (1 - c))
             comp = mu_k(E, 1) * kn(c) / kn_norm * np.exp(-mu_t(e_c) * Lout) * e_c
             rayl = mu_k(E, 0) * ray(c) / ray_norm * np.exp(-mu_t(E) * Lout) * E
-            out[iv, iu] = (wvol[:, None] * phi[:, None] * domega * (comp + rayl)).sum()
+            terms = (comp if "compton" in kinds else 0.0) + (rayl if "rayleigh" in kinds else 0.0)
+            out[iv, iu] = (wvol[:, None] * phi[:, None] * domega * terms).sum()
     return out
 
 
@@ -413,3 +415,37 @@ def test_single_scatter_matches_integral(oracle_lib, rho):
     # the full scatter tally is larger (multiple scatter adds), so mode 1 is a real filter
     r0 = oracle_lib.mc_project(p, seed=17, n=n, mode=0)
     assert r0["tally"][2].sum() > 1.05 * t.sum()
+
+
+@pytest.mark.parametrize("rho", [1.0, 0.55])
+def test_first_order_compton_matches_integral(oracle_lib, rho):
+    """The first-order-Compton tally (Sec. 2.4 names it as a type-specific
+    tally: photons scattered exactly once, by Compton) against the Compton
+    term of the single-scatter integral alone."""
+    nvox, d = 8, 5.0
+    ph = W.box_phantom((nvox, nvox, nvox), (d, d, d), "water", rho)
+    g = W.Geometry(nu=16, nv=16, du_mm=40.0, dv_mm=40.0)
+    flu = np.zeros((16, 16), np.float32)
+    flu[7:9, 7:9] = 1.0
+    grid = W.EnergyGrid()
+    p = make(ph, g, fluence=flu, phys_grid=grid)
+    half = np.full(3, 0.5 * nvox * d)
+    mu_tab = W.cross_section_table(["water"], grid)[0]
+    rho32 = float(np.float32(rho))
+    want = single_scatter_expectation(g, half, grid, mu_tab, 1.0 / (80.0 * 80.0), 40.0, rho=rho32,
+                                      kinds=("compton",))
+    n = 4_000_000
+    r = oracle_lib.mc_project(p, seed=23, n=n, mode=2)
+    t, t2 = r["tally"][2], r["tally"][3]
+    z = zscores(t, t2, n, want)
+    assert np.abs(z).max() < 4.5
+    assert abs((z**2).mean() - 1.0) < 0.35
+    var_tot = np.maximum(t2 - t * t, 0).sum() / n
+    assert abs(t.sum() - want.sum()) < 4 * math.sqrt(var_tot) + 2e-3 * want.sum()
+    # the Rayleigh-only single scatter is what separates mode 2 from mode 1
+    ray_only = single_scatter_expectation(g, half, grid, mu_tab, 1.0 / (80.0 * 80.0), 40.0, rho=rho32,
+                                          kinds=("rayleigh",))
+    r1 = oracle_lib.mc_project(p, seed=23, n=n, mode=1)
+    diff = r1["tally"][2].sum() - t.sum()
+    assert diff > 0
+    assert abs(diff - ray_only.sum()) < 4 * math.sqrt(var_tot) + 0.05 * ray_only.sum()
