@@ -41,10 +41,20 @@
  * stream) and may be recorded into a HIP graph.  The library keeps no device
  * memory between calls: scratch lives in the caller's workspace, which also
  * holds a per-call copy of each phantom laid out for the transport kernel
- * (64 bytes per voxel: the eight interpolation corners of each cell).
+ * (32 bytes per cell of the lattice of voxel centres, (nx+1)(ny+1)(nz+1)
+ * cells: the eight interpolation corners of the cell, the materials in their
+ * sign bits).  Each call that takes a workspace reports the bytes it needs
+ * through its own query (gdrr_*_workspace), sized for that call's arguments.
  *
  * Errors: functions return GDRR_OK (0) or a negative code; no exception
  * crosses the ABI; gdrr_last_error() gives a message for the calling thread.
+ * Arguments the host can see are checked before anything is launched.  Array
+ * contents live on the device and are checked by the kernels while they run:
+ * a density that is negative, NaN or infinite is transported as 0, a
+ * material index >= n_mat as n_mat - 1, and the call still returns GDRR_OK;
+ * gdrr_input_status() on the call's workspace afterwards says whether that
+ * happened (GDRR_EINVAL and a message) -- or whether spectrum or fluence
+ * weights were negative, non-finite or all zero.
  */
 #ifndef GDRR_H
 #define GDRR_H
@@ -67,6 +77,8 @@ extern "C" {
 #define GDRR_ACCUMULATE 4u         /* add to the output tallies / gradient instead of overwriting them */
 #define GDRR_SCATTER_FIRST 8u      /* scatter tally counts only photons scattered exactly once (Sec. 2.4, type-specific tally) */
 #define GDRR_SCATTER_FIRST_COMPTON 16u /* ... only photons scattered exactly once, by Compton */
+#define GDRR_RESUME 32u            /* forward: keep the fixed-point sums an earlier call left in the same workspace
+                                      and add to them; see gdrr_job.first_photon */
 
 #define GDRR_MAX_MATERIALS 16
 #define GDRR_MAX_VOLUMES 8
@@ -76,8 +88,10 @@ extern "C" {
 typedef struct gdrr_volume {
     int32_t nx, ny, nz;
     float dx_mm, dy_mm, dz_mm;
-    const float* density;      /* [nz][ny][nx] g/cm^3, finite and >= 0 */
-    const uint8_t* material;   /* [nz][ny][nx] indices < gdrr_physics.n_mat */
+    const float* density;      /* [nz][ny][nx] g/cm^3, finite and >= 0 (others are transported as 0 and
+                                  reported by gdrr_input_status) */
+    const uint8_t* material;   /* [nz][ny][nx] indices < gdrr_physics.n_mat (others: n_mat - 1, reported) */
+    /* (nx+1)(ny+1)(nz+1) < 2^31 */
     /* Local majorants (not in the paper; 0 = off): the volume is cut into cubes of
      * `macro`^3 voxels (the last ones along an axis shorter), each with the bound
      * (1 + macro_margin) rho_max max_m mu_tot(m, E) over the cube grown by one voxel;
@@ -130,14 +144,21 @@ typedef struct gdrr_geometry {
     float du_mm, dv_mm;
 } gdrr_geometry;
 
-/* One projection of a batch. */
+/* One projection of a batch: the histories of photon indices
+ * first_photon .. first_photon + n_photons - 1 of job `job_id`.  Their tally
+ * is per source photon of that range (divided by n_photons).  A run can be
+ * split and resumed (a checkpoint being the workspace): a call over
+ * [0, m) and then, on the same workspace with the same arguments, a call with
+ * first_photon = m, n_photons = N - m and GDRR_RESUME give bit for bit the
+ * tallies of one call over [0, N), since the fixed-point sums continue and
+ * the output is then divided by first_photon + n_photons. */
 typedef struct gdrr_job {
     int32_t volume;            /* index into the batch's volumes */
     int32_t source;            /* index into the batch's sources */
     gdrr_geometry geom;
-    uint64_t n_photons;        /* < 2^32 */
+    uint64_t n_photons;        /* first_photon + n_photons < 2^32 */
     uint32_t job_id;           /* Philox counter word 1 */
-    uint32_t reserved;         /* must be 0 */
+    uint32_t first_photon;     /* first photon index (Philox counter word 0) */
     int64_t tally_offset;      /* element offset of this job's [4][nv][nu] block in `tallies` */
 } gdrr_job;
 
@@ -146,10 +167,8 @@ typedef struct gdrr_tuning {
     int32_t block;             /* threads per workgroup: a multiple of 64 up to 1024 */
     int32_t blocks_per_cu;     /* workgroups per compute unit */
     int32_t chunk;             /* photons handed out at a time (multiple of 64) */
-    int32_t defer;             /* scheme 1: interactions/refills run when >= defer lanes wait (1..64) */
-    int32_t scheme;            /* 1: each lane keeps its photon through interactions; 2: photons at a
-                                  real collision move to a workgroup queue in LDS and interactions and
-                                  source sampling run on packed lanes; results are identical */
+    int32_t defer;             /* interactions and refills run when >= defer lanes of a wavefront wait (1..64) */
+    int32_t scheme;            /* 0 or 1: one photon per lane for its whole history (the only scheme) */
 } gdrr_tuning;
 
 /*
@@ -290,6 +309,26 @@ size_t gdrr_denoise_workspace(int32_t n_img, int32_t nv, int32_t nu);
 int gdrr_noise(int32_t n_img, int64_t npix, const double* phat, int64_t phat_stride, const double* p,
                const double* shat, int64_t shat_stride, const double* s, double alpha, double* noise,
                double* image, void* stream);
+
+/*
+ * The noise scale of Sec. 2.6, second equation: *alpha = sqrt(n_sim / (zeta I))
+ * for n_sim simulated source photons, zeta source photons per mAs and I mAs
+ * (host arithmetic in float64; all three must be finite and > 0, else
+ * GDRR_EINVAL).
+ */
+int gdrr_noise_scale(double n_sim, double zeta, double mas, double* alpha);
+
+/*
+ * Status of the device-side input checks of the last call that used
+ * `workspace` (gdrr_majorant, gdrr_mc_project, gdrr_mc_project_batch,
+ * gdrr_mc_backward, gdrr_mc_trace, gdrr_primary): waits for `stream`, then
+ * returns GDRR_OK, or GDRR_EINVAL with a message naming what the kernels
+ * found -- densities that are negative, NaN or infinite (transported as 0),
+ * material indices >= n_mat (transported as n_mat - 1), spectrum or fluence
+ * weights that are negative, non-finite or sum to zero (the source is then
+ * undefined).  Does not launch or allocate; not for use under graph capture.
+ */
+int gdrr_input_status(const void* workspace, void* stream);
 
 /*
  * Timing hook (autotuner, benchmarks): while enabled, the transport kernel of

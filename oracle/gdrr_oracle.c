@@ -748,6 +748,10 @@ static int validate(const or_problem* p)
         if (!(p->spec_e[k] >= p->e0 && p->spec_e[k] <= emax)) return -1;
     if (!(p->e_cut >= p->e0)) return -1;
     if (p->macro < 0 || (p->macro > 0 && (p->n_mat > 64 || !(p->macro_margin >= 0.0)))) return -1;
+    /* every voxel: a material of the table, a finite density >= 0 */
+    size_t nvox = (size_t)p->nx * p->ny * p->nz;
+    for (size_t v = 0; v < nvox; ++v)
+        if (p->material[v] >= p->n_mat || !(p->density[v] >= 0.0f) || isinf(p->density[v])) return -1;
     /* the phantom must lie on the source side of the detector plane */
     double rxy = sqrt(0.25 * (p->nx * p->dx) * (p->nx * p->dx) + 0.25 * (p->ny * p->dy) * (p->ny * p->dy));
     if (!(rxy < p->aid) || !(rxy < p->sad)) return -1;

@@ -21,6 +21,7 @@ TALLY_SUMSQ = 2
 ACCUMULATE = 4
 SCATTER_FIRST = 8
 SCATTER_FIRST_COMPTON = 16
+RESUME = 32
 
 MAX_MATERIALS = 16
 MAX_VOLUMES = 8
@@ -55,7 +56,7 @@ class Geometry(C.Structure):
 
 class Job(C.Structure):
     _fields_ = [("volume", C.c_int32), ("source", C.c_int32), ("geom", Geometry),
-                ("n_photons", C.c_uint64), ("job_id", C.c_uint32), ("reserved", C.c_uint32),
+                ("n_photons", C.c_uint64), ("job_id", C.c_uint32), ("first_photon", C.c_uint32),
                 ("tally_offset", C.c_int64)]
 
 
@@ -92,6 +93,8 @@ SIGNATURES = {
     "gdrr_denoise_workspace": (_sz, [C.c_int32, C.c_int32, C.c_int32]),
     "gdrr_noise": (C.c_int, [C.c_int32, C.c_int64, _vp, C.c_int64, _vp, _vp, C.c_int64, _vp, C.c_double, _vp, _vp,
                              _vp]),
+    "gdrr_noise_scale": (C.c_int, [C.c_double, C.c_double, C.c_double, _P(C.c_double)]),
+    "gdrr_input_status": (C.c_int, [_vp, _vp]),
     "gdrr_enable_timing": (C.c_int, [C.c_int]),
     "gdrr_last_kernel_ms": (C.c_int, [_P(C.c_float)]),
     "gdrr_default_tuning": (C.c_int, [_P(Tuning)]),

@@ -20,6 +20,7 @@ TALLY_SUMSQ = _abi.TALLY_SUMSQ
 ACCUMULATE = _abi.ACCUMULATE
 SCATTER_FIRST = _abi.SCATTER_FIRST
 SCATTER_FIRST_COMPTON = _abi.SCATTER_FIRST_COMPTON
+RESUME = _abi.RESUME
 
 
 def _dev(device):
@@ -233,9 +234,15 @@ def noise(phat: torch.Tensor, p: torch.Tensor, shat: torch.Tensor, s: torch.Tens
 
 def noise_scale(n_sim: float, zeta: float, mas: float) -> float:
     """alpha = sqrt(n_sim / (zeta I)) of Sec. 2.6 (I in mAs, zeta source photons per mAs)."""
-    if not (n_sim > 0 and zeta > 0 and mas > 0):
-        raise ValueError("n_sim, zeta and mAs must be > 0")
-    return float(np.sqrt(n_sim / (zeta * mas)))
+    a = C.c_double(0.0)
+    _abi.check(_abi.lib().gdrr_noise_scale(float(n_sim), float(zeta), float(mas), C.byref(a)))
+    return float(a.value)
+
+
+def input_status(workspace: torch.Tensor, stream=None):
+    """Raise GdrrError if the kernels of the last call on `workspace` met invalid
+    device inputs (densities, materials, source weights); waits for the stream."""
+    _abi.check(_abi.lib().gdrr_input_status(C.c_void_p(workspace.data_ptr()), _stream(stream)))
 
 
 def enable_timing(on: bool = True):
@@ -251,11 +258,12 @@ def last_kernel_ms() -> float:
 
 
 class JobSpec:
-    """One projection of a batch."""
+    """One projection of a batch: photon indices first_photon .. first_photon + n_photons - 1."""
 
-    def __init__(self, geom, n_photons: int, job_id: int, volume: int = 0, source: int = 0):
+    def __init__(self, geom, n_photons: int, job_id: int, volume: int = 0, source: int = 0,
+                 first_photon: int = 0):
         self.geom, self.n_photons, self.job_id = geom, int(n_photons), int(job_id)
-        self.volume, self.source = int(volume), int(source)
+        self.volume, self.source, self.first_photon = int(volume), int(source), int(first_photon)
 
 
 def _jobs_array(jobs: Sequence[JobSpec], planes: int = 4):
@@ -265,7 +273,7 @@ def _jobs_array(jobs: Sequence[JobSpec], planes: int = 4):
     for k, j in enumerate(jobs):
         arr[k].volume, arr[k].source = j.volume, j.source
         arr[k].geom = geometry_struct(j.geom)
-        arr[k].n_photons, arr[k].job_id, arr[k].reserved = j.n_photons, j.job_id, 0
+        arr[k].n_photons, arr[k].job_id, arr[k].first_photon = j.n_photons, j.job_id, j.first_photon
         arr[k].tally_offset = off
         off += planes * j.geom.nu * j.geom.nv
     return arr, off
@@ -307,6 +315,23 @@ class Batch:
         if self._ws is None or self._ws.numel() < nbytes:
             self._ws = torch.empty(nbytes, dtype=torch.uint8, device=self.vols[0].density.device)
         return self._ws
+
+    def set_photon_ranges(self, first_photon, n_photons):
+        """Give every job the photon indices first_photon .. first_photon + n_photons - 1
+        (scalars, or one value per job).  The workspace is kept, so a following
+        project(resume=True) continues the fixed-point sums of the previous call."""
+        k = len(self.jobs)
+        firsts = list(first_photon) if hasattr(first_photon, "__len__") else [first_photon] * k
+        counts = list(n_photons) if hasattr(n_photons, "__len__") else [n_photons] * k
+        self.jobs = [JobSpec(j.geom, n, j.job_id, j.volume, j.source, f) for j, f, n in zip(self.jobs, firsts, counts)]
+        self._jobs_c, self.tally_elems = _jobs_array(self.jobs)
+        if hasattr(self, "_img_jobs"):
+            del self._img_jobs
+        return self
+
+    def input_status(self, stream=None):
+        """Raise GdrrError if the last transport call met invalid device inputs."""
+        input_status(self.workspace(), stream)
 
     def tally_views(self, tallies: torch.Tensor) -> List[torch.Tensor]:
         out, off = [], 0
@@ -352,8 +377,14 @@ class Batch:
 
     def project(self, seed: int = 1, interp: bool = True, sumsq: bool = True, flags: int = 0, tune=None,
                 majorants: Optional[torch.Tensor] = None, out: Optional[torch.Tensor] = None,
-                densities=None, stream=None) -> torch.Tensor:
+                densities=None, resume: bool = False, stream=None) -> torch.Tensor:
+        """Tallies of every job (flat float64, each job's [4][nv][nu] block in order).
+        resume: continue the fixed-point sums the previous call left in the workspace
+        (jobs moved on with set_photon_ranges); the output is then per source photon
+        of [0, first_photon + n_photons)."""
         L = _abi.lib()
+        if resume:
+            flags |= RESUME
         va, sa, p = self._structs(densities)
         if out is None:
             out = torch.zeros(self.tally_elems, dtype=torch.float64, device=self.vols[0].density.device)

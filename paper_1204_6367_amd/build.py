@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libgdrr.so")
 SOURCES = [os.path.join(HERE, "csrc", "gdrr_api.hip")]
-DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("gdrr_device.h", "gdrr_kernels.h", "gdrr_queue.h", "gdrr_raytrace.h", "gdrr_denoise.h")] + \
+DEPS = SOURCES + [os.path.join(HERE, "csrc", f) for f in ("gdrr_device.h", "gdrr_kernels.h", "gdrr_raytrace.h", "gdrr_denoise.h")] + \
     [os.path.join(ROOT, "include", "gdrr.h")]
 
 HIPCC_FLAGS = [

@@ -11,7 +11,6 @@
 
 #include "gdrr.h"
 #include "gdrr_kernels.h"
-#include "gdrr_queue.h"
 #include "gdrr_raytrace.h"
 #include "gdrr_denoise.h"
 
@@ -96,6 +95,9 @@ int check_volume(const gdrr_volume* v) {
     if (!v) return fail(GDRR_EINVAL, "volume is NULL");
     if (v->nx < 1 || v->ny < 1 || v->nz < 1) return fail(GDRR_EINVAL, "volume dimensions must be >= 1");
     if ((long long)v->nx * v->ny * v->nz >= (1ll << 31)) return fail(GDRR_EINVAL, "volume has 2^31 voxels or more");
+    // cell records are indexed in 32-bit arithmetic
+    if ((long long)(v->nx + 1) * (v->ny + 1) * (v->nz + 1) >= (1ll << 31))
+        return fail(GDRR_EINVAL, "volume has 2^31 interpolation cells or more ((nx+1)(ny+1)(nz+1))");
     if (!(v->dx_mm > 0 && v->dy_mm > 0 && v->dz_mm > 0)) return fail(GDRR_EINVAL, "voxel sizes must be > 0");
     if (!v->density || !v->material) return fail(GDRR_EINVAL, "volume density/material pointer is NULL");
     if (v->macro < 0 || v->macro > 256) return fail(GDRR_EINVAL, "volume macro must be in [0, 256]");
@@ -422,8 +424,8 @@ int check_batch(const Batch& B) {
         const gdrr_job& J = B.jobs[k];
         if (J.volume < 0 || J.volume >= B.n_vols) return fail(GDRR_EINVAL, "job volume index out of range");
         if (J.source < 0 || J.source >= B.n_srcs) return fail(GDRR_EINVAL, "job source index out of range");
-        if (J.n_photons >= (1ull << 32)) return fail(GDRR_EINVAL, "2^32 or more photons in one job");
-        if (J.reserved != 0) return fail(GDRR_EINVAL, "gdrr_job.reserved must be 0");
+        if (J.n_photons >= (1ull << 32) || (uint64_t)J.first_photon + J.n_photons >= (1ull << 32))
+            return fail(GDRR_EINVAL, "a job's photon indices must stay below 2^32 (first_photon + n_photons)");
         if (J.tally_offset < 0) return fail(GDRR_EINVAL, "negative tally offset");
         if ((rc = check_geometry(&J.geom, &B.vols[J.volume], &B.srcs[J.source]))) return rc;
     }
@@ -433,18 +435,14 @@ int check_batch(const Batch& B) {
         if (t.chunk && (t.chunk % 64 || t.chunk < 64)) return fail(GDRR_EINVAL, "tune.chunk must be a positive multiple of 64");
         if (t.defer < 0 || t.defer > 64) return fail(GDRR_EINVAL, "tune.defer must be in [0, 64]");
         if (t.blocks_per_cu < 0 || t.blocks_per_cu > 64) return fail(GDRR_EINVAL, "tune.blocks_per_cu must be in [0, 64]");
-        if (t.scheme < 0 || t.scheme > 2) return fail(GDRR_EINVAL, "tune.scheme must be 0, 1 or 2");
-        if (t.scheme == 2)
-            for (int v = 0; v < B.n_vols; ++v)
-                if (B.vols[v].macro > 0) return fail(GDRR_ENOTSUP, "tune.scheme 2 does not support local majorants");
+        if (t.scheme < 0 || t.scheme > 1) return fail(GDRR_EINVAL, "tune.scheme must be 0 or 1");
     }
     return GDRR_OK;
 }
 
 // local: 0 single majorants, 1 local majorants with records in global memory, 2 with records in LDS
 template <int MODE>
-const void* mc_func(int scheme, int local) {
-    if (scheme == 2) return reinterpret_cast<const void*>(&mc_queue_kernel<MODE>);
+const void* mc_func(int local) {
     if constexpr (MODE == kModeBackward)
         return local == 2 ? reinterpret_cast<const void*>(&mc_adjoint_kernel<2>)
              : local == 1 ? reinterpret_cast<const void*>(&mc_adjoint_kernel<1>)
@@ -455,9 +453,9 @@ const void* mc_func(int scheme, int local) {
                           : reinterpret_cast<const void*>(&mc_kernel<MODE, 0>);
 }
 
-const void* mc_func_for(int mode, int scheme, int local) {
-    return mode == kModeForward ? mc_func<kModeForward>(scheme, local)
-         : mode == kModeTrace ? mc_func<kModeTrace>(scheme, local) : mc_func<kModeBackward>(scheme, local);
+const void* mc_func_for(int mode, int local) {
+    return mode == kModeForward ? mc_func<kModeForward>(local)
+         : mode == kModeTrace ? mc_func<kModeTrace>(local) : mc_func<kModeBackward>(local);
 }
 
 // Does some job of the launch trace photons in volume v?
@@ -489,16 +487,15 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     unsigned long long total_photons = 0;
     for (int k = 0; k < B.n_jobs; ++k)
         if (B.only_volume < 0 || B.jobs[k].volume == B.only_volume) total_photons += B.jobs[k].n_photons;
-    const int scheme = tune.scheme ? tune.scheme : 1;
     bool local = false;
     for (int v = 0; v < B.n_vols; ++v) local |= B.vols[v].macro > 0;
-    const int block = tune.block ? tune.block : (scheme == 2 ? 512 : 256);
+    const int block = tune.block ? tune.block : 256;
     // local majorants go to LDS (after the tables) while the records of all volumes that the
     // launch traces fit in kMacroLdsMax
     int macro_lds[GDRR_MAX_VOLUMES];
     int macro_lds_n = 0;
     for (int v = 0; v < GDRR_MAX_VOLUMES; ++v) macro_lds[v] = -1;
-    if (local && scheme != 2) {
+    if (local) {
         size_t n = 0;
         for (int v = 0; v < B.n_vols; ++v)
             if (B.vols[v].macro > 0 && batch_uses(B, v))
@@ -512,14 +509,13 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
                                    cubes(B.vols[v].nz, B.vols[v].macro);
                 }
     }
-    const size_t lds = scheme == 2 ? queue_lds_bytes(phys->n_mat, phys->n_e, B.n_vols, phys->response != nullptr, block)
-                                   : lds_bytes(phys->n_mat, phys->n_e, B.n_vols, phys->response != nullptr) +
-                                         (size_t)macro_lds_n * sizeof(uint2);
-    if (lds > dev.lds_max) return fail(GDRR_ENOTSUP, "tables and queues exceed the LDS of a workgroup");
+    const size_t lds = lds_bytes(phys->n_mat, phys->n_e, B.n_vols, phys->response != nullptr) +
+                       (size_t)macro_lds_n * sizeof(uint2);
+    if (lds > dev.lds_max) return fail(GDRR_ENOTSUP, "tables exceed the LDS of a workgroup");
     const int local_kind = !local ? 0 : (macro_lds_n > 0 ? 2 : 1);
     int per_cu = tune.blocks_per_cu;
     if (!per_cu) {
-        const void* f = mc_func_for(B.mode, scheme, local_kind);
+        const void* f = mc_func_for(B.mode, local_kind);
         int nb = 0;
         GDRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, block, lds));
         per_cu = std::max(nb, 1);
@@ -549,6 +545,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
         const unsigned long long n = run ? J.n_photons : 0ull;
         d.n_lo = (uint32_t)J.n_photons;
         d.n_hi = (uint32_t)(J.n_photons >> 32);
+        d.first = J.first_photon;
         d.index = (uint32_t)k;
         d.tally_off = (long long)toff;
         d.adj_off = (long long)(2 * (size_t)g.nu * g.nv * k);
@@ -573,12 +570,20 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
                             hipMemcpyHostToDevice, st));
 
     std::vector<Launch> ls;
-    // ---- clear counters, tallies and the majorant scratch ----
+    unsigned int* status = (unsigned int*)(L.counter + 1);    // input-error bits of this call
+    const bool resume = B.mode == kModeForward && (B.flags & GDRR_RESUME);
+    // ---- clear counters, tallies (unless resuming), the gradient and the majorant scratch ----
     {
         FillParams f{L.counter, 8};
         ls.push_back(make_launch((const void*)&fill_zero_kernel, dim3(1), dim3(256), 0, f));
         FillParams t{L.tally, (long long)L.tally_elems};
-        ls.push_back(make_launch((const void*)&fill_zero_kernel, dim3(std::max<unsigned>(1, std::min<size_t>(4096, (L.tally_elems + 255) / 256))), dim3(256), 0, t));
+        if (!resume)
+            ls.push_back(make_launch((const void*)&fill_zero_kernel, dim3(std::max<unsigned>(1, std::min<size_t>(4096, (L.tally_elems + 255) / 256))), dim3(256), 0, t));
+        if (B.mode == kModeBackward && !(B.flags & GDRR_ACCUMULATE)) {
+            const gdrr_volume& V = B.vols[B.only_volume];
+            GradClearParams g{B.grad, (long long)V.nx * V.ny * V.nz};
+            ls.push_back(make_launch((const void*)&grad_zero_kernel, dim3(1024), dim3(256), 0, g));
+        }
         FillParams r{(unsigned long long*)L.rho_max, (long long)B.n_vols * 128};   // 256 u32 per volume
         ls.push_back(make_launch((const void*)&fill_zero_kernel, dim3(4), dim3(256), 0, r));
         FillParams p{(unsigned long long*)L.present, (long long)B.n_vols * 128};
@@ -589,14 +594,14 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     if (need_maj) {
         for (int v = 0; v < B.n_vols; ++v) {
             const gdrr_volume& V = B.vols[v];
-            MajParams m{V.density, V.material, V.nx, V.ny, V.nz, interp ? 1 : 0, L.rho_max + 256 * v,
-                        L.present + 256 * v, (unsigned int*)(L.counter + 1)};
+            MajParams m{V.density, V.material, V.nx, V.ny, V.nz, interp ? 1 : 0, phys->n_mat, L.rho_max + 256 * v,
+                        L.present + 256 * v, status};
             const long long nvox = (long long)V.nx * V.ny * V.nz;
             const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>(dev.cus * 8, (nvox + 255) / 256));
             ls.push_back(make_launch((const void*)&rho_max_kernel, dim3(g), dim3(256), 0, m));
             MajFinParams fp{L.rho_max + 256 * v, L.present + 256 * v, phys->mu_mass, phys->n_mat, phys->n_e,
                             1.0 + (double)(1.0f / 1048576.0f), L.majorants + (size_t)v * (phys->n_e - 1),
-                            (unsigned int*)(L.counter + 1)};
+                            status};
             ls.push_back(make_launch((const void*)&majorant_kernel, dim3((phys->n_e + 254) / 256), dim3(256), 0, fp));
         }
         maj = L.majorants;
@@ -605,7 +610,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     for (int v = 0; v < B.n_vols; ++v) {
         if (!batch_uses(B, v)) continue;
         const gdrr_volume& V = B.vols[v];
-        CellParams cp{V.density, V.material, V.nx, V.ny, V.nz, phys->n_mat, L.cells[v]};
+        CellParams cp{V.density, V.material, V.nx, V.ny, V.nz, phys->n_mat, L.cells[v], status};
         const size_t nc = cell_count(V);
         ls.push_back(make_launch((const void*)&cells_kernel,
                                  dim3((unsigned)std::max<size_t>(1, std::min<size_t>((size_t)dev.cus * 16, (nc + 255) / 256))),
@@ -625,12 +630,11 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
         const gdrr_source& S = B.srcs[s];
         const SrcArea& A = L.src[s];
         const int rows = spec_rows(S);
-        SrcPrepParams sp{S.spec_prob, S.n_spec, rows, A.spec_cdf, A.spec_guide, (int)A.spec_k,
-                         (unsigned int*)(L.counter + 1)};
+        SrcPrepParams sp{S.spec_prob, S.n_spec, rows, A.spec_cdf, A.spec_guide, (int)A.spec_k, status};
         ls.push_back(make_launch((const void*)&cdf_kernel, dim3(rows), dim3(1024), 0, sp));
         const unsigned gk = (unsigned)std::min<size_t>((size_t)dev.cus * 8, ((size_t)rows * A.spec_k + 255) / 256);
         ls.push_back(make_launch((const void*)&guide_kernel, dim3(gk), dim3(256), 0, sp));
-        SrcPrepParams fp{S.fluence, S.fu * S.fv, 1, A.flu_cdf, A.flu_guide, (int)A.flu_k, (unsigned int*)(L.counter + 1)};
+        SrcPrepParams fp{S.fluence, S.fu * S.fv, 1, A.flu_cdf, A.flu_guide, (int)A.flu_k, status};
         ls.push_back(make_launch((const void*)&cdf_kernel, dim3(1), dim3(1024), 0, fp));
         ls.push_back(make_launch((const void*)&guide_kernel, dim3((A.flu_k + 255) / 256), dim3(256), 0, fp));
     }
@@ -703,7 +707,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     kp.grad = B.grad;
     for (int v = 0; v < kMaxVol; ++v) kp.macro_lds[v] = v < GDRR_MAX_VOLUMES ? macro_lds[v] : -1;
     kp.macro_lds_n = macro_lds_n;
-    const void* mf = mc_func_for(B.mode, scheme, local_kind);
+    const void* mf = mc_func_for(B.mode, local_kind);
     int timed = -1;
     if (chunks > 0) {
         timed = (int)ls.size();
@@ -713,7 +717,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     if (B.mode == kModeForward) {
         int maxpix = 1;
         for (int k = 0; k < B.n_jobs; ++k) maxpix = std::max(maxpix, B.jobs[k].geom.nu * B.jobs[k].geom.nv);
-        FinParams fp{L.jobs, B.n_jobs, L.tally, B.out, L.out_off, B.flags};
+        FinParams fp{L.jobs, B.n_jobs, L.tally, B.out, L.out_off, B.flags & (GDRR_TALLY_SUMSQ | GDRR_ACCUMULATE | GDRR_RESUME)};
         ls.push_back(make_launch((const void*)&finalize_kernel,
                                  dim3((unsigned)std::min(1024, (4 * maxpix + 255) / 256), (unsigned)B.n_jobs), dim3(256), 0, fp));
     }
@@ -743,6 +747,7 @@ size_t batch_bytes(const gdrr_volume* vols, int n_vols, const gdrr_physics* phys
 // Ray-tracing primary (Eq. 1): workspace layout and launch.
 // --------------------------------------------------------------------------
 struct RtLayout {
+    unsigned long long* head;            // [8] status block (word 1: input-error bits)
     DJob* jobs;                          // [n_jobs]
     int* unit_job;                       // [max units]
     unsigned int* unit_first;
@@ -792,6 +797,7 @@ RtLayout rt_carve(void* ws, const gdrr_volume* vols, int n_vols, const gdrr_phys
                   int n_srcs, const gdrr_job* jobs, int n_jobs) {
     Carver c(ws);
     RtLayout L{};
+    L.head = c.take<unsigned long long>(8);
     L.jobs = c.take<DJob>((size_t)n_jobs);
     const size_t units = rt_max_units(jobs, n_jobs);
     L.unit_job = c.take<int>(units);
@@ -935,6 +941,11 @@ int run_primary(const gdrr_volume* vols, int n_vols, const gdrr_physics* phys, c
     GDRR_HIP(hipMemcpyAsync(L.out_off, hs + b_jobs + 3 * b_u, b_off, hipMemcpyHostToDevice, st));
 
     std::vector<Launch> ls;
+    unsigned int* status = (unsigned int*)(L.head + 1);
+    {
+        FillParams f{L.head, 8};
+        ls.push_back(make_launch((const void*)&fill_zero_kernel, dim3(1), dim3(256), 0, f));
+    }
     for (int v = 0; v < n_vols; ++v) {
         const gdrr_volume& V = vols[v];
         DVolume& d = rp.vol[v];
@@ -949,18 +960,24 @@ int run_primary(const gdrr_volume* vols, int n_vols, const gdrr_physics* phys, c
         d.loz = (float)(-0.5 * V.nz * V.dz_mm); d.hiz = -d.loz;
         d.idx = (float)(1.0 / V.dx_mm); d.idy = (float)(1.0 / V.dy_mm); d.idz = (float)(1.0 / V.dz_mm);
         if (interp && L.cells[v]) {
-            CellParams cp{V.density, V.material, V.nx, V.ny, V.nz, phys->n_mat, L.cells[v]};
+            CellParams cp{V.density, V.material, V.nx, V.ny, V.nz, phys->n_mat, L.cells[v], status};
             const size_t nc = cell_count(V);
             ls.push_back(make_launch((const void*)&cells_kernel,
                                      dim3((unsigned)std::max<size_t>(1, std::min<size_t>((size_t)dev.cus * 16, (nc + 255) / 256))),
                                      dim3(256), 0, cp));
+        } else if (volume_used(jobs, n_jobs, v)) {
+            const long long nv = (long long)V.nx * V.ny * V.nz;
+            VolCheckParams vc{V.density, V.material, nv, phys->n_mat, status};
+            ls.push_back(make_launch((const void*)&volume_check_kernel,
+                                     dim3((unsigned)std::max<long long>(1, std::min<long long>((long long)dev.cus * 8, (nv + 255) / 256))),
+                                     dim3(256), 0, vc));
         }
     }
     for (int s = 0; s < n_srcs; ++s) {
         const gdrr_source& S = srcs[s];
         RtPrepParams pp{S.spec_e_kev, S.spec_prob, S.fluence, S.n_spec, S.fu * S.fv, phys->mu_mass, phys->response,
                         phys->n_mat, phys->n_e, (double)phys->e0_kev, (double)phys->de_kev, L.coef[s], L.tab[s],
-                        L.inv_wsum[s]};
+                        L.inv_wsum[s], status};
         ls.push_back(make_launch((const void*)&raytrace_prep_kernel, dim3(spec_rows(S)), dim3(256), 0, pp));
         rp.src[s] = RtSource{S.fluence, L.coef[s], L.tab[s], L.inv_wsum[s], S.n_spec, spec_rows(S)};
     }
@@ -1130,14 +1147,17 @@ int gdrr_majorant(const gdrr_volume* vol, const gdrr_physics* phys, uint32_t fla
     DevInfo dev;
     if ((rc = device_info(dev))) return rc;
     hipStream_t st = (hipStream_t)stream;
-    unsigned int* rmax = (unsigned int*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    // the status block first (as in every workspace; word 1 holds the input-error bits), then the
+    // per-material maxima and presence flags
+    unsigned long long* head = (unsigned long long*)(((uintptr_t)workspace + 255) & ~(uintptr_t)255);
+    unsigned int* err = (unsigned int*)(head + 1);
+    unsigned int* rmax = (unsigned int*)(head + 8);
     unsigned int* pres = rmax + 256;
-    unsigned int* err = pres + 256;
     std::vector<Launch> ls;
-    FillParams f{(unsigned long long*)rmax, 257};
+    FillParams f{head, 8 + 256};
     ls.push_back(make_launch((const void*)&fill_zero_kernel, dim3(2), dim3(256), 0, f));
     MajParams m{vol->density, vol->material, vol->nx, vol->ny, vol->nz, (flags & GDRR_INTERP_DENSITY) ? 1 : 0,
-                rmax, pres, err};
+                phys->n_mat, rmax, pres, err};
     const long long nvox = (long long)vol->nx * vol->ny * vol->nz;
     const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>(dev.cus * 8, (nvox + 255) / 256));
     ls.push_back(make_launch((const void*)&rho_max_kernel, dim3(g), dim3(256), 0, m));
@@ -1188,12 +1208,7 @@ int gdrr_mc_backward(const gdrr_volume* vols, int32_t n_vols, const gdrr_physics
     if (!majorants) return fail(GDRR_EINVAL, "the adjoint needs the forward's majorants");
     if (!adj || !grad_density) return fail(GDRR_EINVAL, "adj / grad_density is NULL");
     if (volume < 0 || volume >= n_vols) return fail(GDRR_EINVAL, "volume index out of range");
-    if (!(flags & GDRR_ACCUMULATE)) {
-        const gdrr_volume& V = vols[volume];
-        GradClearParams g{grad_density, (long long)V.nx * V.ny * V.nz};
-        void* a[1] = {&g};
-        GDRR_HIP(hipLaunchKernel((const void*)&grad_zero_kernel, dim3(1024), dim3(256), a, 0, (hipStream_t)stream));
-    }
+    // (the gradient is cleared by run_batch's launch list, after every argument check)
     Batch B{vols, n_vols, phys, srcs, n_srcs, jobs, n_jobs, majorants, seed, flags, tune, kModeBackward, volume,
             nullptr, adj, grad_density, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, false};
     return run_batch(B, workspace, ws_bytes, (hipStream_t)stream);
@@ -1247,6 +1262,32 @@ int gdrr_noise(int32_t n_img, int64_t npix, const double* phat, int64_t phat_str
     void* a[1] = {&q};
     GDRR_HIP(hipLaunchKernel((const void*)&noise_kernel, dim3(grid), dim3(256), a, 0, (hipStream_t)stream));
     return GDRR_OK;
+}
+
+int gdrr_noise_scale(double n_sim, double zeta, double mas, double* alpha) {
+    if (!alpha) return fail(GDRR_EINVAL, "alpha is NULL");
+    if (!(n_sim > 0.0 && zeta > 0.0 && mas > 0.0) || !std::isfinite(n_sim) || !std::isfinite(zeta) ||
+        !std::isfinite(mas))
+        return fail(GDRR_EINVAL, "n_sim, zeta and mAs must be finite and > 0");
+    *alpha = std::sqrt(n_sim / (zeta * mas));
+    return GDRR_OK;
+}
+
+int gdrr_input_status(const void* workspace, void* stream) {
+    if (!workspace) return fail(GDRR_EINVAL, "workspace is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned int* word = (const unsigned int*)((((uintptr_t)workspace + 255) & ~(uintptr_t)255) + 8);
+    unsigned int bits = 0;
+    GDRR_HIP(hipStreamSynchronize(st));
+    GDRR_HIP(hipMemcpyAsync(&bits, word, sizeof(bits), hipMemcpyDeviceToHost, st));
+    GDRR_HIP(hipStreamSynchronize(st));
+    if (!bits) return GDRR_OK;
+    std::string msg = "invalid device inputs:";
+    if (bits & kErrDensity) msg += " densities negative, NaN or infinite (transported as 0);";
+    if (bits & kErrMaterial) msg += " material indices >= n_mat (transported as n_mat - 1);";
+    if (bits & kErrWeights) msg += " spectrum or fluence weights negative, non-finite or summing to 0;";
+    msg.pop_back();
+    return fail(GDRR_EINVAL, msg);
 }
 
 int gdrr_mc_trace(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr_source* src,

@@ -56,9 +56,13 @@ __device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
 
 __device__ __forceinline__ float fast_log(float x) { return __builtin_amdgcn_logf(x) * 0.69314718055994531f; }
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-// -expm1(e) = 1 - exp(e) for e in [-0.5, 0] by its Taylor series to e^7
-// (relative error below 1e-7 there), without the cancellation of 1 - exp(e).
+__device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+// -expm1(e) = 1 - exp(e) for e <= 0.  For e in [-0.47, 0] (photon energies up
+// to 150 keV in the Compton sampler) by its Taylor series to e^7 (relative
+// error below 3e-7 there), without the cancellation of 1 - exp(e); below
+// -0.47, 1 - exp(e) > 0.37 has no cancellation and is evaluated directly.
 __device__ __forceinline__ float one_minus_exp(float e) {
+    if (e < -0.47f) return 1.0f - fast_exp(e);
     float t = 1.0f + e * (1.0f / 7.0f);
     t = 1.0f + e * (1.0f / 6.0f) * t;
     t = 1.0f + e * (1.0f / 5.0f) * t;
@@ -67,7 +71,15 @@ __device__ __forceinline__ float one_minus_exp(float e) {
     t = 1.0f + e * 0.5f * t;
     return -e * t;
 }
-__device__ __forceinline__ float fast_exp(float x) { return __builtin_amdgcn_exp2f(x * 1.4426950408889634f); }
+
+// A voxel density as the kernels use it: negative, NaN and infinite values
+// count as 0 (the kernels that read them also set the input-error bit).
+__device__ __forceinline__ bool density_ok(float r) { return r >= 0.0f && r <= 3.402823466e38f; }
+__device__ __forceinline__ float clean_density(float r) { return density_ok(r) ? r : 0.0f; }
+
+// Input-error bits, or-ed into a call's status word.
+enum : unsigned int { kErrDensity = 1u, kErrMaterial = 2u, kErrWeights = 4u };
+
 // sin / cos of 2 pi r (the hardware unit takes revolutions)
 __device__ __forceinline__ float sin_rev(float r) { return __builtin_amdgcn_sinf(r); }
 __device__ __forceinline__ float cos_rev(float r) { return __builtin_amdgcn_cosf(r); }
@@ -115,9 +127,10 @@ struct DSource {
     int spec_rows;            // 1, or nu: the spectrum of detector column iu is row iu
 };
 
-// One job, as the kernels read it (global memory, 128 bytes).
+// One job, as the kernels read it (global memory, 112 bytes).
 struct alignas(16) DJob {
-    float Sx, Sy, Sz, pad0;
+    float Sx, Sy, Sz;
+    uint32_t first;           // first photon index of the job
     float Px, Py, Pz, pad1;
     float nx, ny, nz, pad2;   // detector normal
     float ux, uy, uz, pad3;   // u axis; v axis is +z
@@ -246,7 +259,7 @@ __device__ __forceinline__ float scatter_angle(bool is_rayleigh, uint32_t pid, u
         } else {
             float tau, omt;   // tau and 1 - tau, the latter without cancellation
             if (b0 * (a1 + a2) < a1) {
-                const float e = -a1 * b1;               // in [-ln 3, 0]; |e| <= 0.47 for E <= 150 keV
+                const float e = -a1 * b1;               // in [-ln(1 + 2k), 0]; |e| <= 0.47 for E <= 150 keV
                 omt = one_minus_exp(e);
                 tau = 1.0f - omt;
             } else {

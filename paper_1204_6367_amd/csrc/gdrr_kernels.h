@@ -268,7 +268,7 @@ __device__ __forceinline__ void tally_add(const KParams& P, const DJob& J, int c
 template <int MODE>
 __device__ __forceinline__ void trace_out(const KParams& P, const Photon& ph, int cls, int pixel) {
     if (MODE != kModeTrace) return;
-    const uint32_t i = ph.pid;
+    const uint32_t i = ph.pid - P.jobs[ph.job].first;
     if (P.t_cls) P.t_cls[i] = (int8_t)cls;
     if (P.t_pixel) P.t_pixel[i] = pixel;
     if (P.t_e) P.t_e[i] = ph.E;
@@ -595,8 +595,9 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
                     const unsigned long long nph = (unsigned long long)J.n_lo | ((unsigned long long)J.n_hi << 32);
                     const unsigned long long first = (c - P.chunk_prefix[w_job]) * (unsigned long long)P.chunk;
                     const unsigned long long last = first + (unsigned long long)P.chunk < nph ? first + P.chunk : nph;
-                    w_next = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)first);
-                    w_end = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)last);
+                    // photon indices J.first + [first, last); J.first + nph < 2^32
+                    w_next = (uint32_t)__builtin_amdgcn_readfirstlane((int)(J.first + (uint32_t)first));
+                    w_end = (uint32_t)__builtin_amdgcn_readfirstlane((int)(J.first + (uint32_t)last));
                     const int v = __builtin_amdgcn_readfirstlane(J.vol);
                     if (v != w_vol) {
                         if (n_dead == 64) w_vol = v; else w_hold = 1;
@@ -671,7 +672,7 @@ struct MajParams {
     const float* density;
     const uint8_t* material;
     int nx, ny, nz;
-    int interp;
+    int interp, n_mat;
     unsigned int* rho_max;       // [256] float bits, zeroed
     unsigned int* present;       // [256], zeroed
     unsigned int* error;         // error word
@@ -685,11 +686,15 @@ __global__ __launch_bounds__(256) void rho_max_kernel(MajParams M) {
     __syncthreads();
     const long long n = (long long)M.nx * M.ny * M.nz;
     const long long nxy = (long long)M.nx * M.ny;
+    unsigned int err = 0u;
     for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < n;
          v += (long long)gridDim.x * blockDim.x) {
-        const int m = M.material[v];
+        // invalid inputs as the transport reads them: density 0, material n_mat - 1
+        const int mr = M.material[v];
+        const int m = min(mr, M.n_mat - 1);
+        if (mr != m) err |= kErrMaterial;
         float r = M.density[v];
-        if (!(r >= 0.0f) || isinf(r)) { atomicOr(M.error, 1u); r = 0.0f; }
+        if (!density_ok(r)) { err |= kErrDensity; r = 0.0f; }
         if (M.interp) {
             const int z = (int)(v / nxy), y = (int)((v / M.nx) % M.ny), x = (int)(v % M.nx);
             for (int dz = -1; dz <= 1; ++dz) {
@@ -698,7 +703,7 @@ __global__ __launch_bounds__(256) void rho_max_kernel(MajParams M) {
                     const int yy = min(max(y + dy, 0), M.ny - 1);
                     const float* row = M.density + (long long)zz * nxy + (long long)yy * M.nx;
                     for (int dx = -1; dx <= 1; ++dx) {
-                        const float q = row[min(max(x + dx, 0), M.nx - 1)];
+                        const float q = clean_density(row[min(max(x + dx, 0), M.nx - 1)]);
                         r = q > r ? q : r;
                     }
                 }
@@ -707,6 +712,7 @@ __global__ __launch_bounds__(256) void rho_max_kernel(MajParams M) {
         atomicMax(&s_max[m], __float_as_uint(r));
         s_pres[m] = 1u;
     }
+    if (err) atomicOr(M.error, err);
     __syncthreads();
     if (s_pres[threadIdx.x]) {
         atomicMax(&M.rho_max[threadIdx.x], s_max[threadIdx.x]);
@@ -737,8 +743,6 @@ __global__ __launch_bounds__(256) void majorant_kernel(MajFinParams F) {
         }
         F.out[j] = __double2float_ru(best * F.scale);
     }
-    if (blockIdx.x == 0 && threadIdx.x < 256 - F.n_mat && F.present[F.n_mat + threadIdx.x])
-        atomicOr(F.error, 2u);   // material index out of range
 }
 
 // ---------------------------------------------------------------------------
@@ -767,7 +771,7 @@ __global__ __launch_bounds__(256) void macro_kernel(MacroParams M) {
             for (int y = y0; y <= y1; ++y) {
                 const long long row = ((long long)z * M.ny + y) * M.nx;
                 for (int x = x0; x <= x1; ++x) {
-                    r = fmaxf(r, M.density[row + x]);
+                    r = fmaxf(r, clean_density(M.density[row + x]));
                     mask |= 1u << min((int)M.material[row + x], M.n_mat - 1);
                 }
             }
@@ -783,6 +787,7 @@ struct CellParams {
     const uint8_t* material;
     int nx, ny, nz, n_mat;
     CellRec* cells;
+    unsigned int* error;       // input-error bits (invalid densities or materials)
 };
 
 __global__ __launch_bounds__(256) void cells_kernel(CellParams C) {
@@ -790,18 +795,22 @@ __global__ __launch_bounds__(256) void cells_kernel(CellParams C) {
     for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x) {
         const int i = (int)(t % cx) - 1, j = (int)((t / cx) % cy) - 1, k = (int)(t / (cx * cy)) - 1;
         uint32_t d[8];
-        uint32_t m0 = 0u;
+        uint32_t m0 = 0u, err = 0u;
         bool same = true;
         for (int c = 0; c < 8; ++c) {
             const int x = min(max(i + (c & 1), 0), C.nx - 1);
             const int y = min(max(j + ((c >> 1) & 1), 0), C.ny - 1);
             const int z = min(max(k + (c >> 2), 0), C.nz - 1);
             const long long v = ((long long)z * C.ny + y) * C.nx + x;
-            d[c] = __float_as_uint(C.density[v]) & 0x7FFFFFFFu;
+            const float rho = C.density[v];
+            if (!density_ok(rho)) err |= kErrDensity;
+            d[c] = __float_as_uint(clean_density(rho)) & 0x7FFFFFFFu;   // (-0 loses its sign too)
             const uint32_t m = C.material[v];
+            if (m >= (uint32_t)C.n_mat) err |= kErrMaterial;
             if (c == 0) m0 = m;
             same = same && m == m0;
         }
+        if (err) atomicOr(C.error, err);
         if (!same) {
             d[0] |= 0x80000000u;
         } else {
@@ -862,7 +871,7 @@ __global__ __launch_bounds__(1024) void cdf_kernel(SrcPrepParams S) {
         run += (double)w[i];
         cdf[i] = run / total;
     }
-    if (t == 0 && (bad || !(total > 0.0))) atomicOr(S.error, 4u);
+    if (t == 0 && (bad || !(total > 0.0))) atomicOr(S.error, kErrWeights);
 }
 
 __global__ __launch_bounds__(256) void guide_kernel(SrcPrepParams S) {
@@ -901,14 +910,15 @@ struct FinParams {
     const unsigned long long* tally;
     double* out;
     const long long* out_off;   // [n_jobs] double element offsets in `out`
-    uint32_t flags;
+    uint32_t flags;             // GDRR_TALLY_SUMSQ 2, GDRR_ACCUMULATE 4, GDRR_RESUME 32
 };
 
 __global__ __launch_bounds__(256) void finalize_kernel(FinParams F) {
     const int k = blockIdx.y;
     const DJob& J = F.jobs[k];
     const int npix = J.nu * J.nv;
-    const double n = (double)J.n_lo + 4294967296.0 * (double)J.n_hi;
+    // per source photon of the run: a resumed run's sums cover [0, first + n)
+    const double n = (double)J.n_lo + 4294967296.0 * (double)J.n_hi + ((F.flags & 32u) ? (double)J.first : 0.0);
     const double inv = n > 0.0 ? 1.0 / n : 0.0;
     const bool sumsq = (F.flags & 2u) != 0, acc = (F.flags & 4u) != 0;
     double* out = F.out + F.out_off[k];

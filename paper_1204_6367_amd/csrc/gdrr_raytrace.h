@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kRtBlock) void raytrace_kernel(RtParams P) {
                     cur = m;
                     acc = 0.0f;
                 }
-                acc += h * dens[v];
+                acc += h * clean_density(dens[v]);
             }
         } else {
             // software-pipelined: the next interval's cell record is read while
@@ -233,6 +233,25 @@ __global__ __launch_bounds__(kRtBlock) void raytrace_kernel(RtParams P) {
     *o = P.accumulate ? *o + val : val;
 }
 
+// Input check of a volume the ray tracer reads without cell records (no
+// interpolation): the status bits of invalid densities and materials.
+struct VolCheckParams {
+    const float* density;
+    const uint8_t* material;
+    long long n;
+    int n_mat;
+    unsigned int* error;
+};
+
+__global__ __launch_bounds__(256) void volume_check_kernel(VolCheckParams C) {
+    unsigned int err = 0u;
+    for (long long v = blockIdx.x * (long long)blockDim.x + threadIdx.x; v < C.n; v += (long long)gridDim.x * blockDim.x) {
+        if (!density_ok(C.density[v])) err |= kErrDensity;
+        if (C.material[v] >= C.n_mat) err |= kErrMaterial;
+    }
+    if (err) atomicOr(C.error, err);
+}
+
 // Per source: the channel weights phi_k r(E_k) / sum phi (workgroup r: row r
 // of a joint source), the table 0.1 mu_tot(m, E_k) (linear in E between grid
 // points) and 1 / sum w (workgroup 0).
@@ -248,6 +267,7 @@ struct RtPrepParams {
     float* coef;
     float* tab;
     double* inv_wsum;
+    unsigned int* error;          // input-error bits (invalid spectrum or fluence weights)
 };
 
 __global__ __launch_bounds__(256) void raytrace_prep_kernel(RtPrepParams R) {
@@ -256,9 +276,19 @@ __global__ __launch_bounds__(256) void raytrace_prep_kernel(RtPrepParams R) {
     const float* phi = R.spec_p + (size_t)row * R.n_spec;
     float* coef = R.coef + (size_t)row * R.n_spec;
     double sp = 0.0, sw = 0.0;
-    for (int k = threadIdx.x; k < R.n_spec; k += 256) sp += (double)phi[k];
+    bool bad = false;
+    for (int k = threadIdx.x; k < R.n_spec; k += 256) {
+        const double x = (double)phi[k];
+        bad = bad || !(x >= 0.0) || isinf(x);
+        sp += x;
+    }
     if (row == 0)
-        for (int k = threadIdx.x; k < R.npix; k += 256) sw += (double)R.fluence[k];
+        for (int k = threadIdx.x; k < R.npix; k += 256) {
+            const double x = (double)R.fluence[k];
+            bad = bad || !(x >= 0.0) || isinf(x);
+            sw += x;
+        }
+    if (bad) atomicOr(R.error, kErrWeights);
     red[0][threadIdx.x] = sp;
     red[1][threadIdx.x] = sw;
     __syncthreads();
@@ -271,6 +301,7 @@ __global__ __launch_bounds__(256) void raytrace_prep_kernel(RtPrepParams R) {
     }
     const double psum = red[0][0], wsum = red[1][0];
     if (row == 0 && threadIdx.x == 0) R.inv_wsum[0] = wsum > 0.0 ? 1.0 / wsum : 0.0;
+    if (threadIdx.x == 0 && (!(psum > 0.0) || (row == 0 && !(wsum > 0.0)))) atomicOr(R.error, kErrWeights);
     for (int k = threadIdx.x; k < R.n_spec; k += 256) {
         const double E = (double)R.spec_e[k];
         const double g = (E - R.e0) / R.de;

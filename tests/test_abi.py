@@ -51,7 +51,7 @@ int main(void) {
     F(gdrr_volume, density) F(gdrr_volume, material) F(gdrr_volume, macro) F(gdrr_volume, macro_margin)
     F(gdrr_physics, mu_mass) F(gdrr_physics, response) F(gdrr_physics, rayleigh_x0_invA) F(gdrr_physics, e_cut_kev)
     F(gdrr_source, spec_e_kev) F(gdrr_source, fu) F(gdrr_source, fluence) F(gdrr_source, spec_rows)
-    F(gdrr_job, geom) F(gdrr_job, n_photons) F(gdrr_job, job_id) F(gdrr_job, tally_offset)
+    F(gdrr_job, geom) F(gdrr_job, n_photons) F(gdrr_job, job_id) F(gdrr_job, first_photon) F(gdrr_job, tally_offset)
     F(gdrr_tuning, defer) F(gdrr_tuning, scheme)
     return 0;
 }
@@ -109,6 +109,10 @@ def _call(abi, vol, phys, src, geom, n=1000, ws_bytes=1 << 30, tally=0x2000):
                          setattr(s, "fv", 1), setattr(g, "nu", 4097), setattr(g, "nv", 1)), "2^24"),
     (lambda v, p, s, g: setattr(g, "aid_mm", 5.0), "between the source and the detector"),
     (lambda v, p, s, g: setattr(g, "du_mm", 0.0), "detector grid"),
+    # 1024 x 1024 x 2047 voxels (< 2^31) but 1025 x 1025 x 2048 cells (> 2^31): 32-bit cell indices would wrap
+    (lambda v, p, s, g: (setattr(v, "nx", 1024), setattr(v, "ny", 1024), setattr(v, "nz", 2047),
+                         setattr(v, "dx_mm", 0.01), setattr(v, "dy_mm", 0.01), setattr(v, "dz_mm", 0.01)),
+     "interpolation cells"),
 ])
 def test_invalid_arguments_are_rejected(abi, breaker, needle):
     vol, phys, src, geom = _valid_structs(abi)
@@ -199,3 +203,52 @@ def test_denoise_and_noise_reject_bad_arguments_on_the_host(abi):
     assert nz(npix=0) == abi.GDRR_EINVAL
     assert nz(ps=50) == abi.GDRR_EINVAL and "stride" in msg()
     assert nz(alpha=float("inf")) == abi.GDRR_EINVAL
+
+
+def _batch_structs(abi, first=0, n=1000):
+    vol, phys, src, geom = _valid_structs(abi)
+    job = abi.Job()
+    job.volume, job.source, job.geom, job.n_photons, job.job_id, job.first_photon = 0, 0, geom, n, 0, first
+    return vol, phys, src, job
+
+
+def test_photon_index_range_is_checked(abi):
+    """first_photon + n_photons must stay below 2^32 (the Philox counter word)."""
+    L = abi.lib()
+    vol, phys, src, job = _batch_structs(abi, first=(1 << 32) - 1000, n=1000)
+    rc = L.gdrr_mc_project_batch(C.byref(vol), 1, C.byref(phys), C.byref(src), 1, C.byref(job), 1, None, 1, 1,
+                                 None, 0x2000, 0x3000, 1 << 30, None)
+    assert rc == abi.GDRR_EINVAL and "2^32" in L.gdrr_last_error().decode()
+
+
+def test_backward_checks_every_argument_before_touching_the_gradient(abi):
+    """NULL arrays and bad indices are rejected on the host; nothing is launched
+    (the gradient pointer is a dummy that a launch would fault on)."""
+    L = abi.lib()
+    vol, phys, src, job = _batch_structs(abi)
+    msg = lambda: L.gdrr_last_error().decode()
+    call = lambda vols, nv=1, srcs=None, jobs=None, volume=0, maj=0x4000, adj=0x5000, grad=0x6000: \
+        L.gdrr_mc_backward(vols, nv, C.byref(phys), srcs if srcs is not None else C.byref(src), 1,
+                           jobs if jobs is not None else C.byref(job), 1, volume, maj, 1, 1, None, adj, grad,
+                           0x3000, 1 << 30, None)
+    assert call(None) == abi.GDRR_EINVAL and "NULL" in msg()
+    assert call(C.byref(vol), volume=1) == abi.GDRR_EINVAL and "volume" in msg()
+    assert call(C.byref(vol), maj=None) == abi.GDRR_EINVAL and "majorants" in msg()
+    assert call(C.byref(vol), grad=None) == abi.GDRR_EINVAL
+    bad = abi.Volume(8, 8, 0, 2.0, 2.0, 2.0, 0x1000, 0x1000, 0, 0.0)
+    assert call(C.byref(bad)) == abi.GDRR_EINVAL and "dimensions" in msg()
+
+
+def test_noise_scale_in_the_library(abi):
+    """alpha = sqrt(n_sim / (zeta I)) (Sec. 2.6), with the paper's calibration
+    numbers: k = sqrt(n_sim / zeta) = 0.3074 for n_sim = 5e8, zeta = 5.2913e9."""
+    L = abi.lib()
+    a = C.c_double(0.0)
+    assert L.gdrr_noise_scale(5e8, 5.2913e9, 1.0, C.byref(a)) == abi.GDRR_OK
+    assert abs(a.value - 0.3074) < 5e-4
+    assert L.gdrr_noise_scale(5e8, 5.2913e9, 4.0, C.byref(a)) == abi.GDRR_OK
+    assert abs(a.value - 0.3074 / 2) < 3e-4
+    for bad in ((0.0, 1.0, 1.0), (1.0, -1.0, 1.0), (1.0, 1.0, float("nan")), (float("inf"), 1.0, 1.0)):
+        assert L.gdrr_noise_scale(*bad, C.byref(a)) == abi.GDRR_EINVAL
+    assert L.gdrr_noise_scale(1.0, 1.0, 1.0, None) == abi.GDRR_EINVAL
+    assert L.gdrr_input_status(None, None) == abi.GDRR_EINVAL

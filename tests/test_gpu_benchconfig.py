@@ -1,0 +1,271 @@
+"""Parity in the configurations the benchmark runs.
+
+* Transport: the three phantoms of the multi-phantom workload (512x512x256,
+  256x256x160, 128x128x64) with local majorants on cubes of about 40 mm
+  (41, 21 and 10 voxels, all records staged in LDS), the adjoint volume's
+  margin 0.1, one persistent launch of block 512 and defer 16, every job at its
+  full photon count: the batched tallies equal the sums of the traced
+  histories, and sampled histories equal the oracle's one by one.
+* 360 angles of the 256x256x160 projection phantom in one launch equal 360
+  single projections, bit for bit.
+* The adjoint at the 128x128x96 adjoint phantom and at the benchmark's adjoint
+  phantom (256x256x160, cubes of 21 voxels, margin 0.1) against the oracle's
+  float64 adjoint on the same streams.
+* Central finite differences with common random numbers on 64 voxels of the
+  128x128x96 phantom, 32 replicas, against the adjoint.
+"""
+import math
+import time
+
+import numpy as np
+import pytest
+
+from paper_1204_6367_amd import workloads as W
+
+from test_gpu_parity import compare_histories
+
+pytestmark = pytest.mark.gpu
+
+CUBE_MM = 40.0                 # the benchmark's local-majorant cube edge
+FWD_MARGIN = 2.0**-20
+ADJ_MARGIN = 0.1
+BENCH_TUNE = dict(block=512, defer=16)
+
+
+def log(*a):
+    print(*a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1204_6367_amd import api
+    return api
+
+
+def cube_voxels(spacing):
+    return max(1, int(round(CUBE_MM / min(spacing))))
+
+
+@pytest.fixture(scope="module")
+def multi(gpu):
+    t = time.time()
+    phs = [W.ellipsoid_phantom(shape, sp, seed) for shape, sp, seed, _, _ in W.MULTI_PHANTOMS]
+    log(f"phantoms built in {time.time() - t:.1f}s")
+    return phs
+
+
+@pytest.mark.timeout(600)
+def test_benchmark_transport_configuration(gpu, multi):
+    import torch
+    import oracle
+    geom = W.Geometry(**W.PELVIS_DET)
+    srcw = W.pelvis_source(geom)
+    physw = W.physics_for(multi[0])
+    phys = gpu.DevicePhysics(physw.mu_mass, physw.grid.e0_kev, physw.grid.de_kev)
+    src = gpu.DeviceSource(srcw.spec_e, srcw.spec_p, srcw.fluence)
+    vols, macros, margins = [], [], []
+    for v, ph in enumerate(multi):
+        m, g = cube_voxels(ph.spacing_mm), ADJ_MARGIN if v == 1 else FWD_MARGIN
+        vols.append(gpu.DeviceVolume(ph.density, ph.material, ph.spacing_mm).local_majorants(m, g))
+        macros.append(m)
+        margins.append(g)
+    assert macros == [41, 21, 10]
+    cubes = sum(math.prod(-(-n // m) for n in ph.shape) for ph, m in zip(multi, macros))
+    assert cubes * 8 <= 32 << 10                  # every volume's cube records fit the LDS copy
+    # one full-size job per phantom, plus small jobs of every phantom between them
+    jobs, full = [], []
+    for v, (_, _, _, _, nph) in enumerate(W.MULTI_PHANTOMS):
+        full.append(len(jobs))
+        jobs.append(gpu.JobSpec(geom.replace(phi_rad=0.7 + 1.9 * v), nph, 100 + v, volume=v))
+        jobs.append(gpu.JobSpec(geom.replace(phi_rad=2.5 + v), 2_000_000, 200 + v, volume=v))
+    b = gpu.Batch(vols, phys, [src], jobs)
+    t = time.time()
+    views = b.tally_views(b.project(seed=1, sumsq=False, tune=BENCH_TUNE))
+    torch.cuda.synchronize()
+    log(f"batched launch {time.time() - t:.2f}s")
+    for v, k in enumerate(full):
+        j = jobs[k]
+        tr = gpu.trace(vols[v], phys, src, j.geom, j.n_photons, seed=1, job_id=j.job_id)
+        assert int((tr["cls"] < 0).sum()) == 0
+        npix = geom.nu * geom.nv
+        q = torch.round(tr["e_final"].double() * 2**20)
+        tb = views[k].cpu().numpy()
+        for c, plane in ((0, 0), (1, 2)):
+            sel = tr["cls"] == c
+            acc = torch.zeros(npix, dtype=torch.float64, device="cuda")
+            acc.index_add_(0, tr["pixel"][sel].long(), q[sel])
+            acc = (acc / 2**20 / j.n_photons).view(geom.nv, geom.nu).cpu().numpy()
+            assert np.allclose(acc, tb[plane], rtol=1e-12, atol=0), (v, c)
+        ids = np.sort(np.random.default_rng(40 + v).choice(j.n_photons, 3000, replace=False)).astype(np.int64)
+        g = {key: val.index_select(0, torch.tensor(ids, device="cuda")) for key, val in tr.items()}
+        del tr
+        prob = W.Problem(multi[v], physw, srcw, j.geom, j.n_photons)
+        p = oracle.Problem.from_workload(prob).local_majorants(macros[v], margins[v])
+        o = oracle.mc_histories(p, 1, ids.astype(np.uint32), None, job_id=j.job_id)
+        frac, _ = compare_histories(g, o)
+        log(f"phantom {v}: traced sums = batched tallies; identical sampled histories {frac:.4f}")
+        assert frac >= 0.99
+
+
+@pytest.mark.timeout(600)
+def test_360_angles_equal_single_projections(gpu):
+    """The 360-angle workload (1e7 photons per angle, 256x256x160 phantom, local
+    majorants) in one launch, against 360 single projections: bitwise."""
+    import torch
+    prob = W.pelvis_problem(10_000_000)
+    vol, phys, src = gpu.upload(prob)
+    vol.local_majorants(cube_voxels(prob.phantom.spacing_mm))
+    angles = np.deg2rad(np.arange(360.0))
+    jobs = [gpu.JobSpec(prob.geom.replace(phi_rad=float(a)), 10_000_000, k) for k, a in enumerate(angles)]
+    b = gpu.Batch([vol], phys, [src], jobs)
+    t = time.time()
+    views = b.tally_views(b.project(seed=1, tune=BENCH_TUNE))
+    torch.cuda.synchronize()
+    log(f"360 angles batched {time.time() - t:.2f}s")
+    out = torch.zeros(4, prob.geom.nv, prob.geom.nu, dtype=torch.float64, device="cuda")
+    for k, j in enumerate(jobs):
+        gpu.project(vol, phys, src, j.geom, j.n_photons, seed=1, job_id=j.job_id, out=out)
+        assert torch.equal(out, views[k]), k
+    log("360 single projections equal the batch")
+
+
+def pooled(x, f=4):
+    nz, ny, nx = x.shape
+    x = x[: nz // f * f, : ny // f * f, : nx // f * f]
+    return x.reshape(nz // f, f, ny // f, f, nx // f, f).sum((1, 3, 5))
+
+
+def adjoint_case(gpu, ph, n, macro, margin, seed_adj, phi=0.4, job_id=3):
+    """GPU and oracle adjoints of one projection with seeded adjoint weights on
+    the scatter image, and the fraction of sampled histories identical on both
+    sides."""
+    import torch
+    import oracle
+    geom = W.Geometry(**W.PELVIS_DET).replace(phi_rad=phi)
+    prob = W.Problem(ph, W.physics_for(ph), W.pelvis_source(geom), geom, n)
+    vol, phys, src = gpu.upload(prob)
+    vol.local_majorants(macro, margin)
+    adj = np.zeros((2, geom.nv, geom.nu))
+    adj[1] = np.random.default_rng(seed_adj).normal(size=(geom.nv, geom.nu))
+    adj[0] = 0.1 * np.random.default_rng(seed_adj + 1).normal(size=(geom.nv, geom.nu))
+    b = gpu.Batch([vol], phys, [src], [gpu.JobSpec(geom, n, job_id)])
+    p = oracle.Problem.from_workload(prob).local_majorants(macro, margin)
+    if macro:
+        maj_g = torch.zeros(1, phys.n_e - 1, dtype=torch.float32, device="cuda")   # unused with local majorants
+        maj_o = None
+    else:
+        maj_g = gpu.majorant(vol, phys, True, margin)[None]
+        maj_o = oracle.majorant(p, True, margin=margin)
+    t = time.time()
+    gg = b.backward(torch.tensor(adj[None], device="cuda"), maj_g, seed=1).cpu().numpy()
+    log(f"gpu adjoint {time.time() - t:.2f}s")
+    t = time.time()
+    go = oracle.mc_backward(p, 1, n, adj, maj_o, job_id=job_id)
+    log(f"oracle adjoint {time.time() - t:.2f}s")
+    ids = np.sort(np.random.default_rng(seed_adj).choice(n, 20000, replace=False)).astype(np.uint32)
+    tr = gpu.trace(vol, phys, src, geom, n, seed=1, job_id=job_id, majorant_tab=None if macro else maj_g[0])
+    g = {key: val.index_select(0, torch.tensor(ids.astype(np.int64), device="cuda")) for key, val in tr.items()}
+    o = oracle.mc_histories(p, 1, ids, maj_o, job_id=job_id)
+    frac, _ = compare_histories(g, o)
+    full = float(np.linalg.norm(gg - go) / np.linalg.norm(go))
+    pool = float(np.linalg.norm(pooled(gg) - pooled(go)) / np.linalg.norm(pooled(go)))
+    return full, pool, 1.0 - frac
+
+
+@pytest.mark.parametrize("macro", [0, 13])
+def test_adjoint_at_the_adjoint_phantom(gpu, macro):
+    """128x128x96 at 3 mm, 120 kVp + bowtie, 256x192 detector, 2e6 histories,
+    single majorant or cubes of ~40 mm, margin 0.1."""
+    ph = W.adjoint_problem(1)[0].phantom
+    full, pool, div = adjoint_case(gpu, ph, 2_000_000, macro, ADJ_MARGIN, 50)
+    log(f"adjoint 128x128x96 macro {macro}: rel L2 {full:.4f} (4^3 pooled {pool:.4f}); "
+        f"diverged sampled histories {div:.5f}")
+    assert pool <= 0.02
+    assert full <= 0.02
+
+
+def test_adjoint_at_the_benchmark_adjoint_phantom(gpu, multi):
+    """256x256x160 at 1.95 mm with cubes of 21 voxels and margin 0.1, as the benchmark's adjoint."""
+    ph = multi[1]
+    full, pool, div = adjoint_case(gpu, ph, 2_000_000, cube_voxels(ph.spacing_mm), ADJ_MARGIN, 60, phi=1.1,
+                                   job_id=120)
+    log(f"adjoint 256x256x160 cubes 21: rel L2 {full:.4f} (4^3 pooled {pool:.4f}); "
+        f"diverged sampled histories {div:.5f}")
+    assert pool <= 0.02
+    assert full <= 0.02
+
+
+@pytest.mark.timeout(900)
+def test_crn_finite_differences_at_the_adjoint_phantom(gpu):
+    """The adjoint of L = sum_p a_p S_p (a = expected scatter minus the
+    perturbed phantom's, from oracle runs) against central differences with
+    common random numbers (same seed, job and majorant for rho_v +- h, h = 0.1
+    rho_v) on 64 voxels drawn (seed 33) from non-air voxels in the beam; 32
+    replicas (seeds).  Per voxel z = mean(FD - adjoint) / its standard error."""
+    import torch
+    import oracle
+    prob, target = W.adjoint_problem(10_000_000)
+    g = prob.geom
+    # weights of the linear loss from oracle forwards (independent of the GPU path)
+    po = oracle.Problem.from_workload(prob)
+    pt = oracle.Problem.from_workload(W.Problem(target, prob.physics, prob.source, g, 1))
+    s_now = oracle.mc_project(po, 101, 2_000_000)["tally"][2]
+    s_tgt = oracle.mc_project(pt, 102, 2_000_000)["tally"][2]
+    a = s_now - s_tgt
+    a /= np.abs(a).max()
+    vol, phys, src = gpu.upload(prob)
+    adj = torch.zeros(1, 2, g.nv, g.nu, dtype=torch.float64, device="cuda")
+    adj[0, 1] = torch.tensor(a, device="cuda")
+    n = prob.n_photons
+    b = gpu.Batch([vol], phys, [src], [gpu.JobSpec(g, n, 0)])
+    ph = prob.phantom
+    nz, ny, nx = ph.shape
+    zc = (np.arange(nz) + 0.5 - nz / 2) * ph.spacing_mm[2]
+    yc = (np.arange(ny) + 0.5 - ny / 2) * ph.spacing_mm[1]
+    xc = (np.arange(nx) + 0.5 - nx / 2) * ph.spacing_mm[0]
+    Z, Y, X = np.meshgrid(zc, yc, xc, indexing="ij")
+    beam = (np.abs(Z) < 80.0) & (X * X + Y * Y < 100.0**2) & (ph.material > 0)
+    voxels = np.random.default_rng(33).choice(np.flatnonzero(beam.ravel()), 64, replace=False)
+    base = vol.density.clone()
+    # one majorant for every run, valid for rho_v + h
+    maj = gpu.majorant(vol, phys, True, margin=0.25)[None]
+    reps = 32
+    d = np.zeros((reps, 64))
+    fd_all = np.zeros((reps, 64))
+    t = time.time()
+    for r in range(reps):
+        seed = 1000 + r
+        grad = b.backward(adj, maj, seed=seed).cpu().numpy().ravel()[voxels]
+        fd = torch.zeros(64, dtype=torch.float64, device="cuda")
+        work = base.clone()
+        flat = work.view(-1)
+        for i, v in enumerate(voxels):
+            rho = float(base.view(-1)[v])
+            h = 0.1 * rho
+            flat[v] = rho + h
+            sp = b.tally_views(b.project(seed=seed, sumsq=False, majorants=maj, densities=[work]))[0][2].clone()
+            flat[v] = rho - h
+            sm = b.tally_views(b.project(seed=seed, sumsq=False, majorants=maj, densities=[work]))[0][2]
+            flat[v] = rho
+            fd[i] = ((sp - sm) * adj[0, 1]).sum() / (2 * h)
+        fd = fd.cpu().numpy()
+        d[r] = fd - grad
+        fd_all[r] = fd
+        if r % 8 == 7:
+            log(f"replica {r + 1}/{reps} ({time.time() - t:.0f}s)")
+    z = d.mean(0) / (d.std(0, ddof=1) / math.sqrt(reps) + 1e-300)
+    over = int((np.abs(z) > 3).sum())
+    log("z", np.round(z, 2))
+    log(f"|z| > 3: {over} of 64; max |z| {np.abs(z).max():.2f}; mean z^2 {np.mean(z * z):.3f}")
+    # per voxel the paired differences follow Student's t with 31 degrees of
+    # freedom under parity: P(|t| > 3) = 0.0053, so 64 voxels show 0.34 exceedances
+    # on average and 3 or more with probability 0.004
+    assert over <= 2
+    assert np.abs(z).max() <= 4.5
+    assert np.mean(z * z) <= 1.6
+    fd_mean = fd_all.mean(0)
+    fd_se = fd_all.std(0, ddof=1) / math.sqrt(reps)
+    log(f"FD standard error / |FD| (median) {np.median(fd_se / (np.abs(fd_mean) + 1e-300)):.3f}")

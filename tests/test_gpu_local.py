@@ -166,7 +166,7 @@ def test_local_adjoint_matches_oracle(gpu):
     assert rel <= 0.02
 
 
-def test_queue_scheme_rejects_local_majorants(gpu):
+def test_unknown_scheme_rejected(gpu):
     prob = body_problem(1000)
     vol, phys, src = gpu.upload(prob)
     vol.local_majorants(4)
