@@ -189,10 +189,14 @@ CUBE_MM = 40.0
 SOURCE = "factorised"        # or "joint": one spectrum per detector column
 
 
-def apply_majorant(vol, margin):
+ADJ_MARGIN = 0.1            # the adjoint volume's majorant margin (null-collision terms stay bounded)
+ADJ_RHO_MIN = 0.05          # and its cubes' density floor, g/cm^3 (float32 collision points in air cubes)
+
+
+def apply_majorant(vol, margin, rho_min=0.0):
     """Local majorants on cubes of about CUBE_MM (or the single per-energy majorant)."""
     if MAJORANT == "local":
-        vol.local_majorants(max(1, int(round(CUBE_MM / min(vol.spacing_mm)))), margin)
+        vol.local_majorants(max(1, int(round(CUBE_MM / min(vol.spacing_mm)))), margin, rho_min)
 
 
 def majorant_desc(vols):
@@ -244,8 +248,8 @@ def build_workload(name, api, W, torch):
             batch.project(seed=1, majorants=maj, out=tallies, tune=tune)
             return [api.last_kernel_ms()]
 
-        samples = [(prob, float(jobs[k].geom.phi_rad), jobs[k].job_id, vol.macro, vol.macro_margin)
-                   for k in (0, len(jobs) // 2)]
+        samples = [(prob, float(jobs[k].geom.phi_rad), jobs[k].job_id, vol.macro, vol.macro_margin,
+                    vol.macro_rho_min) for k in (0, len(jobs) // 2)]
         return dict(step=step, fwd=fwd, adj=0, samples=samples, adjoint=None, batch=batch, prob_of=lambda k: prob,
                     tallies=tallies,
                     config=dict(workload=name, phantom="256x256x160 @1.95x1.95x2.5mm ellipsoids",
@@ -285,9 +289,9 @@ def build_workload(name, api, W, torch):
                 jid += 1
         batch = api.Batch(vols, dphys, [dsrc], jobs)
         adj_batch = api.Batch(vols, dphys, [dsrc], [jobs[k] for k in adj_idx])
-        margins = [0.1 if v == adj_vol else 2.0**-20 for v in range(len(vols))]
+        margins = [ADJ_MARGIN if v == adj_vol else 2.0**-20 for v in range(len(vols))]
         for k, v in enumerate(vols):
-            apply_majorant(v, margins[k])
+            apply_majorant(v, margins[k], ADJ_RHO_MIN if k == adj_vol else 0.0)
         # target tallies S* of the perturbed phantom (Philox seed 2), not timed
         tgt_vol = api.DeviceVolume(phantoms[adj_vol][1].density, phantoms[adj_vol][1].material,
                                    phantoms[adj_vol][1].spacing_mm)
@@ -322,9 +326,10 @@ def build_workload(name, api, W, torch):
             k = next(i for i, j in enumerate(jobs) if j.volume == v)
             ph = phantoms[v][0]
             samples.append((W.Problem(ph, physw, srcw, jobs[k].geom, nph), float(jobs[k].geom.phi_rad),
-                            jobs[k].job_id, vols[v].macro, vols[v].macro_margin))
+                            jobs[k].job_id, vols[v].macro, vols[v].macro_margin, vols[v].macro_rho_min))
         adjoint = dict(problem=W.Problem(phantoms[adj_vol][0], physw, srcw, jobs[adj_idx[0]].geom, 1),
-                       job_id=jobs[adj_idx[0]].job_id, margin=0.1, macro=vols[adj_vol].macro)
+                       job_id=jobs[adj_idx[0]].job_id, margin=ADJ_MARGIN, macro=vols[adj_vol].macro,
+                       rho_min=vols[adj_vol].macro_rho_min)
         cfg = dict(workload=name, angles=len(jobs), adjoint_angles=len(adj_idx), tuning=tune, adjoint_tuning=adj_tune,
                    majorant=majorant_desc(vols),
                    detector="256x192 @1.552mm", spectrum=SPECTRUM_DESC[SOURCE],
@@ -498,8 +503,8 @@ def cpu_baseline(wl, budget_s=20.0):
     stats_acc = None
     done, spent = 0, 0.0
     per = max(1, len(wl["samples"]))
-    for prob, phi, jid, macro, margin in wl["samples"]:
-        p = oracle.Problem.from_workload(prob, phi_rad=phi).local_majorants(macro, margin)
+    for prob, phi, jid, macro, margin, rho_min in wl["samples"]:
+        p = oracle.Problem.from_workload(prob, phi_rad=phi).local_majorants(macro, margin, rho_min)
         n = 20000
         while True:                                  # grow the sample until ~budget/per seconds
             t = time.time()
@@ -523,8 +528,8 @@ def cpu_baseline(wl, budget_s=20.0):
     fwd_rate = done / spent
     # the same jobs on one thread, about a second each: the oracle's rate per core
     done1, spent1 = 0, 0.0
-    for prob, phi, jid, macro, margin in wl["samples"]:
-        p = oracle.Problem.from_workload(prob, phi_rad=phi).local_majorants(macro, margin)
+    for prob, phi, jid, macro, margin, rho_min in wl["samples"]:
+        p = oracle.Problem.from_workload(prob, phi_rad=phi).local_majorants(macro, margin, rho_min)
         n = 5000
         while True:
             t = time.time()
@@ -539,7 +544,7 @@ def cpu_baseline(wl, budget_s=20.0):
                fwd_rate_1=done1 / spent1, fwd_sample_1=done1)
     if wl["adjoint"] is not None:
         a = wl["adjoint"]
-        p = oracle.Problem.from_workload(a["problem"]).local_majorants(a["macro"], a["margin"])
+        p = oracle.Problem.from_workload(a["problem"]).local_majorants(a["macro"], a["margin"], a["rho_min"])
         mb = None if a["macro"] else oracle.majorant(p, True, margin=a["margin"])
         adj = np.zeros((2, p.nv, p.nu))
         adj[1] = 1.0
@@ -633,13 +638,13 @@ def main():
     if MAJORANT == "local" and not args.no_global_reference:
         # the same forward with one majorant per energy interval (the paper's Woodcock tracking), for reference
         b = wl["batch"]
-        saved = [(v.macro, v.macro_margin) for v in b.vols]
+        saved = [(v.macro, v.macro_margin, v.macro_rho_min) for v in b.vols]
         for v in b.vols:
             v.local_majorants(0)
         b.project(seed=1, sumsq=False, majorants=b.majorants(True), out=wl["tallies"])
         gms = api.last_kernel_ms()
-        for v, (m, g) in zip(b.vols, saved):
-            v.local_majorants(m, g)
+        for v, (m, g, r) in zip(b.vols, saved):
+            v.local_majorants(m, g, r)
         glob = dict(fwd_histories_per_s=round(wl["fwd"] / (gms * 1e-3), 1), transport_kernel_ms=round(gms, 3))
         log(f"global-majorant forward: {gms:.1f} ms")
     rt = None if args.no_raytrace else raytrace_leg(wl, api, torch, args.steps, not args.no_cpu_baseline)

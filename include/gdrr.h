@@ -94,7 +94,8 @@ typedef struct gdrr_volume {
     /* (nx+1)(ny+1)(nz+1) < 2^31 */
     /* Local majorants (not in the paper; 0 = off): the volume is cut into cubes of
      * `macro`^3 voxels (the last ones along an axis shorter), each with the bound
-     * (1 + macro_margin) rho_max max_m mu_tot(m, E) over the cube grown by one voxel;
+     * (1 + macro_margin) max(rho_max, macro_rho_min) max_m mu_tot(m, E), rho_max and
+     * the materials taken over the cube grown by one voxel;
      * a free flight spends an optical depth -ln(u) cube by cube and the collision
      * ladder runs against the bound of the cube it ends in.  Unbiased like the
      * single majorant, with far fewer null collisions in air and soft tissue; it uses
@@ -102,6 +103,13 @@ typedef struct gdrr_volume {
      * the `majorants` argument is not used for this volume.  1 <= macro <= 256. */
     int32_t macro;
     float macro_margin;        /* >= 0; 2^-20 for projections, 0.1-0.2 for the adjoint */
+    /* >= 0, g/cm^3: the least density a cube's bound assumes (0 for projections).  A
+     * cube of air alone gets a bound so small that one unit of optical depth spans
+     * metres; float32 rounding of the optical depth left after denser cubes then
+     * moves its collisions by a visible fraction of a voxel, and the adjoint's
+     * 1/rho terms of real collisions in air magnify that.  A floor of about 0.05
+     * keeps a free path in such cubes near a metre at a few more null collisions. */
+    float macro_rho_min;
 } gdrr_volume;
 
 /* Mass attenuation tables mu_k(i, E) of Sec. 2.1 on the grid

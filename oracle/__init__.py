@@ -56,7 +56,7 @@ class _Problem(C.Structure):
         ("sad", C.c_double), ("aid", C.c_double), ("phi", C.c_double), ("theta", C.c_double),
         ("nu", C.c_int32), ("nv", C.c_int32),
         ("du", C.c_double), ("dv", C.c_double),
-        ("macro", C.c_int32), ("macro_margin", C.c_double),
+        ("macro", C.c_int32), ("macro_margin", C.c_double), ("macro_rho_min", C.c_double),
     ]
 
 
@@ -154,10 +154,12 @@ class Problem:
                    g.theta_rad, g.nu, g.nv, g.du_mm, g.dv_mm, phys.response,
                    phys.rayleigh_x0, phys.e_cut_kev)
 
-    def local_majorants(self, macro: int, margin: float = 2.0**-20) -> "Problem":
-        """Switch the transport to local majorants on cubes of macro^3 voxels (0: back to the global one)."""
+    def local_majorants(self, macro: int, margin: float = 2.0**-20, rho_min: float = 0.0) -> "Problem":
+        """Switch the transport to local majorants on cubes of macro^3 voxels (0: back to the
+        global one); each cube's bound assumes a density of at least rho_min g/cm^3."""
         self.s.macro = int(macro)
         self.s.macro_margin = float(margin)
+        self.s.macro_rho_min = float(rho_min)
         return self
 
     @property

@@ -76,6 +76,7 @@ typedef struct {
     double du, dv;                     /* mm */
     int32_t macro;                     /* local majorants on cubes of macro^3 voxels; 0 = one global majorant */
     double macro_margin;               /* their relative margin */
+    double macro_rho_min;              /* the least density (g/cm^3) a cube's bound assumes */
 } or_problem;
 
 /* ------------------------------------------------------------------------ */
@@ -486,7 +487,8 @@ void or_rotate(const double d[3], double cost, double ph, double out[3])
 /* grown by one voxel.  A flight draws an optical depth tau = -ln u and      */
 /* spends it cube by cube along its line (each cube costs mbar_B times the   */
 /* length inside it); the collision point is where tau runs out, tested      */
-/* against that cube's mbar_B; running out of cubes is an escape.            */
+/* against that cube's mbar_B; running out of cubes is an escape.  rho_max   */
+/* may be raised to a floor macro_rho_min: any larger bound is still a bound. */
 /* ------------------------------------------------------------------------ */
 static int build_macro(const or_problem* p, or_ctx* c)
 {
@@ -507,7 +509,7 @@ static int build_macro(const or_problem* p, or_ctx* c)
                     lo[a] = clampi(b[a] * M - 1, 0, n[a] - 1);
                     hi[a] = clampi((b[a] + 1) * M, 0, n[a] - 1);     /* inclusive: one voxel beyond the cube */
                 }
-                double r = 0.0;
+                double r = p->macro_rho_min;
                 uint64_t mask = 0;
                 for (int z = lo[2]; z <= hi[2]; ++z)
                     for (int y = lo[1]; y <= hi[1]; ++y)
@@ -747,7 +749,8 @@ static int validate(const or_problem* p)
     for (int k = 0; k < p->n_spec; ++k)
         if (!(p->spec_e[k] >= p->e0 && p->spec_e[k] <= emax)) return -1;
     if (!(p->e_cut >= p->e0)) return -1;
-    if (p->macro < 0 || (p->macro > 0 && (p->n_mat > 64 || !(p->macro_margin >= 0.0)))) return -1;
+    if (p->macro < 0 || (p->macro > 0 && (p->n_mat > 64 || !(p->macro_margin >= 0.0) ||
+                                          !(p->macro_rho_min >= 0.0) || isinf(p->macro_rho_min)))) return -1;
     /* every voxel: a material of the table, a finite density >= 0 */
     size_t nvox = (size_t)p->nx * p->ny * p->nz;
     for (size_t v = 0; v < nvox; ++v)

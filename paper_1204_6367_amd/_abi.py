@@ -32,7 +32,7 @@ class Volume(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("dx_mm", C.c_float), ("dy_mm", C.c_float), ("dz_mm", C.c_float),
                 ("density", C.c_void_p), ("material", C.c_void_p),
-                ("macro", C.c_int32), ("macro_margin", C.c_float)]
+                ("macro", C.c_int32), ("macro_margin", C.c_float), ("macro_rho_min", C.c_float)]
 
 
 class Physics(C.Structure):

@@ -47,11 +47,12 @@ class DeviceVolume:
         self.material = _t(material, torch.uint8, dev)
         assert self.density.shape == self.material.shape and self.density.dim() == 3
         self.spacing_mm = tuple(float(s) for s in spacing_mm)
-        self.macro, self.macro_margin = 0, 2.0**-20
+        self.macro, self.macro_margin, self.macro_rho_min = 0, 2.0**-20, 0.0
 
-    def local_majorants(self, macro: int, margin: float = 2.0**-20) -> "DeviceVolume":
-        """Track with local majorants on cubes of macro^3 voxels (0: one majorant per energy interval)."""
-        self.macro, self.macro_margin = int(macro), float(margin)
+    def local_majorants(self, macro: int, margin: float = 2.0**-20, rho_min: float = 0.0) -> "DeviceVolume":
+        """Track with local majorants on cubes of macro^3 voxels (0: one majorant per energy
+        interval); each cube's bound assumes a density of at least rho_min g/cm^3."""
+        self.macro, self.macro_margin, self.macro_rho_min = int(macro), float(margin), float(rho_min)
         return self
 
     @property
@@ -62,7 +63,7 @@ class DeviceVolume:
         d = self.density if density is None else density
         nz, ny, nx = d.shape
         return _abi.Volume(nx, ny, nz, *self.spacing_mm, d.data_ptr(), self.material.data_ptr(), self.macro,
-                           self.macro_margin)
+                           self.macro_margin, self.macro_rho_min)
 
 
 class DevicePhysics:

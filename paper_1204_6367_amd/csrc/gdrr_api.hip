@@ -103,6 +103,8 @@ int check_volume(const gdrr_volume* v) {
     if (v->macro < 0 || v->macro > 256) return fail(GDRR_EINVAL, "volume macro must be in [0, 256]");
     if (v->macro > 0 && (!(v->macro_margin >= 0.0f) || !std::isfinite(v->macro_margin)))
         return fail(GDRR_EINVAL, "volume macro_margin must be finite and >= 0");
+    if (v->macro > 0 && (!(v->macro_rho_min >= 0.0f) || !std::isfinite(v->macro_rho_min)))
+        return fail(GDRR_EINVAL, "volume macro_rho_min must be finite and >= 0");
     return GDRR_OK;
 }
 
@@ -618,7 +620,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
         if (L.macro[v]) {
             MacroParams mp{V.density, V.material, V.nx, V.ny, V.nz, V.macro, cubes(V.nx, V.macro),
                            cubes(V.ny, V.macro), cubes(V.nz, V.macro), phys->n_mat,
-                           1.0 + (double)V.macro_margin, L.macro[v]};
+                           1.0 + (double)V.macro_margin, V.macro_rho_min, L.macro[v]};
             const size_t nm = (size_t)mp.mnx * mp.mny * mp.mnz;
             ls.push_back(make_launch((const void*)&macro_kernel,
                                      dim3((unsigned)std::max<size_t>(1, std::min<size_t>((size_t)dev.cus * 8, (nm + 255) / 256))),

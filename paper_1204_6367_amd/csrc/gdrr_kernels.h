@@ -746,15 +746,17 @@ __global__ __launch_bounds__(256) void majorant_kernel(MajFinParams F) {
 }
 
 // ---------------------------------------------------------------------------
-// Local majorants: per cube of mcube^3 voxels, the largest density and the
-// materials over the cube grown by one voxel (the interpolation corners of
-// every point in the cube, with a voxel to spare at its faces).
+// Local majorants: per cube of mcube^3 voxels, the largest density (at least
+// rho_min) and the materials over the cube grown by one voxel (the
+// interpolation corners of every point in the cube, with a voxel to spare at
+// its faces).
 // ---------------------------------------------------------------------------
 struct MacroParams {
     const float* density;
     const uint8_t* material;
     int nx, ny, nz, mcube, mnx, mny, mnz, n_mat;
     double scale;              // 1 + margin
+    float rho_min;             // least density a cube's bound assumes
     uint2* out;
 };
 
@@ -765,7 +767,7 @@ __global__ __launch_bounds__(256) void macro_kernel(MacroParams M) {
         const int x0 = max(bx * M.mcube - 1, 0), x1 = min((bx + 1) * M.mcube, M.nx - 1);
         const int y0 = max(by * M.mcube - 1, 0), y1 = min((by + 1) * M.mcube, M.ny - 1);
         const int z0 = max(bz * M.mcube - 1, 0), z1 = min((bz + 1) * M.mcube, M.nz - 1);
-        float r = 0.0f;
+        float r = M.rho_min;
         uint32_t mask = 0u;
         for (int z = z0; z <= z1; ++z)
             for (int y = y0; y <= y1; ++y) {
@@ -805,8 +807,10 @@ __global__ __launch_bounds__(256) void cells_kernel(CellParams C) {
             const float rho = C.density[v];
             if (!density_ok(rho)) err |= kErrDensity;
             d[c] = __float_as_uint(clean_density(rho)) & 0x7FFFFFFFu;   // (-0 loses its sign too)
-            const uint32_t m = C.material[v];
-            if (m >= (uint32_t)C.n_mat) err |= kErrMaterial;
+            // a material beyond the table reads as the last one, here as everywhere
+            const uint32_t mr = C.material[v];
+            if (mr >= (uint32_t)C.n_mat) err |= kErrMaterial;
+            const uint32_t m = min(mr, (uint32_t)(C.n_mat - 1));
             if (c == 0) m0 = m;
             same = same && m == m0;
         }
@@ -814,8 +818,7 @@ __global__ __launch_bounds__(256) void cells_kernel(CellParams C) {
         if (!same) {
             d[0] |= 0x80000000u;
         } else {
-            const uint32_t mc = min(m0, (uint32_t)(C.n_mat - 1));
-            for (int b = 0; b < 4; ++b) d[1 + b] |= ((mc >> b) & 1u) << 31;
+            for (int b = 0; b < 4; ++b) d[1 + b] |= ((m0 >> b) & 1u) << 31;
         }
         float4* out = reinterpret_cast<float4*>(C.cells + t);
         out[0] = make_float4(__uint_as_float(d[0]), __uint_as_float(d[1]), __uint_as_float(d[2]), __uint_as_float(d[3]));

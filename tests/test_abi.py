@@ -49,6 +49,7 @@ int main(void) {
     printf("gdrr_job %zu\n", sizeof(gdrr_job));
     printf("gdrr_tuning %zu\n", sizeof(gdrr_tuning));
     F(gdrr_volume, density) F(gdrr_volume, material) F(gdrr_volume, macro) F(gdrr_volume, macro_margin)
+    F(gdrr_volume, macro_rho_min)
     F(gdrr_physics, mu_mass) F(gdrr_physics, response) F(gdrr_physics, rayleigh_x0_invA) F(gdrr_physics, e_cut_kev)
     F(gdrr_source, spec_e_kev) F(gdrr_source, fu) F(gdrr_source, fluence) F(gdrr_source, spec_rows)
     F(gdrr_job, geom) F(gdrr_job, n_photons) F(gdrr_job, job_id) F(gdrr_job, first_photon) F(gdrr_job, tally_offset)
@@ -237,6 +238,9 @@ def test_backward_checks_every_argument_before_touching_the_gradient(abi):
     assert call(C.byref(vol), grad=None) == abi.GDRR_EINVAL
     bad = abi.Volume(8, 8, 0, 2.0, 2.0, 2.0, 0x1000, 0x1000, 0, 0.0)
     assert call(C.byref(bad)) == abi.GDRR_EINVAL and "dimensions" in msg()
+    for floor in (-0.01, float("nan"), float("inf")):
+        bad = abi.Volume(8, 8, 8, 2.0, 2.0, 2.0, 0x1000, 0x1000, 4, 0.1, floor)
+        assert call(C.byref(bad)) == abi.GDRR_EINVAL and "macro_rho_min" in msg()
 
 
 def test_noise_scale_in_the_library(abi):

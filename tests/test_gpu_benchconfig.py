@@ -3,14 +3,18 @@
 * Transport: the three phantoms of the multi-phantom workload (512x512x256,
   256x256x160, 128x128x64) with local majorants on cubes of about 40 mm
   (41, 21 and 10 voxels, all records staged in LDS), the adjoint volume's
-  margin 0.1, one persistent launch of block 512 and defer 16, every job at its
+  margin 0.1 and cube density floor 0.05 g/cm^3, one persistent launch of block 512 and defer 16, every job at its
   full photon count: the batched tallies equal the sums of the traced
   histories, and sampled histories equal the oracle's one by one.
 * 360 angles of the 256x256x160 projection phantom in one launch equal 360
   single projections, bit for bit.
 * The adjoint at the 128x128x96 adjoint phantom and at the benchmark's adjoint
-  phantom (256x256x160, cubes of 21 voxels, margin 0.1) against the oracle's
-  float64 adjoint on the same streams.
+  phantom (256x256x160, cubes of 21 voxels, margin 0.1, floor 0.05) against the
+  oracle's float64 adjoint on the same streams.  Without the floor a cube of air
+  alone has a free path of tens of metres per unit optical depth, and float32
+  rounding of the depth left after denser cubes moves its collisions by a
+  fraction of a voxel: the adjoint's 1/rho_air terms then differ history by
+  history.
 * Central finite differences with common random numbers on 64 voxels of the
   128x128x96 phantom, 32 replicas, against the adjoint.
 """
@@ -29,6 +33,7 @@ pytestmark = pytest.mark.gpu
 CUBE_MM = 40.0                 # the benchmark's local-majorant cube edge
 FWD_MARGIN = 2.0**-20
 ADJ_MARGIN = 0.1
+ADJ_RHO_MIN = 0.05             # the adjoint volume's cube density floor, g/cm^3
 BENCH_TUNE = dict(block=512, defer=16)
 
 
@@ -66,12 +71,14 @@ def test_benchmark_transport_configuration(gpu, multi):
     physw = W.physics_for(multi[0])
     phys = gpu.DevicePhysics(physw.mu_mass, physw.grid.e0_kev, physw.grid.de_kev)
     src = gpu.DeviceSource(srcw.spec_e, srcw.spec_p, srcw.fluence)
-    vols, macros, margins = [], [], []
+    vols, macros, margins, floors = [], [], [], []
     for v, ph in enumerate(multi):
         m, g = cube_voxels(ph.spacing_mm), ADJ_MARGIN if v == 1 else FWD_MARGIN
-        vols.append(gpu.DeviceVolume(ph.density, ph.material, ph.spacing_mm).local_majorants(m, g))
+        r = ADJ_RHO_MIN if v == 1 else 0.0
+        vols.append(gpu.DeviceVolume(ph.density, ph.material, ph.spacing_mm).local_majorants(m, g, r))
         macros.append(m)
         margins.append(g)
+        floors.append(r)
     assert macros == [41, 21, 10]
     cubes = sum(math.prod(-(-n // m) for n in ph.shape) for ph, m in zip(multi, macros))
     assert cubes * 8 <= 32 << 10                  # every volume's cube records fit the LDS copy
@@ -103,7 +110,7 @@ def test_benchmark_transport_configuration(gpu, multi):
         g = {key: val.index_select(0, torch.tensor(ids, device="cuda")) for key, val in tr.items()}
         del tr
         prob = W.Problem(multi[v], physw, srcw, j.geom, j.n_photons)
-        p = oracle.Problem.from_workload(prob).local_majorants(macros[v], margins[v])
+        p = oracle.Problem.from_workload(prob).local_majorants(macros[v], margins[v], floors[v])
         o = oracle.mc_histories(p, 1, ids.astype(np.uint32), None, job_id=j.job_id)
         frac, _ = compare_histories(g, o)
         log(f"phantom {v}: traced sums = batched tallies; identical sampled histories {frac:.4f}")
@@ -138,7 +145,7 @@ def pooled(x, f=4):
     return x.reshape(nz // f, f, ny // f, f, nx // f, f).sum((1, 3, 5))
 
 
-def adjoint_case(gpu, ph, n, macro, margin, seed_adj, phi=0.4, job_id=3):
+def adjoint_case(gpu, ph, n, macro, margin, seed_adj, phi=0.4, job_id=3, rho_min=ADJ_RHO_MIN):
     """GPU and oracle adjoints of one projection with seeded adjoint weights on
     the scatter image, and the fraction of sampled histories identical on both
     sides."""
@@ -147,12 +154,12 @@ def adjoint_case(gpu, ph, n, macro, margin, seed_adj, phi=0.4, job_id=3):
     geom = W.Geometry(**W.PELVIS_DET).replace(phi_rad=phi)
     prob = W.Problem(ph, W.physics_for(ph), W.pelvis_source(geom), geom, n)
     vol, phys, src = gpu.upload(prob)
-    vol.local_majorants(macro, margin)
+    vol.local_majorants(macro, margin, rho_min)
     adj = np.zeros((2, geom.nv, geom.nu))
     adj[1] = np.random.default_rng(seed_adj).normal(size=(geom.nv, geom.nu))
     adj[0] = 0.1 * np.random.default_rng(seed_adj + 1).normal(size=(geom.nv, geom.nu))
     b = gpu.Batch([vol], phys, [src], [gpu.JobSpec(geom, n, job_id)])
-    p = oracle.Problem.from_workload(prob).local_majorants(macro, margin)
+    p = oracle.Problem.from_workload(prob).local_majorants(macro, margin, rho_min)
     if macro:
         maj_g = torch.zeros(1, phys.n_e - 1, dtype=torch.float32, device="cuda")   # unused with local majorants
         maj_o = None

@@ -23,15 +23,15 @@ def bone_water(seed, shape=(10, 10, 10), sp=(5.0, 5.0, 5.0)):
     return W.Phantom(d, m, sp, ["water", "bone"])
 
 
-@pytest.mark.parametrize("interp,macro", [(True, 1), (True, 5), (False, 3)])
-def test_local_primary_matches_exact_eq1(oracle_lib, interp, macro):
+@pytest.mark.parametrize("interp,macro,rho_min", [(True, 1, 0.0), (True, 5, 0.0), (False, 3, 0.0), (True, 4, 0.6)])
+def test_local_primary_matches_exact_eq1(oracle_lib, interp, macro, rho_min):
     ph = random_phantom((12, 12, 12), (5.0, 5.0, 5.0), seed=11)
     g = W.Geometry(phi_rad=0.7, nu=16, nv=12, du_mm=8.0, dv_mm=8.0)
     spec = (np.array([30.0, 45.5, 60.0, 80.0, 110.0], np.float32),
             np.array([0.1, 0.3, 0.3, 0.2, 0.1], np.float32))
     p = make(ph, g, spec=spec)
     want = oracle_lib.primary_exact(p, interp=interp, nq=32)
-    p.local_majorants(macro)
+    p.local_majorants(macro, rho_min=rho_min)
     n = 2_000_000
     r = oracle_lib.mc_project(p, seed=3, n=n, interp=interp)
     z = zscores(r["tally"][0], r["tally"][1], n, want)
@@ -90,6 +90,38 @@ def test_local_bound_holds_everywhere(oracle_lib):
             assert np.all(rho * mut <= mb), interp
 
 
+def test_local_bound_density_floor(oracle_lib):
+    """With a density floor a cube's bound is (1 + margin) max(rho_max, floor)
+    max_m mu_tot(m, E): a cube of air alone takes the floor, a denser cube keeps
+    its own bound, and the floor never lowers a bound."""
+    d = np.full((8, 8, 8), 0.0012, np.float32)
+    d[4:, :, :] = 1.0
+    m = np.zeros((8, 8, 8), np.uint8)
+    m[4:, :, :] = 1
+    ph = W.Phantom(d, m, (4.0, 4.0, 4.0), ["air", "water"])
+    p = make(ph, W.Geometry(nu=8, nv=6))
+    tab = p.mu.astype(np.float64).sum(-1)
+    eg = W.EnergyGrid().energies()
+    e = np.array([20.0, 60.25, 100.0])
+    air_pt = np.array([[-10.0, -10.0, -14.0]] * 3)        # cube z in [-16, -8): voxels z 0..1 (+1 ring) are air
+    water_pt = np.array([[-10.0, -10.0, 12.0]] * 3)
+    for margin in (2.0**-20, 0.1):
+        p.local_majorants(2, margin=margin)
+        a0 = oracle_lib.local_majorant_at(p, air_pt, e)
+        w0 = oracle_lib.local_majorant_at(p, water_pt, e)
+        p.local_majorants(2, margin=margin, rho_min=0.05)
+        a1 = oracle_lib.local_majorant_at(p, air_pt, e)
+        w1 = oracle_lib.local_majorant_at(p, water_pt, e)
+        air_tot = np.array([np.interp(x, eg, tab[0]) for x in e])
+        water_tot = np.array([np.interp(x, eg, tab[1]) for x in e])
+        assert np.allclose(a0, (1 + margin) * np.float64(np.float32(0.0012)) * air_tot, rtol=1e-12)
+        assert np.allclose(a1, (1 + margin) * 0.05 * air_tot, rtol=1e-12)
+        assert np.allclose(w1, w0, rtol=0) and np.allclose(w0, (1 + margin) * 1.0 * water_tot, rtol=1e-12)
+    p.local_majorants(2, rho_min=-0.01)
+    with pytest.raises(ValueError):
+        oracle_lib.mc_project(p, 1, 10)
+
+
 def test_local_and_global_tallies_agree(oracle_lib):
     """Primary and scatter tallies of the two majorants agree within noise on a
     heterogeneous phantom (pooled 4 x 4 bins and totals)."""
@@ -123,7 +155,7 @@ def test_local_adjoint_matches_volume_integral(oracle_lib):
     want = primary_gradient_reference(oracle_lib, p, ph, g, True, 1.0 / (80.0 * 80.0), nq=12)
     coarse = primary_gradient_reference(oracle_lib, p, ph, g, True, 1.0 / (80.0 * 80.0), nq=8)
     qerr = 2.0 * np.abs(want - coarse)
-    p.local_majorants(2, margin=0.2)
+    p.local_majorants(2, margin=0.2, rho_min=0.3)
     adj = np.zeros((2, 8, 8))
     adj[0] = 1.0
     reps = np.array([oracle_lib.mc_backward(p, s, 400_000, adj, None) for s in range(1, 9)])
