@@ -210,6 +210,35 @@ int gdrr_mc_project(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr
 size_t gdrr_mc_project_workspace(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr_source* src,
                                  const gdrr_geometry* geom);
 
+/* Bytes of the per-device scratch array behind gdrr_mc_project_static. */
+#define GDRR_STATIC_SCRATCH_BYTES (128u << 20)
+
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * gdrr_mc_project without a workspace argument.  Its scratch is one array of
+ * GDRR_STATIC_SCRATCH_BYTES per device, part of the library's code object, so
+ * each device the library runs on holds it until the process ends; its device
+ * address is looked up once per device, by gdrr_init() or by the first call of
+ * this function there.  Arguments and results are those of gdrr_mc_project,
+ * bit for bit, with these differences:
+ *  - a call whose gdrr_mc_project_workspace() exceeds GDRR_STATIC_SCRATCH_BYTES
+ *    (about 4 million interpolation cells, e.g. 128x128x96 fits, 256x256x160
+ *    does not), or that sets GDRR_RESUME, returns GDRR_EINVAL before any
+ *    device work;
+ *  - the device-side input checks are not reported (gdrr_input_status needs a
+ *    caller's workspace) and the timing hook is not applied.
+ * Allocates no device memory and issues no host-to-device copy (the job's
+ * tables travel as kernel arguments); host bookkeeping uses the C++ heap.
+ * Every call on a device uses that device's one array, which keeps the last
+ * call's contents (the call clears what must start at zero): calls that
+ * overlap on one device -- other streams, other threads -- race and give wrong
+ * results, so the caller orders them.
+ */
+int gdrr_mc_project_static(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr_source* src,
+                           const gdrr_geometry* geom, const float* majorant, uint64_t seed,
+                           uint64_t n_photons, uint32_t job_id, uint32_t flags, double* tally, void* stream);
+
 /*
  * Batch: every job of `jobs` (host array) in one persistent launch, replayed
  * from a cached HIP graph when called again with the same arguments.  Job k

@@ -23,6 +23,8 @@ SCATTER_FIRST = 8
 SCATTER_FIRST_COMPTON = 16
 RESUME = 32
 
+STATIC_SCRATCH_BYTES = 128 << 20     # the per-device scratch of gdrr_mc_project_static
+
 MAX_MATERIALS = 16
 MAX_VOLUMES = 8
 MAX_SOURCES = 8
@@ -73,6 +75,8 @@ SIGNATURES = {
     "gdrr_mc_project": (C.c_int, [_P(Volume), _P(Physics), _P(Source), _P(Geometry), _vp, C.c_uint64,
                                   C.c_uint64, C.c_uint32, C.c_uint32, _vp, _vp, _sz, _vp]),
     "gdrr_mc_project_workspace": (_sz, [_P(Volume), _P(Physics), _P(Source), _P(Geometry)]),
+    "gdrr_mc_project_static": (C.c_int, [_P(Volume), _P(Physics), _P(Source), _P(Geometry), _vp, C.c_uint64,
+                                         C.c_uint64, C.c_uint32, C.c_uint32, _vp, _vp]),
     "gdrr_mc_project_batch": (C.c_int, [_P(Volume), C.c_int32, _P(Physics), _P(Source), C.c_int32, _P(Job),
                                         C.c_int32, _vp, C.c_uint64, C.c_uint32, _P(Tuning), _vp, _vp, _sz,
                                         _vp]),

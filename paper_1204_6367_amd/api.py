@@ -156,6 +156,24 @@ def project(vol: DeviceVolume, phys: DevicePhysics, src: DeviceSource, geom, n_p
     return out
 
 
+def project_static(vol: DeviceVolume, phys: DevicePhysics, src: DeviceSource, geom, n_photons: int, seed: int = 1,
+                   job_id: int = 0, interp: bool = True, sumsq: bool = True,
+                   majorant_tab: Optional[torch.Tensor] = None, flags: int = 0,
+                   out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """project() through gdrr_mc_project_static: no workspace, the library's
+    per-device static scratch (calls on one device must not overlap).  With
+    `out` given, nothing is allocated here either."""
+    L = _abi.lib()
+    g = geometry_struct(geom)
+    v, p, s = vol.struct(), phys.struct(), src.struct()
+    if out is None:
+        out = torch.zeros(4, geom.nv, geom.nu, dtype=torch.float64, device=vol.density.device)
+    mb = None if majorant_tab is None else majorant_tab.data_ptr()
+    _abi.check(L.gdrr_mc_project_static(C.byref(v), C.byref(p), C.byref(s), C.byref(g), mb, seed, n_photons,
+                                        job_id, _flags(interp, sumsq, flags), out.data_ptr(), _stream(stream)))
+    return out
+
+
 def trace(vol: DeviceVolume, phys: DevicePhysics, src: DeviceSource, geom, n_photons: int, seed: int = 1,
           job_id: int = 0, interp: bool = True, majorant_tab: Optional[torch.Tensor] = None,
           stream=None) -> Dict[str, torch.Tensor]:

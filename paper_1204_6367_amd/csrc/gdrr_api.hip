@@ -381,6 +381,7 @@ struct Batch {
     double* grad;               // backward
     int8_t* t_cls; int32_t* t_pixel; float* t_e; int32_t* t_steps; int32_t* t_nc; int32_t* t_nr;
     bool use_graph;
+    bool tables_by_kernel = false;   // one job: its tables as kernel arguments, no host copy, no timing
 };
 
 // Host staging of the per-call tables.  It is pageable memory: a host-to-device
@@ -561,17 +562,23 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
 
     // The volume order of the dispenser: jobs are taken in array order; a
     // wavefront drains before it changes phantom, so callers group jobs by volume.
-    g_staging.resize(job_bytes + sizeof(DJob) * n_jobs + sizeof(long long) * n_jobs + 1024);
-    char* hs = g_staging.data();
-    std::memcpy(hs, prefix.data(), job_bytes);
-    GDRR_HIP(hipMemcpyAsync(L.chunk_prefix, hs, job_bytes, hipMemcpyHostToDevice, st));
-    std::memcpy(hs + job_bytes, dj.data(), sizeof(DJob) * n_jobs);
-    GDRR_HIP(hipMemcpyAsync(L.jobs, hs + job_bytes, sizeof(DJob) * n_jobs, hipMemcpyHostToDevice, st));
-    std::memcpy(hs + job_bytes + sizeof(DJob) * n_jobs, out_off.data(), sizeof(long long) * n_jobs);
-    GDRR_HIP(hipMemcpyAsync(L.out_off, hs + job_bytes + sizeof(DJob) * n_jobs, sizeof(long long) * n_jobs,
-                            hipMemcpyHostToDevice, st));
-
     std::vector<Launch> ls;
+    if (B.tables_by_kernel) {
+        if (n_jobs != 1) return fail(GDRR_EINVAL, "internal: kernel-written tables need one job");
+        JobTableParams jt{L.chunk_prefix, L.jobs, L.out_off, prefix[0], prefix[1], out_off[0], dj[0]};
+        ls.push_back(make_launch((const void*)&job_table_kernel, dim3(1), dim3(64), 0, jt));
+    } else {
+        g_staging.resize(job_bytes + sizeof(DJob) * n_jobs + sizeof(long long) * n_jobs + 1024);
+        char* hs = g_staging.data();
+        std::memcpy(hs, prefix.data(), job_bytes);
+        GDRR_HIP(hipMemcpyAsync(L.chunk_prefix, hs, job_bytes, hipMemcpyHostToDevice, st));
+        std::memcpy(hs + job_bytes, dj.data(), sizeof(DJob) * n_jobs);
+        GDRR_HIP(hipMemcpyAsync(L.jobs, hs + job_bytes, sizeof(DJob) * n_jobs, hipMemcpyHostToDevice, st));
+        std::memcpy(hs + job_bytes + sizeof(DJob) * n_jobs, out_off.data(), sizeof(long long) * n_jobs);
+        GDRR_HIP(hipMemcpyAsync(L.out_off, hs + job_bytes + sizeof(DJob) * n_jobs, sizeof(long long) * n_jobs,
+                                hipMemcpyHostToDevice, st));
+    }
+
     unsigned int* status = (unsigned int*)(L.counter + 1);    // input-error bits of this call
     const bool resume = B.mode == kModeForward && (B.flags & GDRR_RESUME);
     // ---- clear counters, tallies (unless resuming), the gradient and the majorant scratch ----
@@ -724,7 +731,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
                                  dim3((unsigned)std::min(1024, (4 * maxpix + 255) / 256), (unsigned)B.n_jobs), dim3(256), 0, fp));
     }
     TimeEvents* ev = nullptr;
-    {
+    if (!B.tables_by_kernel) {
         std::lock_guard<std::mutex> lk(g_time_mu);
         if (g_timing && timed >= 0 && (rc = timing_events(&ev))) return rc;
     }
@@ -1086,6 +1093,32 @@ int run_denoise(const double* shat, long long stride, int n_img, int nv, int nu,
     return run_direct(ls, st, ev ? 0 : -1, ev, ev ? (int)ls.size() - 1 : -1);
 }
 
+// --------------------------------------------------------------------------
+// Scratch of gdrr_mc_project_static: one array per device in the code object.
+// Host code never passes `scratch` itself (in host code the name stands for a
+// host-side shadow); it passes the device address that hipGetSymbolAddress
+// returns for the current device, looked up once per device.
+// --------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char scratch[GDRR_STATIC_SCRATCH_BYTES];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64];
+
+int static_scratch(void** out) {
+    int dev = 0;
+    GDRR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(GDRR_ENOTSUP, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        GDRR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(GDRR_EHIP, "hipGetSymbolAddress returned NULL for the static scratch");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return GDRR_OK;
+}
+
 gdrr_job single_job(const gdrr_geometry* geom, uint64_t n, uint32_t job_id) {
     gdrr_job j{};
     j.volume = 0;
@@ -1107,7 +1140,10 @@ const char* gdrr_version(void) { return "gdrr-mi355x 0.1"; }
 
 int gdrr_init(void) {
     DevInfo d;
-    return device_info(d);
+    int rc = device_info(d);
+    if (rc) return rc;
+    void* p = nullptr;
+    return static_scratch(&p);
 }
 
 int gdrr_enable_timing(int enable) {
@@ -1185,6 +1221,28 @@ int gdrr_mc_project(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr
     Batch B{vol, 1, phys, src, 1, &j, 1, majorant, seed, flags, nullptr, kModeForward, -1, tally,
             nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, false};
     return run_batch(B, workspace, ws_bytes, (hipStream_t)stream);
+}
+
+int gdrr_mc_project_static(const gdrr_volume* vol, const gdrr_physics* phys, const gdrr_source* src,
+                           const gdrr_geometry* geom, const float* majorant, uint64_t seed, uint64_t n_photons,
+                           uint32_t job_id, uint32_t flags, double* tally, void* stream) {
+    if (!geom) return fail(GDRR_EINVAL, "geometry is NULL");
+    if (!tally) return fail(GDRR_EINVAL, "tally is NULL");
+    if (flags & GDRR_RESUME) return fail(GDRR_EINVAL, "gdrr_mc_project_static does not resume (GDRR_RESUME)");
+    gdrr_job j = single_job(geom, n_photons, job_id);
+    Batch B{vol, 1, phys, src, 1, &j, 1, majorant, seed, flags, nullptr, kModeForward, -1, tally,
+            nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, false};
+    B.tables_by_kernel = true;
+    int rc = check_batch(B);
+    if (rc) return rc;
+    const size_t need = batch_bytes(vol, 1, phys, src, 1, &j, 1, majorant == nullptr);
+    if (need > GDRR_STATIC_SCRATCH_BYTES)
+        return fail(GDRR_EINVAL, "gdrr_mc_project_static: the call needs " + std::to_string(need) +
+                                 " bytes of scratch; the static scratch holds " +
+                                 std::to_string((size_t)GDRR_STATIC_SCRATCH_BYTES) + " (use gdrr_mc_project)");
+    void* ws = nullptr;
+    if ((rc = static_scratch(&ws))) return rc;
+    return run_batch(B, ws, GDRR_STATIC_SCRATCH_BYTES, (hipStream_t)stream);
 }
 
 size_t gdrr_mc_project_batch_workspace(const gdrr_volume* vols, int32_t n_vols, const gdrr_physics* phys,

@@ -907,6 +907,25 @@ __global__ __launch_bounds__(256) void fill_zero_kernel(FillParams F) {
         F.p[i] = 0ull;
 }
 
+// The dispenser prefix, job record and output offset of a one-job launch,
+// written from the kernel's arguments instead of copied from the host.
+struct JobTableParams {
+    unsigned long long* prefix;     // [2]
+    DJob* jobs;                     // [1]
+    long long* out_off;             // [1]
+    unsigned long long p0, p1;
+    long long off;
+    DJob job;
+};
+
+__global__ __launch_bounds__(64) void job_table_kernel(JobTableParams T) {
+    if (threadIdx.x != 0) return;
+    T.prefix[0] = T.p0;
+    T.prefix[1] = T.p1;
+    T.out_off[0] = T.off;
+    T.jobs[0] = T.job;
+}
+
 struct FinParams {
     const DJob* jobs;
     int n_jobs;

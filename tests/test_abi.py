@@ -48,6 +48,7 @@ int main(void) {
     printf("gdrr_geometry %zu\n", sizeof(gdrr_geometry));
     printf("gdrr_job %zu\n", sizeof(gdrr_job));
     printf("gdrr_tuning %zu\n", sizeof(gdrr_tuning));
+    printf("GDRR_STATIC_SCRATCH_BYTES %zu\n", (size_t)GDRR_STATIC_SCRATCH_BYTES);
     F(gdrr_volume, density) F(gdrr_volume, material) F(gdrr_volume, macro) F(gdrr_volume, macro_margin)
     F(gdrr_volume, macro_rho_min)
     F(gdrr_physics, mu_mass) F(gdrr_physics, response) F(gdrr_physics, rayleigh_x0_invA) F(gdrr_physics, e_cut_kev)
@@ -69,6 +70,7 @@ def test_struct_layout_matches_binding(abi, tmp_path):
                                                        check=True).stdout.splitlines())
     m = {"gdrr_volume": abi.Volume, "gdrr_physics": abi.Physics, "gdrr_source": abi.Source,
          "gdrr_geometry": abi.Geometry, "gdrr_job": abi.Job, "gdrr_tuning": abi.Tuning}
+    assert int(got.pop("GDRR_STATIC_SCRATCH_BYTES")) == abi.STATIC_SCRATCH_BYTES
     for k, v in got.items():
         if "." in k:
             t, f = k.split(".")
@@ -130,6 +132,28 @@ def test_too_many_photons_and_small_workspace(abi):
     assert _call(abi, vol, phys, src, geom, ws_bytes=16) == abi.GDRR_EINVAL
     assert "workspace" in abi.lib().gdrr_last_error().decode()
     assert _call(abi, vol, phys, src, geom, tally=None) == abi.GDRR_EINVAL
+
+
+def test_static_entry_point_rejects_before_any_device_work(abi):
+    """gdrr_mc_project_static: invalid arguments, GDRR_RESUME and calls whose
+    workspace exceeds the static scratch are refused on the host (the dummy
+    pointers would fault if anything were launched)."""
+    L = abi.lib()
+    msg = lambda: L.gdrr_last_error().decode()
+    call = lambda vol, phys, src, geom, flags=1, tally=0x2000: L.gdrr_mc_project_static(
+        C.byref(vol), C.byref(phys), C.byref(src), C.byref(geom), None, 1, 1000, 0, flags, tally, None)
+    vol, phys, src, geom = _valid_structs(abi)
+    assert call(vol, phys, src, geom, tally=None) == abi.GDRR_EINVAL and "tally" in msg()
+    assert call(vol, phys, src, geom, flags=1 | abi.RESUME) == abi.GDRR_EINVAL and "RESUME" in msg()
+    vol.nx = 0
+    assert call(vol, phys, src, geom) == abi.GDRR_EINVAL and "dimensions" in msg()
+    # 170^3 voxels: 171^3 32-byte cell records alone exceed 128 MiB
+    vol, phys, src, geom = _valid_structs(abi)
+    vol.nx = vol.ny = vol.nz = 170
+    vol.dx_mm = vol.dy_mm = vol.dz_mm = 1.0
+    need = L.gdrr_mc_project_workspace(C.byref(vol), C.byref(phys), C.byref(src), C.byref(geom))
+    assert need > abi.STATIC_SCRATCH_BYTES
+    assert call(vol, phys, src, geom) == abi.GDRR_EINVAL and "static scratch" in msg()
 
 
 def test_workspace_query_is_positive(abi):
