@@ -437,6 +437,50 @@ def raytrace_leg(wl, api, torch, steps, cpu):
 
 
 # ---------------------------------------------------------------------------
+# The plain single projection (one launch, one job) on the same GPU: the
+# 256x256x160 ellipsoid phantom at 1.95x1.95x2.5 mm, 120 kVp + bowtie, 1e8
+# photons, with the step's majorant scheme, against which the batched forward
+# and the adjoint rates are read
+# ---------------------------------------------------------------------------
+SINGLE_PHOTONS = 100_000_000
+
+
+def single_projection_leg(wl, api, W, torch, steps, fwd_rate, adj_rate):
+    prob = W.pelvis_problem(SINGLE_PHOTONS)
+    if SOURCE == "joint":
+        prob.source = W.pelvis_source(prob.geom, joint=True)
+    vol, phys, src = api.upload(prob)
+    apply_majorant(vol, 2.0**-20)
+    batch = api.Batch([vol], phys, [src], [api.JobSpec(prob.geom, SINGLE_PHOTONS, 0)])
+    tune = autotune_for(batch)
+    out = torch.zeros(batch.tally_elems, dtype=torch.float64, device="cuda")
+    maj = batch.majorants(True)
+    batch.project(seed=1, sumsq=False, majorants=maj, out=out, tune=tune)       # warm-up
+    ms = []
+    for _ in range(max(steps, 1)):
+        batch.project(seed=1, sumsq=False, majorants=batch.majorants(True), out=out, tune=tune)
+        ms.append(api.last_kernel_ms())
+    torch.cuda.synchronize()
+    kms = float(np.mean(ms))
+    rate = SINGLE_PHOTONS / (kms * 1e-3)
+    return dict(workload="256x256x160 @1.95x1.95x2.5mm ellipsoids, 1 angle, 1e8 photons, one launch",
+                histories_per_s=round(rate, 1), transport_kernel_ms=round(kms, 3), tuning=tune,
+                majorant=majorant_desc([vol]),
+                batched_fwd_over_single=round(fwd_rate / rate, 4),
+                adjoint_over_single=round(adj_rate / rate, 4) if adj_rate else None)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+# ---------------------------------------------------------------------------
 # Scatter denoising (Eq. 5) and noise assembly (Sec. 2.6) of the step's tallies
 # ---------------------------------------------------------------------------
 DENOISE_ITERS = 256
@@ -580,6 +624,8 @@ def main():
                          "one bowtie-hardened spectrum per detector column")
     ap.add_argument("--no-global-reference", action="store_true",
                     help="with local majorants, skip the reference forward with the single majorant")
+    ap.add_argument("--no-single", action="store_true",
+                    help="skip the plain single-projection reference (one launch of 1e8 photons)")
     ap.add_argument("--tune-cache", default=None,
                     help="autotuner cache file (default: the one shipped with the package)")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "traffic.json"),
@@ -647,6 +693,12 @@ def main():
             v.local_majorants(m, g, r)
         glob = dict(fwd_histories_per_s=round(wl["fwd"] / (gms * 1e-3), 1), transport_kernel_ms=round(gms, 3))
         log(f"global-majorant forward: {gms:.1f} ms")
+    fwd_rate = wl["fwd"] / (fwd_ms * 1e-3)
+    adj_rate = wl["adj"] / (adj_ms * 1e-3) if adj_ms else None
+    single = None
+    if not args.no_single:
+        single = single_projection_leg(wl, api, W, torch, args.steps, fwd_rate, adj_rate)
+        log(f"single projection: {single['transport_kernel_ms']:.2f} ms, {single['histories_per_s']:.4g} histories/s")
     rt = None if args.no_raytrace else raytrace_leg(wl, api, torch, args.steps, not args.no_cpu_baseline)
     dn = None if args.no_raytrace else denoise_leg(wl, api, torch, args.steps, wl["batch"].primary(),
                                                    not args.no_cpu_baseline)
@@ -678,15 +730,17 @@ def main():
         else:
             cval = cpu["fwd_rate"]
             sample = f"{cpu['fwd_sample']} forward histories over {len(wl['samples'])} jobs of the same workload"
-        cpu = dict(value=round(cval, 1), unit="histories/s", cores=cores, kind="oracle", sample=sample,
+        cpu = dict(value=round(cval, 1), unit="histories/s", cores=cores, cpu_model=cpu_model(), kind="oracle",
+                   sample=sample,
                    single_thread=dict(value=round(cpu["fwd_rate_1"], 1), unit="forward histories/s", cores=1,
                                       sample=f"{cpu['fwd_sample_1']} forward histories over {len(wl['samples'])} jobs"))
     line = dict(metric=METRIC, value=round(value, 1), unit="histories/s", n_gpus=1, steps=args.steps,
                 warmup=args.warmup, ms_per_step=round(ms_step, 2), higher_is_better=True, scaling="weak",
                 vs_baseline=None, dtype="f32", data="synthetic",
                 config=wl["config"], roofline=roof, cpu_baseline=cpu,
-                fwd_histories_per_s=round(wl["fwd"] / (fwd_ms * 1e-3), 1),
-                adj_histories_per_s=round(wl["adj"] / (adj_ms * 1e-3), 1) if adj_ms else None,
+                fwd_histories_per_s=round(fwd_rate, 1),
+                adj_histories_per_s=round(adj_rate, 1) if adj_rate else None,
+                single_projection=single,
                 transport_kernel_ms=round(fwd_ms, 3), adjoint_kernel_ms=round(adj_ms, 3) if adj_ms else None,
                 **extra, global_majorant=glob, raytrace=rt, denoise=dn)
     print(json.dumps(line), flush=True)
