@@ -175,8 +175,8 @@ typedef struct gdrr_tuning {
     int32_t block;             /* threads per workgroup: a multiple of 64 up to 1024 */
     int32_t blocks_per_cu;     /* workgroups per compute unit */
     int32_t chunk;             /* photons handed out at a time (multiple of 64) */
-    int32_t defer;             /* interactions and refills run when >= defer lanes of a wavefront wait (1..64) */
-    int32_t scheme;            /* 0 or 1: one photon per lane for its whole history (the only scheme) */
+    int32_t defer;             /* refills run when >= defer lanes of a wavefront wait (1..64) */
+    int32_t coll_defer;        /* interactions run when >= coll_defer lanes wait (1..64; 0: defer) */
 } gdrr_tuning;
 
 /*

@@ -64,7 +64,7 @@ class Job(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("block", C.c_int32), ("blocks_per_cu", C.c_int32),
-                ("chunk", C.c_int32), ("defer", C.c_int32), ("scheme", C.c_int32)]
+                ("chunk", C.c_int32), ("defer", C.c_int32), ("coll_defer", C.c_int32)]
 
 
 # every function the header declares, with its ctypes signature

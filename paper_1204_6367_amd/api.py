@@ -304,7 +304,7 @@ def tuning_struct(tune) -> Optional[_abi.Tuning]:
     if isinstance(tune, _abi.Tuning):
         return tune
     return _abi.Tuning(int(tune.get("block", 0)), int(tune.get("blocks_per_cu", 0)),
-                       int(tune.get("chunk", 0)), int(tune.get("defer", 0)), int(tune.get("scheme", 0)))
+                       int(tune.get("chunk", 0)), int(tune.get("defer", 0)), int(tune.get("coll_defer", 0)))
 
 
 class Batch:

@@ -1,13 +1,15 @@
 """Launch-shape autotuner for the persistent transport kernel.
 
-Times candidate (block, defer, chunk) shapes on a reduced copy of a batch
+Times candidate launch shapes (workgroup size, refill and collision
+deferral, then chunk size and workgroups per CU) on a reduced copy of a batch
 (same phantoms, sources and angles, a fraction of the photons) with the
-library's kernel timing hook, and caches the fastest per workload class in a
-JSON file.  Tallies do not depend on the shape (integer tallies keyed by
+library's kernel timing hook, and caches the fastest per workload class, mode,
+kernel-source hash and device in a JSON file.  Tallies do not depend on the shape (integer tallies keyed by
 photon index), so tuning never changes results.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 from typing import Dict, Iterable, List, Optional
@@ -18,17 +20,31 @@ from . import api
 
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotune_cache.json")
 
+# Stage 1: block x refill deferral x collision deferral; stage 2, one field at a
+# time from the best so far: chunk size, workgroups per CU.
 CANDIDATES: List[Dict[str, int]] = [
-    dict(block=b, defer=d, chunk=0, blocks_per_cu=0)
-    for b in (256, 512) for d in (8, 12, 16, 24, 32)
+    dict(block=b, defer=d, coll_defer=c, chunk=0, blocks_per_cu=0)
+    for b in (256, 512) for d in (8, 16, 24, 32) for c in (0, 12, 20, 28)
 ]
+REFINE: List[Dict[str, int]] = [dict(chunk=c) for c in (128, 512, 2048)] + [dict(blocks_per_cu=n) for n in (1, 2)]
 
 
-def workload_key(batch: "api.Batch", mode: str = "forward") -> str:
+def kernel_sha() -> str:
+    """Hash of the HIP sources: a cached shape is valid only for the kernels it was timed on."""
+    h = hashlib.sha1()
+    d = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".h", ".hip")):
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()[:12]
+
+
+def workload_key(batch: "api.Batch", mode: str = "forward", interp: bool = True) -> str:
     vols = ";".join("x".join(map(str, v.shape)) + (f"/m{v.macro}" if v.macro else "") for v in batch.vols)
     dets = sorted({(j.geom.nu, j.geom.nv) for j in batch.jobs})
-    key = f"vols={vols}|det={dets}|jobs={len(batch.jobs)}"
-    return key if mode == "forward" else f"{key}|{mode}"
+    dev = torch.cuda.get_device_name() if torch.cuda.is_available() else "cpu"
+    return (f"vols={vols}|det={dets}|jobs={len(batch.jobs)}|mode={mode}|interp={int(interp)}"
+            f"|src={kernel_sha()}|dev={dev}")
 
 
 def _reduced(batch: "api.Batch", fraction: float, min_photons: int) -> "api.Batch":
@@ -46,7 +62,7 @@ def autotune(batch: "api.Batch", candidates: Optional[Iterable[Dict[str, int]]] 
     scatter images, so that every scored scatter history is replayed)."""
     if mode not in ("forward", "backward"):
         raise ValueError("mode must be 'forward' or 'backward'")
-    key = workload_key(batch, mode)
+    key = workload_key(batch, mode, interp)
     table = {}
     if cache and os.path.exists(cache):
         try:
@@ -64,15 +80,25 @@ def autotune(batch: "api.Batch", candidates: Optional[Iterable[Dict[str, int]]] 
         adj[:, 1] = 1.0
     api.enable_timing(True)
     results = []
-    for cand in (candidates or CANDIDATES):
+
+    def run(cand):
         try:
             _timed(small, maj, cand, interp, adj, volume)                 # warm-up / graph build
             ms = min(_timed(small, maj, cand, interp, adj, volume) for _ in range(repeats))
         except api._abi.GdrrError:
-            continue
+            return
         results.append((ms, cand))
+
+    for cand in (candidates or CANDIDATES):
+        run(dict(cand))
     if not results:
         raise RuntimeError("no candidate launch shape ran")
+    if candidates is None:                      # refine one field at a time from the best so far
+        for r in REFINE:
+            best = min(results, key=lambda x: x[0])[1]
+            if all(best.get(k) == v for k, v in r.items()):
+                continue
+            run({**best, **r})
     results.sort(key=lambda r: r[0])
     best_ms, best = results[0]
     if cache:

@@ -438,7 +438,7 @@ int check_batch(const Batch& B) {
         if (t.chunk && (t.chunk % 64 || t.chunk < 64)) return fail(GDRR_EINVAL, "tune.chunk must be a positive multiple of 64");
         if (t.defer < 0 || t.defer > 64) return fail(GDRR_EINVAL, "tune.defer must be in [0, 64]");
         if (t.blocks_per_cu < 0 || t.blocks_per_cu > 64) return fail(GDRR_EINVAL, "tune.blocks_per_cu must be in [0, 64]");
-        if (t.scheme < 0 || t.scheme > 1) return fail(GDRR_EINVAL, "tune.scheme must be 0 or 1");
+        if (t.coll_defer < 0 || t.coll_defer > 64) return fail(GDRR_EINVAL, "tune.coll_defer must be in [0, 64]");
     }
     return GDRR_OK;
 }
@@ -532,6 +532,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
         chunk = (int)(c / 64 * 64);
     }
     const int defer = tune.defer ? tune.defer : 32;
+    const int cdefer = tune.coll_defer ? tune.coll_defer : defer;
 
     const size_t n_jobs = (size_t)B.n_jobs;
     const size_t job_bytes = sizeof(unsigned long long) * (n_jobs + 1);
@@ -710,6 +711,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     kp.flags = B.flags;
     kp.chunk = chunk;
     kp.defer = defer;
+    kp.cdefer = cdefer;
     kp.t_cls = B.t_cls; kp.t_pixel = B.t_pixel; kp.t_e = B.t_e;
     kp.t_steps = B.t_steps; kp.t_nc = B.t_nc; kp.t_nr = B.t_nr;
     kp.adj = B.adj;
@@ -1169,7 +1171,7 @@ int gdrr_default_tuning(gdrr_tuning* out) {
     out->blocks_per_cu = 0;
     out->chunk = 0;
     out->defer = 32;
-    out->scheme = 1;
+    out->coll_defer = 0;
     return GDRR_OK;
 }
 

@@ -8,8 +8,9 @@
 // phantoms of a batch run in the same launch.  Each loop iteration has three
 // phases -- refill (start new histories), flight (one Woodcock step of every
 // flying lane) and collision (interaction sampling) -- and the two rare ones
-// run only when at least `defer` lanes wait for them, so that the
-// wavefront's SIMD lanes mostly execute the same free-flight code.
+// run only when enough lanes wait for them (`defer` for refills, `cdefer` for
+// collisions), so that the wavefront's SIMD lanes mostly execute the same
+// free-flight code.
 #pragma once
 
 #include "gdrr_device.h"
@@ -37,7 +38,7 @@ struct KParams {
     float e0, inv_de, e_max, e_cut, x0;
     uint32_t k0, k1;
     uint32_t flags;
-    int chunk, defer;
+    int chunk, defer, cdefer;
     // diagnostics (trace mode)
     int8_t* t_cls;
     int32_t* t_pixel;
@@ -81,53 +82,9 @@ __device__ __forceinline__ ECache energy_cache(const KParams& P, const Tables& T
 }
 
 // Density at x (tri-linear on the voxel-centre lattice, clamped to the edge
-// voxels; or the containing voxel's), the containing voxel's material, and --
-// for the adjoint -- the eight corner voxels and weights.
-template <bool WANT_STENCIL>
-__device__ __forceinline__ float density_at(const DVolume& V, bool interp, float px, float py, float pz,
-                                            int& mat, int* vox, float* wt) {
-    const float gx = (px - V.lox) * V.idx, gy = (py - V.loy) * V.idy, gz = (pz - V.loz) * V.idz;
-    int cx = (int)floorf(gx), cy = (int)floorf(gy), cz = (int)floorf(gz);
-    cx = min(max(cx, 0), V.nx - 1);
-    cy = min(max(cy, 0), V.ny - 1);
-    cz = min(max(cz, 0), V.nz - 1);
-    const int cvox = cz * V.nxy + cy * V.nx + cx;
-    mat = V.material[cvox];
-    if (!interp) {
-        if (WANT_STENCIL) { vox[0] = cvox; wt[0] = 1.0f; }
-        return V.density[cvox];
-    }
-    const float hx = gx - 0.5f, hy = gy - 0.5f, hz = gz - 0.5f;
-    const float fx0 = floorf(hx), fy0 = floorf(hy), fz0 = floorf(hz);
-    const float fx = hx - fx0, fy = hy - fy0, fz = hz - fz0;
-    const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
-    const int x0 = min(max(ix, 0), V.nx - 1), x1 = min(max(ix + 1, 0), V.nx - 1);
-    const int y0 = min(max(iy, 0), V.ny - 1) * V.nx, y1 = min(max(iy + 1, 0), V.ny - 1) * V.nx;
-    const int z0 = min(max(iz, 0), V.nz - 1) * V.nxy, z1 = min(max(iz + 1, 0), V.nz - 1) * V.nxy;
-    const float* __restrict__ d = V.density;
-    const float c000 = d[z0 + y0 + x0], c001 = d[z0 + y0 + x1];
-    const float c010 = d[z0 + y1 + x0], c011 = d[z0 + y1 + x1];
-    const float c100 = d[z1 + y0 + x0], c101 = d[z1 + y0 + x1];
-    const float c110 = d[z1 + y1 + x0], c111 = d[z1 + y1 + x1];
-    const float a00 = c000 + fx * (c001 - c000), a01 = c010 + fx * (c011 - c010);
-    const float a10 = c100 + fx * (c101 - c100), a11 = c110 + fx * (c111 - c110);
-    const float b0 = a00 + fy * (a01 - a00), b1 = a10 + fy * (a11 - a10);
-    if (WANT_STENCIL) {
-        const float gx0 = 1.0f - fx, gy0 = 1.0f - fy, gz0 = 1.0f - fz;
-        vox[0] = z0 + y0 + x0; wt[0] = gx0 * gy0 * gz0;
-        vox[1] = z0 + y0 + x1; wt[1] = fx * gy0 * gz0;
-        vox[2] = z0 + y1 + x0; wt[2] = gx0 * fy * gz0;
-        vox[3] = z0 + y1 + x1; wt[3] = fx * fy * gz0;
-        vox[4] = z1 + y0 + x0; wt[4] = gx0 * gy0 * fz;
-        vox[5] = z1 + y0 + x1; wt[5] = fx * gy0 * fz;
-        vox[6] = z1 + y1 + x0; wt[6] = gx0 * fy * fz;
-        vox[7] = z1 + y1 + x1; wt[7] = fx * fy * fz;
-    }
-    return b0 + fz * (b1 - b0);
-}
-
-// The same density and material from the cell records (one 32-byte record;
-// the voxel array only for the material of a cell whose corners differ).
+// voxels; or the containing voxel's) and the containing voxel's material, from
+// the cell records (one 32-byte record; the voxel array only for the material
+// of a cell whose corners differ).
 // The containing voxel is corner (f >= 1/2) of the cell along each axis.
 __device__ __forceinline__ float cell_density(const DVolume& V, bool interp, float px, float py, float pz,
                                               int& mat) {
@@ -185,7 +142,7 @@ struct Photon {
     uint32_t pair;             // flight pairs opened so far (Philox step of the flight block)
     float sel;                 // pending collision: ladder / rho, compared with mu_R and mu_R + mu_C
     int pm;                    // pending collision: material
-    float w;                   // adjoint weight of the history
+    double w;                  // adjoint weight of the history
 };
 
 // Source photon (Sec. 2.1/2.4): aim pixel and energy channel by inverse CDF
@@ -295,8 +252,8 @@ __device__ __forceinline__ void finish(const KParams& P, const Tables& T, const 
         const int npix = J.nu * J.nv;
         const double a = P.adj[J.adj_off + (cls == kPrimary ? 0 : npix) + pixel];
         const float r = fminf(fmaxf(response_at(P, T, ph.ec, ph.E), 0.0f), kMaxResponse);
-        const float w = (float)(a * (double)r / n);
-        if (w != 0.0f) {
+        const double w = a * (double)r / n;
+        if (w != 0.0) {
             ph.w = w;
             ph.passb = true;
             ph.st = start_photon(P, T, V, vol_off, ph) ? kFly : kDead;
@@ -306,19 +263,40 @@ __device__ __forceinline__ void finish(const KParams& P, const Tables& T, const 
     ph.st = kDead;
 }
 
-// Score-function terms of one tentative collision (adjoint, second pass).
+// Score-function terms of one tentative collision (adjoint, second pass):
+// base w_v / rho (real) or -mu_tot w_v / (mbar - rho mu_tot) (null) times the
+// history's weight, added to every stencil voxel v.  The stencil -- the eight
+// lattice corners of the interpolation (clamped to the edge voxels, so a
+// clamped corner repeats a voxel) and their weights, or the containing voxel --
+// comes from the position alone: rho is the density the collision test has
+// just computed, so no voxel is read again.
 __device__ __forceinline__ void visit(const KParams& P, const DVolume& V, bool interp, const Photon& ph,
                                       bool real, float rho, float tot, float mbar) {
-    int vox[8];
-    float wt[8];
-    int m;
-    density_at<true>(V, interp, ph.px, ph.py, ph.pz, m, vox, wt);
-    const int n = interp ? 8 : 1;
     const float base = real ? 1.0f / rho : -tot / (mbar - rho * tot);
-    for (int k = 0; k < n; ++k) {
-        const float s = base * wt[k];
-        if (s != 0.0f) unsafeAtomicAdd(P.grad + vox[k], (double)ph.w * (double)s);
+    const float gx = (ph.px - V.lox) * V.idx, gy = (ph.py - V.loy) * V.idy, gz = (ph.pz - V.loz) * V.idz;
+    if (!interp) {
+        const int cx = min(max((int)floorf(gx), 0), V.nx - 1);
+        const int cy = min(max((int)floorf(gy), 0), V.ny - 1);
+        const int cz = min(max((int)floorf(gz), 0), V.nz - 1);
+        if (base != 0.0f) unsafeAtomicAdd(P.grad + (cz * V.nxy + cy * V.nx + cx), ph.w * (double)base);
+        return;
     }
+    const float hx = gx - 0.5f, hy = gy - 0.5f, hz = gz - 0.5f;
+    const float fx0 = floorf(hx), fy0 = floorf(hy), fz0 = floorf(hz);
+    const float fx = hx - fx0, fy = hy - fy0, fz = hz - fz0;
+    const int ix = (int)fx0, iy = (int)fy0, iz = (int)fz0;
+    const int x0 = min(max(ix, 0), V.nx - 1), x1 = min(max(ix + 1, 0), V.nx - 1);
+    const int y0 = min(max(iy, 0), V.ny - 1) * V.nx, y1 = min(max(iy + 1, 0), V.ny - 1) * V.nx;
+    const int z0 = min(max(iz, 0), V.nz - 1) * V.nxy, z1 = min(max(iz + 1, 0), V.nz - 1) * V.nxy;
+    const float gx0 = 1.0f - fx, gy0 = 1.0f - fy, gz0 = 1.0f - fz;
+    const int vox[8] = {z0 + y0 + x0, z0 + y0 + x1, z0 + y1 + x0, z0 + y1 + x1,
+                        z1 + y0 + x0, z1 + y0 + x1, z1 + y1 + x0, z1 + y1 + x1};
+    const float wt[8] = {gx0 * gy0 * gz0, fx * gy0 * gz0, gx0 * fy * gz0, fx * fy * gz0,
+                         gx0 * gy0 * fz, fx * gy0 * fz, gx0 * fy * fz, fx * fy * fz};
+    const double wb = ph.w * (double)base;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (wt[k] != 0.0f) unsafeAtomicAdd(P.grad + vox[k], wb * (double)wt[k]);
 }
 
 // One Woodcock free flight with uniforms (ra, rb): flight length -ln(u)/mbar,
@@ -553,7 +531,7 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
     Photon ph;
     ph.st = kDead;
     ph.passb = false;
-    ph.w = 0.0f;
+    ph.w = 0.0;
     ph.job = 0;
     ph.pid = 0;
     ph.jid = 0;
@@ -646,14 +624,15 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
         // ---- collision: interaction type and sampling ----
         const int n_coll2 = __popcll(__ballot(ph.st == kColl));
         const int n_fly2 = __popcll(__ballot(ph.st == kFly));
-        if (n_coll2 > 0 && (n_coll2 >= P.defer || n_fly2 == 0 || w_done || w_hold)) {
+        if (n_coll2 > 0 && (n_coll2 >= P.cdefer || n_fly2 == 0 || w_done || w_hold)) {
             if (ph.st == kColl) collide<MODE>(P, T, V, vo, ph);
         }
     }
 }
 
+// The forward and trace transport: at most 80 VGPRs (6 wavefronts per SIMD).
 template <int MODE, int LOCAL>
-__global__ __launch_bounds__(1024) void mc_kernel(KParams P) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void mc_kernel(KParams P) {
     mc_body<MODE, LOCAL>(P);
 }
 

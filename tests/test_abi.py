@@ -54,7 +54,7 @@ int main(void) {
     F(gdrr_physics, mu_mass) F(gdrr_physics, response) F(gdrr_physics, rayleigh_x0_invA) F(gdrr_physics, e_cut_kev)
     F(gdrr_source, spec_e_kev) F(gdrr_source, fu) F(gdrr_source, fluence) F(gdrr_source, spec_rows)
     F(gdrr_job, geom) F(gdrr_job, n_photons) F(gdrr_job, job_id) F(gdrr_job, first_photon) F(gdrr_job, tally_offset)
-    F(gdrr_tuning, defer) F(gdrr_tuning, scheme)
+    F(gdrr_tuning, defer) F(gdrr_tuning, coll_defer)
     return 0;
 }
 """

@@ -166,10 +166,11 @@ def test_local_adjoint_matches_oracle(gpu):
     assert rel <= 0.02
 
 
-def test_unknown_scheme_rejected(gpu):
+def test_bad_collision_deferral_rejected(gpu):
     prob = body_problem(1000)
     vol, phys, src = gpu.upload(prob)
     vol.local_majorants(4)
     b = gpu.Batch([vol], phys, [src], [gpu.JobSpec(prob.geom, 1000, 0)])
-    with pytest.raises(gpu._abi.GdrrError):
-        b.project(seed=1, tune=dict(scheme=2))
+    for bad in (-1, 65):
+        with pytest.raises(gpu._abi.GdrrError):
+            b.project(seed=1, tune=dict(coll_defer=bad))

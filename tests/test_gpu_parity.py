@@ -201,8 +201,9 @@ def test_multi_phantom_batch_any_launch_shape(gpu):
     src = gpu.DeviceSource(*W.mono_spectrum(70.0), W.fluence_map(prob.geom))
     jobs = [gpu.JobSpec(prob.geom.replace(phi_rad=0.3 * k), 40_000 + 977 * k, k, volume=k % 3) for k in range(9)]
     b = gpu.Batch(vols, phys, [src], jobs)
-    ref = b.project(seed=6, tune=dict(scheme=1))
-    for t in (dict(block=128, chunk=64, defer=4), dict(block=1024), dict(block=512, chunk=256, blocks_per_cu=1)):
+    ref = b.project(seed=6)
+    for t in (dict(block=128, chunk=64, defer=4), dict(block=1024), dict(block=512, chunk=256, blocks_per_cu=1),
+              dict(block=256, defer=8, coll_defer=48), dict(block=512, defer=40, coll_defer=1)):
         assert torch.equal(b.project(seed=6, tune=t), ref), t
 
 
