@@ -182,6 +182,28 @@ def measured_traffic(path, workload, kernel=None):
     return round(rec["fetch_bytes"] + rec["write_bytes"], 0)
 
 
+def measured_counters(path, workload, kernel=None):
+    """rocprofv3 counter readings of a kernel (active-lane fraction, VALU
+    instruction rate and the issue-utilisation bounds priced from the
+    issue-rate calibration, L2 hit rate), if taken on the current kernel
+    sources; `kernel` selects a secondary record ("adjoint", ...)."""
+    if not path or not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path)).get(workload)
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("kernel_sha") != kernel_sources_sha():
+        return None
+    if kernel is not None:
+        rec = rec.get("others", {}).get(kernel)
+    if not rec or "counters" not in rec:
+        return None
+    c = {k: v for k, v in rec["counters"].items() if k != "duration_ms"}
+    c["kernel"] = rec["kernel"]
+    return c
+
+
 TUNE_MODE = "auto"
 TUNE_CACHE = None
 MAJORANT = "local"
@@ -738,6 +760,8 @@ def main():
                 warmup=args.warmup, ms_per_step=round(ms_step, 2), higher_is_better=True, scaling="weak",
                 vs_baseline=None, dtype="f32", data="synthetic",
                 config=wl["config"], roofline=roof, cpu_baseline=cpu,
+                counters=measured_counters(args.traffic, args.workload),
+                adjoint_counters=measured_counters(args.traffic, args.workload, "adjoint") if wl["adj"] else None,
                 fwd_histories_per_s=round(fwd_rate, 1),
                 adj_histories_per_s=round(adj_rate, 1) if adj_rate else None,
                 single_projection=single,

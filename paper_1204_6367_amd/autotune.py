@@ -12,6 +12,7 @@ from __future__ import annotations
 import hashlib
 import json
 import os
+import sys
 from typing import Dict, Iterable, List, Optional
 
 import torch
@@ -42,7 +43,12 @@ def kernel_sha() -> str:
 def workload_key(batch: "api.Batch", mode: str = "forward", interp: bool = True) -> str:
     vols = ";".join("x".join(map(str, v.shape)) + (f"/m{v.macro}" if v.macro else "") for v in batch.vols)
     dets = sorted({(j.geom.nu, j.geom.nv) for j in batch.jobs})
-    dev = torch.cuda.get_device_name() if torch.cuda.is_available() else "cpu"
+    # the architecture and CU count, not the marketing name (which depends on the host's ids file)
+    if torch.cuda.is_available():
+        pr = torch.cuda.get_device_properties(torch.cuda.current_device())
+        dev = f"{pr.gcnArchName.split(':')[0]}/{pr.multi_processor_count}cu"
+    else:
+        dev = "cpu"
     return (f"vols={vols}|det={dets}|jobs={len(batch.jobs)}|mode={mode}|interp={int(interp)}"
             f"|src={kernel_sha()}|dev={dev}")
 
@@ -71,6 +77,8 @@ def autotune(batch: "api.Batch", candidates: Optional[Iterable[Dict[str, int]]] 
             table = {}
     if not force and key in table:
         return dict(table[key]["tuning"])
+    if not force:
+        print(f"autotune: no cached shape for {key} in {cache}", file=sys.stderr, flush=True)
     small = _reduced(batch, fraction, min_photons)
     maj = small.majorants(interp)
     adj = None

@@ -43,7 +43,29 @@ def test_shipped_traffic_record_names_its_summary():
     rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["c4"]
     assert os.path.exists(os.path.join(ROOT, rec["summary"]))
     assert rec["fetch_bytes"] > 0 and rec["write_bytes"] > 0
-    assert set(rec["others"]) == {"raytrace", "denoise"}
+    assert set(rec["others"]) == {"raytrace", "denoise", "adjoint"}
+    # the counter readings the benchmark line carries
+    c = rec["counters"]
+    assert 0.0 < c["lanes_active"] <= 1.0 and 0.0 < c["l2_hit"] < 1.0
+    lo, hi = c["valu_issue_util"]
+    assert 0.0 < lo <= hi <= 1.0
+
+
+def test_measured_counters_follow_the_kernel_sources(tmp_path):
+    sha = bench.kernel_sources_sha()
+    ctr = {"lanes_active": 0.3, "valu_inst_rate": 1.05, "valu_issue_util": [0.8, 1.0], "l2_hit": 0.45,
+           "duration_ms": 3.0}
+    rec = {"c4": {"kernel": "k", "kernel_sha": sha, "counters": ctr,
+                  "others": {"adjoint": {"kernel": "a", "counters": dict(ctr, lanes_active=0.2)}}}}
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps(rec))
+    got = bench.measured_counters(str(p), "c4")
+    assert got["lanes_active"] == 0.3 and got["kernel"] == "k" and "duration_ms" not in got
+    assert bench.measured_counters(str(p), "c4", "adjoint")["lanes_active"] == 0.2
+    assert bench.measured_counters(str(p), "c4", "raytrace") is None
+    rec["c4"]["kernel_sha"] = "0" * 16
+    p.write_text(json.dumps(rec))
+    assert bench.measured_counters(str(p), "c4") is None
 
 
 def test_work_model_composition():
