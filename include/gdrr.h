@@ -38,8 +38,10 @@
  * array, is a DEVICE pointer owned by the caller; the struct pointers
  * themselves are host pointers read during the call.  All calls are
  * asynchronous on `stream` (a hipStream_t passed as void*; NULL = the null
- * stream) and may be recorded into a HIP graph.  The library keeps no device
- * memory between calls: scratch lives in the caller's workspace, which also
+ * stream) and may be recorded into a HIP graph.  The library allocates no
+ * device memory and keeps none between calls, apart from the fixed array in
+ * its code object behind gdrr_mc_project_static: scratch lives in the
+ * caller's workspace, which also
  * holds a per-call copy of each phantom laid out for the transport kernel
  * (32 bytes per cell of the lattice of voxel centres, (nx+1)(ny+1)(nz+1)
  * cells: the eight interpolation corners of the cell, the materials in their
