@@ -512,8 +512,14 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
                                    cubes(B.vols[v].nz, B.vols[v].macro);
                 }
     }
-    const size_t lds = lds_bytes(phys->n_mat, phys->n_e, B.n_vols, phys->response != nullptr) +
-                       (size_t)macro_lds_n * sizeof(uint2);
+    // the single-majorant tables are staged only if some traced volume tracks with them
+    bool any_single = false;
+    for (int v = 0; v < B.n_vols; ++v) any_single |= batch_uses(B, v) && B.vols[v].macro <= 0;
+    const int n_maj = any_single ? B.n_vols : 0;
+    // tables, cube records, then 64 source-draw slots of 16 bytes per wavefront
+    const size_t lds = draw_slots_offset_bytes(lds_bytes(phys->n_mat, phys->n_e, n_maj, phys->response != nullptr) +
+                                               (size_t)macro_lds_n * sizeof(uint2)) +
+                       (size_t)block * 16;
     if (lds > dev.lds_max) return fail(GDRR_ENOTSUP, "tables exceed the LDS of a workgroup");
     const int local_kind = !local ? 0 : (macro_lds_n > 0 ? 2 : 1);
     int per_cu = tune.blocks_per_cu;
@@ -663,7 +669,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
         d.loy = (float)(-0.5 * V.ny * V.dy_mm); d.hiy = -d.loy;
         d.loz = (float)(-0.5 * V.nz * V.dz_mm); d.hiz = -d.loz;
         d.idx = (float)(1.0 / V.dx_mm); d.idy = (float)(1.0 / V.dy_mm); d.idz = (float)(1.0 / V.dz_mm);
-        d.lds_majorant = v * (phys->n_e - 1);
+        d.lds_majorant = n_maj ? v * (phys->n_e - 1) : -1;
         d.macro = L.macro[v];
         if (V.macro > 0) {
             d.mnx = cubes(V.nx, V.macro); d.mny = cubes(V.ny, V.macro); d.mnz = cubes(V.nz, V.macro);
@@ -699,6 +705,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     kp.total_chunks = chunks;
     kp.n_jobs = B.n_jobs;
     kp.n_vols = B.n_vols;
+    kp.n_maj = n_maj;
     kp.n_mat = phys->n_mat;
     kp.n_e = phys->n_e;
     kp.e0 = phys->e0_kev;

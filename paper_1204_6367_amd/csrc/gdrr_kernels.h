@@ -35,6 +35,7 @@ struct KParams {
     const float* majorants;                   // [n_vols][n_e - 1], 1/cm
     unsigned long long total_chunks;
     int n_jobs, n_vols, n_mat, n_e;
+    int n_maj;                                // volumes whose single-majorant table is staged in LDS (0 or n_vols)
     float e0, inv_de, e_max, e_cut, x0;
     uint32_t k0, k1;
     uint32_t flags;
@@ -57,8 +58,8 @@ struct KParams {
 // LDS holds what every free flight reads: the total attenuation per
 // (material, grid point) and the majorants; interaction-type splits are read
 // from the global table at the (rarer) real collisions.
-__host__ __device__ inline size_t lds_bytes(int n_mat, int n_e, int n_vols, bool resp) {
-    return (size_t)n_mat * n_e * 8 + (size_t)n_vols * (n_e - 1) * 8 + (resp ? (size_t)n_e * 8 : 0);
+__host__ __device__ inline size_t lds_bytes(int n_mat, int n_e, int n_maj, bool resp) {
+    return (size_t)n_mat * n_e * 8 + (size_t)n_maj * (n_e - 1) * 8 + (resp ? (size_t)n_e * 8 : 0);
 }
 
 struct Tables {
@@ -73,11 +74,12 @@ struct ECache {
     float f, mbar, mfp;
 };
 
+// vol_off < 0: the volume tracks with local majorants and has no staged table.
 __device__ __forceinline__ ECache energy_cache(const KParams& P, const Tables& T, int vol_off, float E) {
     const float g = (E - P.e0) * P.inv_de;
     int j = (int)floorf(g);
     j = j < 0 ? 0 : (j > P.n_e - 2 ? P.n_e - 2 : j);
-    const float2 m = T.maj[vol_off + j];
+    const float2 m = vol_off >= 0 ? T.maj[vol_off + j] : make_float2(0.0f, 0.0f);
     return ECache{j, g - (float)j, m.x, m.y};
 }
 
@@ -145,24 +147,35 @@ struct Photon {
     double w;                  // adjoint weight of the history
 };
 
-// Source photon (Sec. 2.1/2.4): aim pixel and energy channel by inverse CDF
-// (the energy from the row of the pixel's column for a joint source), aim
-// point uniform inside the pixel, straight line from S to the phantom.
-// Returns true if the photon enters the phantom; otherwise it reaches its
-// aim pixel unscattered.
-__device__ __forceinline__ bool start_photon(const KParams& P, const Tables& T, const DVolume& V, int vol_off,
-                                             Photon& ph) {
-    const DJob& J = P.jobs[ph.job];
+// Source photon (Sec. 2.1/2.4), in two parts.  The draw: aim pixel and energy
+// channel by inverse CDF (the energy from the row of the pixel's column for a
+// joint source) and the two jitter words, from photon `pid`'s step-0 blocks
+// alone, so that a wavefront can draw for the next photons of its chunk all at
+// once.  Returns (pixel, channel, jitter word u, jitter word v).
+__device__ __forceinline__ uint4 draw_source(const KParams& P, int job, uint32_t pid) {
+    const DJob& J = P.jobs[job];
     const DSource& S = P.src[J.src];
-    const Block b0 = philox(ph.pid, ph.jid, 0u, 0u, P.k0, P.k1);
-    const Block b1 = philox(ph.pid, ph.jid, 0u, 1u, P.k0, P.k1);
+    const Block b0 = philox(pid, J.job_id, 0u, 0u, P.k0, P.k1);
+    const Block b1 = philox(pid, J.job_id, 0u, 1u, P.k0, P.k1);
     const int kf = sample_cdf(S.flu_cdf, S.flu_guide, S.npix, S.flu_k, u53(b0.z, b0.w));
-    const int iv = kf / J.nu, iu = kf - iv * J.nu;
+    const int iu = kf - (kf / J.nu) * J.nu;
     const int row = S.spec_rows > 1 ? iu : 0;
     const int ke = sample_cdf(S.spec_cdf + (size_t)row * S.n_spec, S.spec_guide + (size_t)row * S.spec_k, S.n_spec,
                               S.spec_k, u53(b0.x, b0.y));
-    const float uc = ((float)iu + u24(b1.x) - 0.5f * (float)J.nu) * J.du;
-    const float vc = ((float)iv + u24(b1.y) - 0.5f * (float)J.nv) * J.dv;
+    return make_uint4((uint32_t)kf, (uint32_t)ke, b1.x, b1.y);
+}
+
+// The rest of the start: aim point uniform inside the pixel, straight line from
+// S to the phantom.  Returns true if the photon enters the phantom; otherwise
+// it reaches its aim pixel unscattered.
+__device__ __forceinline__ bool start_from_draw(const KParams& P, const Tables& T, const DVolume& V, int vol_off,
+                                                Photon& ph, uint4 d) {
+    const DJob& J = P.jobs[ph.job];
+    const DSource& S = P.src[J.src];
+    const int kf = (int)d.x, ke = (int)d.y;
+    const int iv = kf / J.nu, iu = kf - iv * J.nu;
+    const float uc = ((float)iu + u24(d.z) - 0.5f * (float)J.nu) * J.du;
+    const float vc = ((float)iv + u24(d.w) - 0.5f * (float)J.nv) * J.dv;
     float dx = J.Px + uc * J.ux - J.Sx;
     float dy = J.Py + uc * J.uy - J.Sy;
     float dz = J.Pz + uc * J.uz + vc - J.Sz;
@@ -184,6 +197,11 @@ __device__ __forceinline__ bool start_photon(const KParams& P, const Tables& T, 
         return true;
     }
     return false;
+}
+
+__device__ __forceinline__ bool start_photon(const KParams& P, const Tables& T, const DVolume& V, int vol_off,
+                                             Photon& ph) {
+    return start_from_draw(P, T, V, vol_off, ph, draw_source(P, ph.job, ph.pid));
 }
 
 // Detector hit of a photon leaving the phantom: the primary pixel for an
@@ -483,7 +501,7 @@ __device__ __forceinline__ void collide(const KParams& P, const Tables& T, const
 __device__ __forceinline__ Tables stage_tables(const KParams& P, float2* lds) {
     float2* s_tot = lds;
     float2* s_maj = s_tot + P.n_mat * P.n_e;
-    float2* s_resp = s_maj + P.n_vols * (P.n_e - 1);
+    float2* s_resp = s_maj + P.n_maj * (P.n_e - 1);
     for (int i = threadIdx.x; i < P.n_mat * P.n_e; i += blockDim.x) {
         const int j = i / P.n_mat, m = i - j * P.n_mat;
         const float* a = P.mu_mass + ((size_t)m * P.n_e + j) * 3;
@@ -491,7 +509,7 @@ __device__ __forceinline__ Tables stage_tables(const KParams& P, float2* lds) {
         const float t0 = a[0] + a[1] + a[2], t1 = b[0] + b[1] + b[2];
         s_tot[i] = make_float2(t0, t1 - t0);
     }
-    for (int i = threadIdx.x; i < P.n_vols * (P.n_e - 1); i += blockDim.x) {
+    for (int i = threadIdx.x; i < P.n_maj * (P.n_e - 1); i += blockDim.x) {
         const float mb = P.majorants[i];
         s_maj[i] = make_float2(mb, mb > 0.0f ? 1.0f / (0.1f * mb) : INFINITY);
     }
@@ -503,8 +521,14 @@ __device__ __forceinline__ Tables stage_tables(const KParams& P, float2* lds) {
     return Tables{s_tot, s_maj, s_resp};
 }
 
-__host__ __device__ inline size_t table_floats2(int n_mat, int n_e, int n_vols, bool resp) {
-    return (size_t)n_mat * n_e + (size_t)n_vols * (n_e - 1) + (resp ? (size_t)n_e : 0);
+__host__ __device__ inline size_t table_floats2(int n_mat, int n_e, int n_maj, bool resp) {
+    return (size_t)n_mat * n_e + (size_t)n_maj * (n_e - 1) + (resp ? (size_t)n_e : 0);
+}
+
+// Per wavefront, after the tables and cube records: 64 slots of source draws
+// (16 bytes each), starting at a 16-byte boundary.
+__host__ __device__ inline size_t draw_slots_offset_bytes(size_t tables_and_records_bytes) {
+    return (tables_and_records_bytes + 15) & ~(size_t)15;
 }
 
 // LOCAL: 0 = every volume has one majorant per energy interval; 1 = some
@@ -516,7 +540,11 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
     extern __shared__ float2 lds[];
     const Tables T = stage_tables(P, lds);
     // local majorants small enough to stage: every volume's cube records after the tables
-    uint2* lds_macro = reinterpret_cast<uint2*>(lds + table_floats2(P.n_mat, P.n_e, P.n_vols, P.response != nullptr));
+    uint2* lds_macro = reinterpret_cast<uint2*>(lds + table_floats2(P.n_mat, P.n_e, P.n_maj, P.response != nullptr));
+    // this wavefront's source-draw slots: offset (bytes) of the first from the LDS base (wavefront-uniform)
+    const uint32_t draws_off = __builtin_amdgcn_readfirstlane(
+        (int)(draw_slots_offset_bytes(table_floats2(P.n_mat, P.n_e, P.n_maj, P.response != nullptr) * 8 +
+                                      (size_t)P.macro_lds_n * 8) + (threadIdx.x & ~63u) * 16u));
     if (LOCAL == 2)
         for (int v = 0; v < P.n_vols; ++v) {
             if (P.macro_lds[v] < 0 || !P.vol[v].macro) continue;
@@ -540,9 +568,9 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
     ph.pair = 0u;
     ph.pm = 0;
 
-    // wavefront-uniform dispenser state
+    // wavefront-uniform dispenser state; the draw slots hold photons [d_first, d_end) of the chunk
     int w_vol = -1, w_job = 0, w_hold = 0, w_done = 0;
-    uint32_t w_next = 0, w_end = 0;
+    uint32_t w_next = 0, w_end = 0, d_first = 0, d_end = 0;
 
     for (;;) {
         const uint64_t dead = __ballot(ph.st == kDead);
@@ -576,6 +604,7 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
                     // photon indices J.first + [first, last); J.first + nph < 2^32
                     w_next = (uint32_t)__builtin_amdgcn_readfirstlane((int)(J.first + (uint32_t)first));
                     w_end = (uint32_t)__builtin_amdgcn_readfirstlane((int)(J.first + (uint32_t)last));
+                    d_first = d_end = w_next;                  // no draws of this chunk yet
                     const int v = __builtin_amdgcn_readfirstlane(J.vol);
                     if (v != w_vol) {
                         if (n_dead == 64) w_vol = v; else w_hold = 1;
@@ -583,7 +612,17 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
                 }
             }
             if (!w_done && !w_hold) {
-                const uint32_t avail = w_end - w_next;
+                // Not enough drawn photons left for the waiting lanes: every lane draws one of the
+                // chunk's next 64 photons (the draws of a photon depend on its index alone).
+                if (w_next + (uint32_t)n_dead > d_end && d_end < w_end) {
+                    const uint32_t nd = w_end - w_next < 64u ? w_end - w_next : 64u;
+                    uint4* draws = reinterpret_cast<uint4*>(reinterpret_cast<char*>(lds) + draws_off);
+                    if ((uint32_t)lane < nd) draws[lane] = draw_source(P, w_job, w_next + (uint32_t)lane);
+                    d_first = w_next;
+                    d_end = w_next + nd;
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");   // the slots are read by other lanes
+                }
+                const uint32_t avail = d_end - w_next;
                 const uint32_t rank = (uint32_t)__popcll(dead & lt);
                 if (ph.st == kDead && rank < avail) {
                     ph.pid = w_next + rank;
@@ -592,7 +631,8 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
                     ph.passb = false;
                     const DVolume& V = P.vol[w_vol];
                     const int vo = V.lds_majorant;
-                    if (start_photon(P, T, V, vo, ph)) ph.st = kFly;
+                    const uint4* draws = reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(lds) + draws_off);
+                    if (start_from_draw(P, T, V, vo, ph, draws[ph.pid - d_first])) ph.st = kFly;
                     else finish<MODE>(P, T, V, vo, ph, kPrimary, ph.pix0);
                 }
                 w_next += (uint32_t)n_dead < avail ? (uint32_t)n_dead : avail;
