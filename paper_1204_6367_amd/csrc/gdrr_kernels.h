@@ -466,7 +466,7 @@ __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, 
 // A real collision (Sec. 2.4): the ladder value picks Rayleigh, Compton or
 // photoelectric absorption; scattering samples the angle, updates energy and
 // direction and the distance to the phantom's boundary.
-template <int MODE>
+template <int MODE, bool ALL_LOCAL>
 __device__ __forceinline__ void collide(const KParams& P, const Tables& T, const DVolume& V, int vo, Photon& ph) {
     const int m = ph.pm;
     const float* a = P.mu_mass + ((size_t)m * P.n_e + ph.ec.j) * 3;   // j <= n_e - 2
@@ -493,7 +493,7 @@ __device__ __forceinline__ void collide(const KParams& P, const Tables& T, const
         ph.st = kDead;
         return;
     }
-    if (!V.macro) ph.trem = box_exit(V, ph.px, ph.py, ph.pz, ph.dx, ph.dy, ph.dz);   // local majorants walk cubes instead
+    if (!ALL_LOCAL && !V.macro) ph.trem = box_exit(V, ph.px, ph.py, ph.pz, ph.dx, ph.dy, ph.dz);   // local majorants walk cubes instead
     ph.st = kFly;
 }
 
@@ -533,8 +533,10 @@ __host__ __device__ inline size_t draw_slots_offset_bytes(size_t tables_and_reco
 
 // LOCAL: 0 = every volume has one majorant per energy interval; 1 = some
 // volume tracks with local majorants, cube records read from global memory;
-// 2 = the same with every such volume's records staged in LDS.  Separate
-// instantiations, so that the single-majorant loop keeps its register budget.
+// 2 = the same with every such volume's records staged in LDS; 3 = every
+// traced volume tracks with local majorants, records in LDS (no
+// single-majorant flight in the code at all).  Separate instantiations, so
+// that each loop keeps its register budget.
 template <int MODE, int LOCAL>
 __device__ __forceinline__ void mc_body(const KParams& P) {
     extern __shared__ float2 lds[];
@@ -545,7 +547,7 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
     const uint32_t draws_off = __builtin_amdgcn_readfirstlane(
         (int)(draw_slots_offset_bytes(table_floats2(P.n_mat, P.n_e, P.n_maj, P.response != nullptr) * 8 +
                                       (size_t)P.macro_lds_n * 8) + (threadIdx.x & ~63u) * 16u));
-    if (LOCAL == 2)
+    if (LOCAL >= 2)
         for (int v = 0; v < P.n_vols; ++v) {
             if (P.macro_lds[v] < 0 || !P.vol[v].macro) continue;
             const int n = P.vol[v].mnx * P.vol[v].mny * P.vol[v].mnz;
@@ -649,15 +651,17 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
         if (ph.st == kFly) {
             ph.pair += 1u;
             const Block b = philox(ph.pid, ph.jid, ph.pair, 0u, P.k0, P.k1);
-            if (LOCAL == 2 && V.macro) {
+            if (LOCAL == 3 || (LOCAL == 2 && V.macro)) {
                 const uint2* lr = lds_macro + P.macro_lds[w_vol];
                 if (flight_local<MODE, true>(P, T, V, vo, interp, ph, b.x, b.y, lr))
                     flight_local<MODE, true>(P, T, V, vo, interp, ph, b.z, b.w, lr);
-            } else if (LOCAL == 1 && V.macro) {
-                if (flight_local<MODE, false>(P, T, V, vo, interp, ph, b.x, b.y, nullptr))
-                    flight_local<MODE, false>(P, T, V, vo, interp, ph, b.z, b.w, nullptr);
-            } else if (flight<MODE>(P, T, V, vo, interp, ph, b.x, b.y)) {
-                flight<MODE>(P, T, V, vo, interp, ph, b.z, b.w);
+            } else if constexpr (LOCAL != 3) {
+                if (LOCAL == 1 && V.macro) {
+                    if (flight_local<MODE, false>(P, T, V, vo, interp, ph, b.x, b.y, nullptr))
+                        flight_local<MODE, false>(P, T, V, vo, interp, ph, b.z, b.w, nullptr);
+                } else if (flight<MODE>(P, T, V, vo, interp, ph, b.x, b.y)) {
+                    flight<MODE>(P, T, V, vo, interp, ph, b.z, b.w);
+                }
             }
         }
 
@@ -665,7 +669,7 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
         const int n_coll2 = __popcll(__ballot(ph.st == kColl));
         const int n_fly2 = __popcll(__ballot(ph.st == kFly));
         if (n_coll2 > 0 && (n_coll2 >= P.cdefer || n_fly2 == 0 || w_done || w_hold)) {
-            if (ph.st == kColl) collide<MODE>(P, T, V, vo, ph);
+            if (ph.st == kColl) collide<MODE, LOCAL == 3>(P, T, V, vo, ph);
         }
     }
 }
