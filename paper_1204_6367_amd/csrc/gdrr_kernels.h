@@ -380,22 +380,23 @@ __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, 
     int by = min(max((int)floorf((ph.py - V.loy) * V.imy), 0), V.mny - 1);
     int bz = min(max((int)floorf((ph.pz - V.loz) * V.imz), 0), V.mnz - 1);
     // Distances along the line (from the flight's start) to the next cube face
-    // on each axis, advanced by one cube edge per crossing (Amanatides-Woo);
-    // on the positive side the last cube ends at the box face.
+    // on each axis, advanced by one cube edge per crossing (Amanatides-Woo).
     const float rx = ph.dx != 0.0f ? fast_rcp(ph.dx) : 0.0f;
     const float ry = ph.dy != 0.0f ? fast_rcp(ph.dy) : 0.0f;
     const float rz = ph.dz != 0.0f ? fast_rcp(ph.dz) : 0.0f;
     const int sx = ph.dx > 0.0f ? 1 : (ph.dx < 0.0f ? -1 : 0);
     const int sy = ph.dy > 0.0f ? 1 : (ph.dy < 0.0f ? -1 : 0);
     const int sz = ph.dz > 0.0f ? 1 : (ph.dz < 0.0f ? -1 : 0);
-    const float bex = sx > 0 ? (V.hix - ph.px) * rx : INFINITY;       // box exit on the positive side
-    const float bey = sy > 0 ? (V.hiy - ph.py) * ry : INFINITY;
-    const float bez = sz > 0 ? (V.hiz - ph.pz) * rz : INFINITY;
-    float tmx = sx > 0 ? fminf((V.lox + (float)(bx + 1) * V.mex - ph.px) * rx, bex)
+    // where the line leaves the box through a face on the positive side of an axis (the last
+    // cube there may reach past the face); leaving through a negative side is the cube index
+    // leaving the grid
+    const float tex = fminf(sx > 0 ? (V.hix - ph.px) * rx : INFINITY,
+                            fminf(sy > 0 ? (V.hiy - ph.py) * ry : INFINITY, sz > 0 ? (V.hiz - ph.pz) * rz : INFINITY));
+    float tmx = sx > 0 ? (V.lox + (float)(bx + 1) * V.mex - ph.px) * rx
               : (sx < 0 ? (V.lox + (float)bx * V.mex - ph.px) * rx : INFINITY);
-    float tmy = sy > 0 ? fminf((V.loy + (float)(by + 1) * V.mey - ph.py) * ry, bey)
+    float tmy = sy > 0 ? (V.loy + (float)(by + 1) * V.mey - ph.py) * ry
               : (sy < 0 ? (V.loy + (float)by * V.mey - ph.py) * ry : INFINITY);
-    float tmz = sz > 0 ? fminf((V.loz + (float)(bz + 1) * V.mez - ph.pz) * rz, bez)
+    float tmz = sz > 0 ? (V.loz + (float)(bz + 1) * V.mez - ph.pz) * rz
               : (sz < 0 ? (V.loz + (float)bz * V.mez - ph.pz) * rz : INFINITY);
     const float dtx = V.mex * fabsf(rx), dty = V.mey * fabsf(ry), dtz = V.mez * fabsf(rz);
     const float2* tot = T.tot + ph.ec.j * P.n_mat;
@@ -416,7 +417,8 @@ __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, 
         }
         mb = __uint_as_float(rec.x) * tmax;
         const float tnext = fminf(tmx, fminf(tmy, tmz));
-        const float span = tnext - t;
+        const float tn = tnext < tex ? tnext : tex;                    // the cube's exit, within the box
+        const float span = tn - t;
         const float need = 0.1f * mb * (span > 0.0f ? span : 0.0f);   // mbar in 1/cm, lengths in mm
         if (mb > 0.0f && tau < need) {
             t += tau * fast_rcp(0.1f * mb);
@@ -424,16 +426,16 @@ __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, 
             break;
         }
         tau -= need;
-        t = tnext > t ? tnext : t;
+        t = tn > t ? tn : t;
+        if (!(tn < tex)) break;                                        // left the box
         const bool ax = tmx <= tmy && tmx <= tmz, ay = !ax && tmy <= tmz, az = !ax && !ay;
         bx += ax ? sx : 0;
         by += ay ? sy : 0;
         bz += az ? sz : 0;
         ci += ax ? cix : (ay ? ciy : ciz);
-        const float nx = tmx + dtx, ny = tmy + dty, nz = tmz + dtz;
-        tmx = ax ? (nx < bex ? nx : bex) : tmx;
-        tmy = ay ? (ny < bey ? ny : bey) : tmy;
-        tmz = az ? (nz < bez ? nz : bez) : tmz;
+        tmx = ax ? tmx + dtx : tmx;
+        tmy = ay ? tmy + dty : tmy;
+        tmz = az ? tmz + dtz : tmz;
         if ((unsigned)bx >= (unsigned)V.mnx || (unsigned)by >= (unsigned)V.mny || (unsigned)bz >= (unsigned)V.mnz)
             break;
     }
