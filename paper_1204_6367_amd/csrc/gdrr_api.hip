@@ -444,7 +444,7 @@ int check_batch(const Batch& B) {
 }
 
 // local: 0 single majorants, 1 local majorants with records in global memory, 2 with records in LDS,
-// 3 every traced volume with local majorants and records in LDS
+// 3 every traced volume with local majorants and records in LDS, interpolated density
 template <int MODE>
 const void* mc_func(int local) {
     if constexpr (MODE == kModeBackward)
@@ -524,7 +524,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
                                                (size_t)macro_lds_n * sizeof(uint2)) +
                        (size_t)block * 16;
     if (lds > dev.lds_max) return fail(GDRR_ENOTSUP, "tables exceed the LDS of a workgroup");
-    const int local_kind = !local ? 0 : (macro_lds_n > 0 ? (any_single ? 2 : 3) : 1);
+    const int local_kind = !local ? 0 : (macro_lds_n > 0 ? (any_single || !interp ? 2 : 3) : 1);
     int per_cu = tune.blocks_per_cu;
     if (!per_cu) {
         const void* f = mc_func_for(B.mode, local_kind);

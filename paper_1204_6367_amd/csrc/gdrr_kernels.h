@@ -536,9 +536,10 @@ __host__ __device__ inline size_t draw_slots_offset_bytes(size_t tables_and_reco
 // LOCAL: 0 = every volume has one majorant per energy interval; 1 = some
 // volume tracks with local majorants, cube records read from global memory;
 // 2 = the same with every such volume's records staged in LDS; 3 = every
-// traced volume tracks with local majorants, records in LDS (no
-// single-majorant flight in the code at all).  Separate instantiations, so
-// that each loop keeps its register budget.
+// traced volume tracks with local majorants, records in LDS, and density is
+// interpolated (no single-majorant flight and no nearest-voxel lookup in the
+// code at all).  Separate instantiations, so that each loop keeps its
+// register budget.
 template <int MODE, int LOCAL>
 __device__ __forceinline__ void mc_body(const KParams& P) {
     extern __shared__ float2 lds[];
@@ -556,7 +557,7 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
             for (int i = threadIdx.x; i < n; i += blockDim.x) lds_macro[P.macro_lds[v] + i] = P.vol[v].macro[i];
         }
     __syncthreads();
-    const bool interp = (P.flags & 1u) != 0;
+    const bool interp = LOCAL == 3 || (P.flags & 1u) != 0;
     const int lane = __lane_id();
     const uint64_t lt = (1ull << lane) - 1ull;
 
@@ -683,9 +684,12 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void 
 }
 
 // The adjoint: at most 96 VGPRs (5 wavefronts per SIMD), where it would
-// otherwise take 97 and drop to 4.
+// otherwise take 97 and drop to 4; the all-local instantiation (85 VGPRs
+// unconstrained) at 80 and 6 wavefronts, measured faster despite 12 bytes of
+// spills.
 template <int LOCAL>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(5))) void mc_adjoint_kernel(KParams P) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LOCAL == 3 ? 6 : 5))) void mc_adjoint_kernel(
+    KParams P) {
     mc_body<kModeBackward, LOCAL>(P);
 }
 
