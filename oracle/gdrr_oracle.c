@@ -176,7 +176,8 @@ typedef struct {
     double* cdf_f;
     const double* mbar;                /* [n_e - 1], 1/cm */
     int nb[3];                         /* macro cells per axis (local majorants) */
-    double* mac_rho;                   /* [nbz][nby][nbx] largest density the cell's positions can show */
+    double* mac_rho;                   /* [nbz][nby][nbx] (1 + margin) x the largest density the cube's
+                                          positions can show, 19 significant bits rounded up */
     uint64_t* mac_mask;                /* materials its positions can take, one bit each */
     uint32_t key[2];
     uint32_t job;
@@ -489,7 +490,24 @@ void or_rotate(const double d[3], double cost, double ph, double out[3])
 /* length inside it); the collision point is where tau runs out, tested      */
 /* against that cube's mbar_B; running out of cubes is an escape.  rho_max   */
 /* may be raised to a floor macro_rho_min: any larger bound is still a bound. */
+/* Two more liberties a bound allows fix its exact values:                   */
+/*  - the density factor (1 + margin) max(rho_max, floor) is kept with 19    */
+/*    significant bits, rounded up;                                          */
+/*  - within an energy interval [E_j, E_j+1] the material factor is the      */
+/*    chord from max_{m in B} mu_tot(m, E_j) to max_{m in B} mu_tot(m,       */
+/*    E_j+1).  Each mu_tot(m, .) is linear on the interval, so their maximum */
+/*    is convex there and never above that chord; the two agree wherever one */
+/*    material is the largest at both ends, and always for one material.     */
 /* ------------------------------------------------------------------------ */
+
+/* The least number with 19 significant bits that is >= v (v >= 0). */
+static double round_up_19_bits(double v)
+{
+    if (!(v > 0.0)) return v;
+    int e;
+    const double m = frexp(v, &e);                 /* v = m 2^e, m in [1/2, 1) */
+    return ldexp(ceil(ldexp(m, 19)), e - 19);
+}
 static int build_macro(const or_problem* p, or_ctx* c)
 {
     const int M = p->macro;
@@ -519,7 +537,7 @@ static int build_macro(const or_problem* p, or_ctx* c)
                             mask |= (uint64_t)1 << p->material[v];
                         }
                 size_t bi = ((size_t)bz * c->nb[1] + by) * c->nb[0] + bx;
-                c->mac_rho[bi] = r;
+                c->mac_rho[bi] = round_up_19_bits((1.0 + p->macro_margin) * r);
                 c->mac_mask[bi] = mask;
             }
     return 0;
@@ -527,15 +545,19 @@ static int build_macro(const or_problem* p, or_ctx* c)
 
 static double macro_mbar(const or_problem* p, const or_ctx* c, size_t bi, double E)
 {
-    double best = 0.0;
+    double f;
+    const int j = e_interval(p, E, &f);
+    double t0 = 0.0, t1 = 0.0;                     /* max mu_tot of the cube's materials at E_j, E_j+1 */
     for (int m = 0; m < p->n_mat; ++m) {
         if (!((c->mac_mask[bi] >> m) & 1u)) continue;
-        double mu3[3];
-        xs_at(p, m, E, mu3);
-        double t = mu3[0] + mu3[1] + mu3[2];
-        if (t > best) best = t;
+        const float* a = p->mu + ((size_t)m * p->n_e + j) * 3;
+        const float* b = a + 3;
+        const double s0 = (double)a[0] + (double)a[1] + (double)a[2];
+        const double s1 = (double)b[0] + (double)b[1] + (double)b[2];
+        if (s0 > t0) t0 = s0;
+        if (s1 > t1) t1 = s1;
     }
-    return (1.0 + p->macro_margin) * c->mac_rho[bi] * best;
+    return c->mac_rho[bi] * (t0 + f * (t1 - t0));
 }
 
 /* Spends optical depth tau from pos along dir; on a collision moves pos there,
