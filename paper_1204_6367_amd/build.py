@@ -23,7 +23,7 @@ HIPCC_FLAGS = [
 
 # calibration programs behind the benchmark's rooflines (not part of the library): instruction
 # issue costs and random-gather throughput
-CALIB = ["issue_rate", "gather_rate"]      # paper_1204_6367_amd/calib/<name>.hip -> <name>
+CALIB = ["issue_rate", "gather_rate", "lds_granule"]      # paper_1204_6367_amd/calib/<name>.hip -> <name>
 
 
 def build(force: bool = True, verbose: bool = False) -> str:

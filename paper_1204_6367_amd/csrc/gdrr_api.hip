@@ -36,7 +36,7 @@ int fail(int code, const std::string& msg) {
 // --------------------------------------------------------------------------
 struct DevInfo {
     int cus = 0;
-    size_t lds_max = 0;
+    size_t lds_max = 0;      // per workgroup
     bool ok = false;
 };
 
@@ -114,6 +114,11 @@ int cubes(int n, int m) { return (n + m - 1) / m; }
 #define GDRR_MACRO_LDS_MAX (32 << 10)
 #endif
 constexpr size_t kMacroLdsMax = GDRR_MACRO_LDS_MAX;   // bytes of cube records staged in LDS
+// LDS allocation granule of a gfx950 workgroup (160 KiB / 128), as measured by
+// calib/lds_granule: three 512-thread workgroups share a compute unit up to 42
+// granules (53760 bytes) each, where hipOccupancyMaxActiveBlocksPerMultiprocessor
+// still reports three up to 54528.
+constexpr size_t kLdsGranule = 1280;
 
 int check_physics(const gdrr_physics* p) {
     if (!p) return fail(GDRR_EINVAL, "physics is NULL");
@@ -496,18 +501,23 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     bool local = false;
     for (int v = 0; v < B.n_vols; ++v) local |= B.vols[v].macro > 0;
     const int block = tune.block ? tune.block : 256;
+    // the single-majorant tables are staged only if some traced volume tracks with them
+    bool any_single = false;
+    for (int v = 0; v < B.n_vols; ++v) any_single |= batch_uses(B, v) && B.vols[v].macro <= 0;
+    const int n_maj = any_single ? B.n_vols : 0;
     // local majorants go to LDS (after the tables) while the records of all volumes that the
-    // launch traces fit in kMacroLdsMax
+    // launch traces fit in kMacroLdsMax (one word per cube in the all-local instantiation)
     int macro_lds[GDRR_MAX_VOLUMES];
     int macro_lds_n = 0;
     for (int v = 0; v < GDRR_MAX_VOLUMES; ++v) macro_lds[v] = -1;
+    const size_t rec_bytes = lds_record_bytes(local && !any_single && interp ? 3 : 2);
     if (local) {
         size_t n = 0;
         for (int v = 0; v < B.n_vols; ++v)
             if (B.vols[v].macro > 0 && batch_uses(B, v))
                 n += (size_t)cubes(B.vols[v].nx, B.vols[v].macro) * cubes(B.vols[v].ny, B.vols[v].macro) *
                      cubes(B.vols[v].nz, B.vols[v].macro);
-        if (n * sizeof(uint2) <= kMacroLdsMax)
+        if (n * rec_bytes <= kMacroLdsMax)
             for (int v = 0; v < B.n_vols; ++v)
                 if (B.vols[v].macro > 0 && batch_uses(B, v)) {
                     macro_lds[v] = macro_lds_n;
@@ -515,21 +525,46 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
                                    cubes(B.vols[v].nz, B.vols[v].macro);
                 }
     }
-    // the single-majorant tables are staged only if some traced volume tracks with them
-    bool any_single = false;
-    for (int v = 0; v < B.n_vols; ++v) any_single |= batch_uses(B, v) && B.vols[v].macro <= 0;
-    const int n_maj = any_single ? B.n_vols : 0;
-    // tables, cube records, then 64 source-draw slots of 16 bytes per wavefront
-    const size_t lds = draw_slots_offset_bytes(lds_bytes(phys->n_mat, phys->n_e, n_maj, phys->response != nullptr) +
-                                               (size_t)macro_lds_n * sizeof(uint2)) +
-                       (size_t)block * 16;
-    if (lds > dev.lds_max) return fail(GDRR_ENOTSUP, "tables exceed the LDS of a workgroup");
     const int local_kind = !local ? 0 : (macro_lds_n > 0 ? (any_single || !interp ? 2 : 3) : 1);
+    // Rows for the material sets of cubes (all-local launches, at most 8 materials): as many
+    // as keep the workgroups per compute unit that the launch has without them (or the tuned
+    // count), as the runtime's occupancy calculation has it.
+    const int n_mat = phys->n_mat;
+    const auto lds_for = [&](int rows) {
+        return draw_slots_offset_bytes(table_floats2(rows, phys->n_e, n_maj) * 8 +
+                                       (size_t)macro_lds_n * lds_record_bytes(local_kind)) +
+               (size_t)block * 16;
+    };
+    const void* mfunc = mc_func_for(B.mode, local_kind);
+    // (the LDS of a workgroup is allocated in granules of kLdsGranule bytes, which the
+    // runtime's occupancy calculation does not round to: the query gets the rounded size)
+    const auto per_cu_with = [&](size_t bytes, int& nb) -> int {
+        nb = 0;
+        const size_t held = (bytes + kLdsGranule - 1) / kLdsGranule * kLdsGranule;
+        GDRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, mfunc, block, held));
+        return GDRR_OK;
+    };
+    int mask_rows = 0;
+    if (local_kind == 3 && n_mat <= 8 && lds_for(n_mat) <= dev.lds_max) {
+        int target = tune.blocks_per_cu;
+        if (!target && (rc = per_cu_with(lds_for(n_mat), target))) return rc;
+        const int sets = std::min((1 << n_mat) - 1 - n_mat, (int)kNoRow - n_mat);   // sets of two or more
+        for (int r = sets; r > 0; --r) {                       // the most rows that keep the target
+            if (lds_for(n_mat + r) > dev.lds_max) continue;
+            int nb = 0;
+            if ((rc = per_cu_with(lds_for(n_mat + r), nb))) return rc;
+            if (nb >= target) {
+                mask_rows = r;
+                break;
+            }
+        }
+    }
+    const size_t lds = lds_for(n_mat + mask_rows);
+    if (lds > dev.lds_max) return fail(GDRR_ENOTSUP, "tables exceed the LDS of a workgroup");
     int per_cu = tune.blocks_per_cu;
     if (!per_cu) {
-        const void* f = mc_func_for(B.mode, local_kind);
         int nb = 0;
-        GDRR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, block, lds));
+        if ((rc = per_cu_with(lds, nb))) return rc;
         per_cu = std::max(nb, 1);
     }
     const unsigned grid = (unsigned)(dev.cus * per_cu);
@@ -710,6 +745,8 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     kp.n_vols = B.n_vols;
     kp.n_maj = n_maj;
     kp.n_mat = phys->n_mat;
+    kp.tot_rows = phys->n_mat + mask_rows;
+    kp.mask_rows = mask_rows;
     kp.n_e = phys->n_e;
     kp.e0 = phys->e0_kev;
     kp.inv_de = (float)(1.0 / phys->de_kev);

@@ -36,6 +36,8 @@ struct KParams {
     unsigned long long total_chunks;
     int n_jobs, n_vols, n_mat, n_e;
     int n_maj;                                // volumes whose single-majorant table is staged in LDS (0 or n_vols)
+    int tot_rows;                             // rows per energy of the LDS attenuation table (>= n_mat)
+    int mask_rows;                            // rows after the materials' kept for material sets of cubes
     float e0, inv_de, e_max, e_cut, x0;
     uint32_t k0, k1;
     uint32_t flags;
@@ -50,22 +52,39 @@ struct KParams {
     // adjoint (backward mode)
     const double* adj;
     double* grad;
-    // local majorants staged in LDS after the tables: per volume the offset (uint2 units) or -1
+    // local majorants staged in LDS after the tables: per volume the offset (records) or -1
     int macro_lds[kMaxVol];
     int macro_lds_n;          // records staged in total
 };
 
 // LDS holds what every free flight reads: the total attenuation per
-// (material, grid point) and the majorants; interaction-type splits are read
-// from the global table at the (rarer) real collisions.
-__host__ __device__ inline size_t lds_bytes(int n_mat, int n_e, int n_maj, bool resp) {
-    return (size_t)n_mat * n_e * 8 + (size_t)n_maj * (n_e - 1) * 8 + (resp ? (size_t)n_e * 8 : 0);
+// (grid point, row) and the majorants; interaction-type splits are read from
+// the global table at the (rarer) real collisions.  Rows 0 .. n_mat-1 are the
+// materials; with local majorants the rows after them hold, for the material
+// sets of several materials that cubes have, the chord between the largest
+// mu_tot of the set at the interval's two grid energies (the set's bound).
+__host__ __device__ inline size_t table_floats2(int tot_rows, int n_e, int n_maj) {
+    return (size_t)tot_rows * n_e + (size_t)n_maj * (n_e - 1);
 }
 
+// Bytes of cube records per cube in LDS: the all-local instantiation keeps one
+// word (the density bound, whose low 5 bits are zero, with a table row there),
+// the others the record as built.
+__host__ __device__ inline size_t lds_record_bytes(int local_kind) { return local_kind == 3 ? 4 : 8; }
+
+// Per wavefront, after the tables and cube records: 64 slots of source draws
+// (16 bytes each), starting at a 16-byte boundary.
+__host__ __device__ inline size_t draw_slots_offset_bytes(size_t tables_and_records_bytes) {
+    return (tables_and_records_bytes + 15) & ~(size_t)15;
+}
+
+// The row field of an all-local LDS record: 31 = no row (the bound then comes
+// from the cube's material mask in its global record).
+constexpr uint32_t kNoRow = 31u;
+
 struct Tables {
-    const float2* tot;    // [j][m] (tot_j, tot_j+1 - tot_j): the materials of one interval side by side
+    const float2* tot;    // [j][row] (tot_j, tot_j+1 - tot_j): the rows of one interval side by side
     const float2* maj;    // [v][j] (mbar, mean free path per unit of -ln u, mm)
-    const float2* resp;   // [j] (r_j, r_j+1 - r_j)
 };
 
 // Energy-interval cache of a photon: interval index, fraction, majorant, mfp.
@@ -125,10 +144,11 @@ __device__ __forceinline__ float cell_density(const DVolume& V, bool interp, flo
     return b0 + fz * (b1 - b0);
 }
 
+// (read from global memory: one lookup per scored photon; j <= n_e - 2)
 __device__ __forceinline__ float response_at(const KParams& P, const Tables& T, const ECache& ec, float E) {
     if (!P.response) return E;
-    const float2 r = T.resp[ec.j];
-    return r.x + ec.f * r.y;
+    const float r0 = P.response[ec.j], r1 = P.response[ec.j + 1];
+    return r0 + ec.f * (r1 - r0);
 }
 
 // Per-lane photon state.
@@ -343,7 +363,7 @@ __device__ __forceinline__ bool flight(const KParams& P, const Tables& T, const 
     int m;
     const float rho = cell_density(V, interp, ph.px, ph.py, ph.pz, m);
     m = m < P.n_mat ? m : P.n_mat - 1;
-    const float2 tt = T.tot[ph.ec.j * P.n_mat + m];
+    const float2 tt = T.tot[ph.ec.j * P.tot_rows + m];
     const float tot = tt.x + ph.ec.f * tt.y;
     // one uniform on [0, mbar): real below mu = rho tot, then the type ladder
     const float ladder = u24(rb) * ph.ec.mbar;
@@ -358,17 +378,35 @@ __device__ __forceinline__ bool flight(const KParams& P, const Tables& T, const 
     return true;
 }
 
+// Material factor of a cube's bound from its material mask, tot pointing at the
+// row of the photon's energy interval j: the chord between the largest mu_tot
+// of the cube's materials at E_j and at E_j+1 (the next interval's rows; j <=
+// n_e - 2), the same float operations as a row of the set's (stage_records_rows),
+// so that a cube's bound does not depend on where it is read from.
+__device__ __forceinline__ float set_bound(const float2* tot, int rows, uint32_t mask, float f) {
+    float t0 = 0.0f, t1 = 0.0f;
+    for (; mask; mask &= mask - 1u) {
+        const int m = __builtin_ctz(mask);
+        const float a = tot[m].x, b = tot[rows + m].x;
+        t0 = a > t0 ? a : t0;
+        t1 = b > t1 ? b : t1;
+    }
+    return t0 + f * (t1 - t0);
+}
+
 // One free flight under local majorants (uniforms ra, rb): an optical depth
 // tau = -ln(u) is spent cube by cube along the line, each cube at its own
 // bound mbar_B = (1 + margin) rho_max(B) max_{m in B} mu_tot(m, E); where tau
 // runs out the collision ladder runs against that cube's bound; leaving the
-// last cube is an escape.  Returns true after a null collision.  REC_LDS:
-// the cube records are read from their LDS copy lds_rec (a separate
-// instantiation, so that the load is an LDS read, not a generic one).
-template <int MODE, bool REC_LDS>
+// last cube is an escape.  Returns true after a null collision.  REC: where
+// the cube records are read: 0 = global memory; 1 = their LDS copy lds_rec
+// (a separate instantiation, so that the load is an LDS read, not a generic
+// one); 2 = the all-local LDS words (density bound and table row; a cube
+// without a row takes its material mask from the global record).
+template <int MODE, int REC>
 __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, const DVolume& V, int vo,
                                              bool interp, Photon& ph, uint32_t ra, uint32_t rb,
-                                             const uint2* lds_rec) {
+                                             const void* lds_rec) {
     if (ph.step >= kMaxSteps) {
         if (MODE == kModeTrace) trace_out<MODE>(P, ph, kLost, -1);
         ph.st = kDead;
@@ -399,7 +437,7 @@ __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, 
     float tmz = sz > 0 ? (V.loz + (float)(bz + 1) * V.mez - ph.pz) * rz
               : (sz < 0 ? (V.loz + (float)bz * V.mez - ph.pz) * rz : INFINITY);
     const float dtx = V.mex * fabsf(rx), dty = V.mey * fabsf(ry), dtz = V.mez * fabsf(rz);
-    const float2* tot = T.tot + ph.ec.j * P.n_mat;
+    const float2* tot = T.tot + ph.ec.j * P.tot_rows;
     // the cube index moves by one of these per crossing
     const int cix = sx, ciy = sy * V.mnx, ciz = sz * V.mnx * V.mny;
     int ci = (bz * V.mny + by) * V.mnx + bx;
@@ -408,14 +446,24 @@ __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, 
     // (selects instead of fminf/fmaxf below: no NaN can occur, and these need
     // no canonicalisation of their operands)
     for (;;) {
-        const uint2 rec = REC_LDS ? lds_rec[ci] : V.macro[ci];
-        float tmax = 0.0f;
-        for (uint32_t mask = rec.y; mask; mask &= mask - 1u) {
-            const float2 tt = tot[__builtin_ctz(mask)];
-            const float tm = tt.x + ph.ec.f * tt.y;
-            tmax = tm > tmax ? tm : tmax;
+        float tmax;
+        uint32_t rho_bits;
+        if constexpr (REC == 2) {
+            const uint32_t w = reinterpret_cast<const uint32_t*>(lds_rec)[ci];
+            const uint32_t row = w & 31u;
+            rho_bits = w & ~31u;
+            if (row != kNoRow) {
+                const float2 tt = tot[row];
+                tmax = tt.x + ph.ec.f * tt.y;
+            } else {
+                tmax = set_bound(tot, P.tot_rows, V.macro[ci].y, ph.ec.f);
+            }
+        } else {
+            const uint2 rec = REC == 1 ? reinterpret_cast<const uint2*>(lds_rec)[ci] : V.macro[ci];
+            rho_bits = rec.x;
+            tmax = set_bound(tot, P.tot_rows, rec.y, ph.ec.f);
         }
-        mb = __uint_as_float(rec.x) * tmax;
+        mb = __uint_as_float(rho_bits) * tmax;
         const float tnext = fminf(tmx, fminf(tmy, tmz));
         const float tn = tnext < tex ? tnext : tex;                    // the cube's exit, within the box
         const float span = tn - t;
@@ -451,7 +499,7 @@ __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, 
     int m;
     const float rho = cell_density(V, interp, ph.px, ph.py, ph.pz, m);
     m = m < P.n_mat ? m : P.n_mat - 1;
-    const float2 tt = T.tot[ph.ec.j * P.n_mat + m];
+    const float2 tt = T.tot[ph.ec.j * P.tot_rows + m];
     const float tot_m = tt.x + ph.ec.f * tt.y;
     const float ladder = u24(rb) * mb;
     const bool real = ladder < rho * tot_m;
@@ -500,37 +548,91 @@ __device__ __forceinline__ void collide(const KParams& P, const Tables& T, const
 }
 
 // Copies the per-launch tables into LDS (all threads of the workgroup).
+// mu_tot of material m at grid point j (float32, summed as everywhere)
+__device__ __forceinline__ float tot_at(const KParams& P, int m, int j) {
+    const float* a = P.mu_mass + ((size_t)m * P.n_e + j) * 3;
+    return a[0] + a[1] + a[2];
+}
+
 __device__ __forceinline__ Tables stage_tables(const KParams& P, float2* lds) {
     float2* s_tot = lds;
-    float2* s_maj = s_tot + P.n_mat * P.n_e;
-    float2* s_resp = s_maj + P.n_maj * (P.n_e - 1);
+    float2* s_maj = s_tot + P.tot_rows * P.n_e;
     for (int i = threadIdx.x; i < P.n_mat * P.n_e; i += blockDim.x) {
         const int j = i / P.n_mat, m = i - j * P.n_mat;
-        const float* a = P.mu_mass + ((size_t)m * P.n_e + j) * 3;
-        const float* b = j + 1 < P.n_e ? a + 3 : a;
-        const float t0 = a[0] + a[1] + a[2], t1 = b[0] + b[1] + b[2];
-        s_tot[i] = make_float2(t0, t1 - t0);
+        const float t0 = tot_at(P, m, j), t1 = tot_at(P, m, j + 1 < P.n_e ? j + 1 : j);
+        s_tot[j * P.tot_rows + m] = make_float2(t0, t1 - t0);
     }
     for (int i = threadIdx.x; i < P.n_maj * (P.n_e - 1); i += blockDim.x) {
         const float mb = P.majorants[i];
         s_maj[i] = make_float2(mb, mb > 0.0f ? 1.0f / (0.1f * mb) : INFINITY);
     }
-    if (P.response)
-        for (int i = threadIdx.x; i < P.n_e; i += blockDim.x) {
-            const float r0 = P.response[i], r1 = P.response[i + 1 < P.n_e ? i + 1 : i];
-            s_resp[i] = make_float2(r0, r1 - r0);
+    return Tables{s_tot, s_maj};
+}
+
+// Rank of bit b among the set bits of the 256-bit set bm.
+__device__ __forceinline__ int set_rank(const uint32_t* bm, uint32_t b) {
+    int r = __popc(bm[b >> 5] & ((1u << (b & 31u)) - 1u));
+    for (uint32_t w = 0; w < (b >> 5); ++w) r += __popc(bm[w]);
+    return r;
+}
+
+// All-local launches: one LDS word per cube, its density bound with the row of
+// the LDS table that holds its material factor: the material's own for a cube
+// of one material; for several, a row of their set, if the set is among the
+// first mask_rows distinct sets (by mask value) of the staged volumes (n_mat
+// <= 8, masks < 256); kNoRow otherwise.  bm: 8 + 32 words of LDS scratch.
+__device__ __forceinline__ void stage_records_rows(const KParams& P, float2* s_tot, uint32_t* rec_lds,
+                                                   uint32_t* bm) {
+    if (P.mask_rows > 0) {
+        if (threadIdx.x < 8) bm[threadIdx.x] = 0u;
+        __syncthreads();
+        for (int v = 0; v < P.n_vols; ++v) {
+            if (P.macro_lds[v] < 0 || !P.vol[v].macro) continue;
+            const int n = P.vol[v].mnx * P.vol[v].mny * P.vol[v].mnz;
+            for (int i = threadIdx.x; i < n; i += blockDim.x) {
+                const uint32_t mask = P.vol[v].macro[i].y;
+                if (mask & (mask - 1u)) atomicOr(&bm[(mask >> 5) & 7u], 1u << (mask & 31u));
+            }
         }
-    return Tables{s_tot, s_maj, s_resp};
-}
-
-__host__ __device__ inline size_t table_floats2(int n_mat, int n_e, int n_maj, bool resp) {
-    return (size_t)n_mat * n_e + (size_t)n_maj * (n_e - 1) + (resp ? (size_t)n_e : 0);
-}
-
-// Per wavefront, after the tables and cube records: 64 slots of source draws
-// (16 bytes each), starting at a 16-byte boundary.
-__host__ __device__ inline size_t draw_slots_offset_bytes(size_t tables_and_records_bytes) {
-    return (tables_and_records_bytes + 15) & ~(size_t)15;
+        __syncthreads();
+        for (int t = threadIdx.x; t < 256; t += blockDim.x)
+            if ((bm[t >> 5] >> (t & 31)) & 1u) {
+                const int r = set_rank(bm, (uint32_t)t);
+                if (r < P.mask_rows) bm[8 + r] = (uint32_t)t;
+            }
+        __syncthreads();
+        int n_sets = 0;
+        for (int w = 0; w < 8; ++w) n_sets += __popc(bm[w]);
+        for (int i = threadIdx.x; i < P.mask_rows * P.n_e; i += blockDim.x) {
+            const int j = i / P.mask_rows, k = i - j * P.mask_rows;
+            const int j1 = j + 1 < P.n_e ? j + 1 : j;
+            float t0 = 0.0f, t1 = 0.0f;
+            if (k < n_sets)
+                for (uint32_t mask = bm[8 + k]; mask; mask &= mask - 1u) {
+                    const int m = __builtin_ctz(mask);
+                    const float a = tot_at(P, m, j), b = tot_at(P, m, j1);
+                    t0 = a > t0 ? a : t0;
+                    t1 = b > t1 ? b : t1;
+                }
+            s_tot[j * P.tot_rows + P.n_mat + k] = make_float2(t0, t1 - t0);
+        }
+    }
+    for (int v = 0; v < P.n_vols; ++v) {
+        if (P.macro_lds[v] < 0 || !P.vol[v].macro) continue;
+        const int n = P.vol[v].mnx * P.vol[v].mny * P.vol[v].mnz;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            const uint2 rec = P.vol[v].macro[i];
+            uint32_t row = kNoRow;
+            if (!(rec.y & (rec.y - 1u))) {
+                const uint32_t m = rec.y ? (uint32_t)__builtin_ctz(rec.y) : kNoRow;
+                row = m < kNoRow ? m : kNoRow;
+            } else if (P.mask_rows > 0) {
+                const int r = set_rank(bm, rec.y & 255u);
+                row = r < P.mask_rows ? (uint32_t)(P.n_mat + r) : kNoRow;
+            }
+            rec_lds[P.macro_lds[v] + i] = (rec.x & ~31u) | row;
+        }
+    }
 }
 
 // LOCAL: 0 = every volume has one majorant per energy interval; 1 = some
@@ -545,17 +647,24 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
     extern __shared__ float2 lds[];
     const Tables T = stage_tables(P, lds);
     // local majorants small enough to stage: every volume's cube records after the tables
-    uint2* lds_macro = reinterpret_cast<uint2*>(lds + table_floats2(P.n_mat, P.n_e, P.n_maj, P.response != nullptr));
-    // this wavefront's source-draw slots: offset (bytes) of the first from the LDS base (wavefront-uniform)
-    const uint32_t draws_off = __builtin_amdgcn_readfirstlane(
-        (int)(draw_slots_offset_bytes(table_floats2(P.n_mat, P.n_e, P.n_maj, P.response != nullptr) * 8 +
-                                      (size_t)P.macro_lds_n * 8) + (threadIdx.x & ~63u) * 16u));
-    if (LOCAL >= 2)
+    float2* const lds_rec = lds + table_floats2(P.tot_rows, P.n_e, P.n_maj);
+    // the source-draw slots (offset in bytes from the LDS base of the first wavefront's)
+    const uint32_t slots_off = (uint32_t)draw_slots_offset_bytes(
+        table_floats2(P.tot_rows, P.n_e, P.n_maj) * 8 + (size_t)P.macro_lds_n * lds_record_bytes(LOCAL));
+    // this wavefront's slots (wavefront-uniform)
+    const uint32_t draws_off = __builtin_amdgcn_readfirstlane((int)(slots_off + (threadIdx.x & ~63u) * 16u));
+    if (LOCAL == 3) {
+        // (the slots serve as scratch until the transport starts)
+        stage_records_rows(P, lds, reinterpret_cast<uint32_t*>(lds_rec),
+                           reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(lds) + slots_off));
+    } else if (LOCAL == 2) {
+        uint2* r = reinterpret_cast<uint2*>(lds_rec);
         for (int v = 0; v < P.n_vols; ++v) {
             if (P.macro_lds[v] < 0 || !P.vol[v].macro) continue;
             const int n = P.vol[v].mnx * P.vol[v].mny * P.vol[v].mnz;
-            for (int i = threadIdx.x; i < n; i += blockDim.x) lds_macro[P.macro_lds[v] + i] = P.vol[v].macro[i];
+            for (int i = threadIdx.x; i < n; i += blockDim.x) r[P.macro_lds[v] + i] = P.vol[v].macro[i];
         }
+    }
     __syncthreads();
     const bool interp = LOCAL == 3 || (P.flags & 1u) != 0;
     const int lane = __lane_id();
@@ -654,14 +763,18 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
         if (ph.st == kFly) {
             ph.pair += 1u;
             const Block b = philox(ph.pid, ph.jid, ph.pair, 0u, P.k0, P.k1);
-            if (LOCAL == 3 || (LOCAL == 2 && V.macro)) {
-                const uint2* lr = lds_macro + P.macro_lds[w_vol];
-                if (flight_local<MODE, true>(P, T, V, vo, interp, ph, b.x, b.y, lr))
-                    flight_local<MODE, true>(P, T, V, vo, interp, ph, b.z, b.w, lr);
-            } else if constexpr (LOCAL != 3) {
+            if constexpr (LOCAL == 3) {
+                const uint32_t* lr = reinterpret_cast<const uint32_t*>(lds_rec) + P.macro_lds[w_vol];
+                if (flight_local<MODE, 2>(P, T, V, vo, interp, ph, b.x, b.y, lr))
+                    flight_local<MODE, 2>(P, T, V, vo, interp, ph, b.z, b.w, lr);
+            } else if (LOCAL == 2 && V.macro) {
+                const uint2* lr = reinterpret_cast<const uint2*>(lds_rec) + P.macro_lds[w_vol];
+                if (flight_local<MODE, 1>(P, T, V, vo, interp, ph, b.x, b.y, lr))
+                    flight_local<MODE, 1>(P, T, V, vo, interp, ph, b.z, b.w, lr);
+            } else {
                 if (LOCAL == 1 && V.macro) {
-                    if (flight_local<MODE, false>(P, T, V, vo, interp, ph, b.x, b.y, nullptr))
-                        flight_local<MODE, false>(P, T, V, vo, interp, ph, b.z, b.w, nullptr);
+                    if (flight_local<MODE, 0>(P, T, V, vo, interp, ph, b.x, b.y, nullptr))
+                        flight_local<MODE, 0>(P, T, V, vo, interp, ph, b.z, b.w, nullptr);
                 } else if (flight<MODE>(P, T, V, vo, interp, ph, b.x, b.y)) {
                     flight<MODE>(P, T, V, vo, interp, ph, b.z, b.w);
                 }
@@ -806,7 +919,9 @@ __global__ __launch_bounds__(256) void macro_kernel(MacroParams M) {
                     mask |= 1u << min((int)M.material[row + x], M.n_mat - 1);
                 }
             }
-        M.out[c] = make_uint2(__float_as_uint(__double2float_ru((double)r * M.scale)), mask);
+        // the density factor rounded up to 19 significant bits: the low 5 bits stay free
+        const uint32_t rb = __float_as_uint(__double2float_ru((double)r * M.scale));
+        M.out[c] = make_uint2((rb + 31u) & ~31u, mask);
     }
 }
 
