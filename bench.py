@@ -71,11 +71,11 @@ SLOTS_BOX_EXIT = slots(i=6, f=28, t=3)                # single majorant only: di
 SLOTS_SOURCE = 2 * SLOTS_PHILOX + slots(i=50, f=55, t=4)   # two blocks, CDFs (fp64), aim point, box entry
 # local majorants: every flight first sets up its walk (cube coordinates, three
 # reciprocals, steps, exit-face distances), then visits cubes (its first, and
-# one per face crossed): record address and load, bound from the material mask
-# (~1.5 materials), spend or stop, advance, step the cube index
+# one per face crossed): record word address and load, the bound from the row of
+# the material-set table it names, spend or stop, advance, step the cube index
 SLOTS_WALK = slots(i=30, f=42, t=3)
-SLOTS_CUBE = slots(i=25, f=25)
-BYTES_CUBE = 8
+SLOTS_CUBE = slots(i=20, f=23)
+BYTES_CUBE = 4
 BYTES_FLIGHT_IN = 8 * 4 + 1                            # eight density corners + the containing voxel's material
 BYTES_SOURCE = 2 * (2 * 8 + 4) + 4                     # CDF + guide reads for energy and pixel, energy
 BYTES_SCORE = 8                                        # one fixed-point atomic
