@@ -60,7 +60,7 @@ def slots(i=0, f=0, t=0):
     return i * SLOTS_INT + f * SLOTS_F32 + t * SLOTS_TRANS
 
 
-SLOTS_PHILOX = slots(i=10 * (2 + 4))                  # per round: two 32x32->64 products, four xors
+SLOTS_PHILOX = slots(i=10 * (2 + 2))                  # per round: two 32x32->64 products, two 3-way xors
 # free flights come in pairs sharing one Philox block (counted per history below)
 SLOTS_FLIGHT_IN = slots(i=10, f=31, t=1)              # uniforms, -ln u, move, cell-record trilinear, lookup+ladder
 SLOTS_FLIGHT_OUT = slots(i=7, f=27, t=2)              # the escaping flight: -ln u, detector intersection

@@ -96,6 +96,21 @@ __global__ __launch_bounds__(kBlock) void k_xadv(uint32_t* out, float s) {
     out[blockIdx.x * kBlock + threadIdx.x] = r;
 }
 
+// three-input xor (gfx950 v_bitop3_b32, truth table 0x96) then an add, vector operands
+__global__ __launch_bounds__(kBlock) void k_bitop3v(uint32_t* out, float s) {
+    uint32_t a[kChains];
+    const uint32_t kv = out[blockIdx.x * kBlock + threadIdx.x] | 1u;
+    const uint32_t kw = kv * 3u;
+    _Pragma("unroll") for (int c = 0; c < kChains; ++c) a[c] = threadIdx.x * kChains + c + __float_as_uint(s);
+    for (int i = 0; i < kIters; ++i) {
+        _Pragma("unroll") for (int c = 0; c < kChains; ++c)
+            a[c] = __builtin_amdgcn_bitop3_b32(a[c], kv, (uint32_t)i, 0x96) + kw;
+    }
+    uint32_t r = 0;
+    _Pragma("unroll") for (int c = 0; c < kChains; ++c) r ^= a[c];
+    out[blockIdx.x * kBlock + threadIdx.x] = r;
+}
+
 __global__ __launch_bounds__(kBlock) void k_mad64v(uint32_t* out, float s) {
     uint32_t a[kChains];
     const uint32_t kv = out[blockIdx.x * kBlock + threadIdx.x] | 1u;
@@ -141,6 +156,7 @@ int main() {
         {"mul_lo_u32", k_mullo, "v_mul_lo_u32 + v_xor_b32"},
         {"cvt_f32_u32", k_cvt, "v_cvt_f32_u32 + v_mul_f32 + v_cvt_u32_f32"},
         {"xad_u32_v", k_xadv, "v_xad_u32 (vector operands)"},
+        {"bitop3_add_v", k_bitop3v, "v_bitop3_b32 (a ^ b ^ c) + v_add_u32 (vector operands)"},
         {"mul_hi_u32", k_mulhi, "v_mul_hi_u32 + v_xor_b32"},
         {"mad_u64_u32", k_mad64, "v_mad_u64_u32 (32x32->64 product) + v_xor_b32"},
         {"mad_u64_u32_v", k_mad64v, "v_mad_u64_u32 (vector multiplier) + v_xor_b32"},

@@ -97,10 +97,10 @@ def test_work_model_prices_measured_issue_costs():
     gfx950, in slots of a full-rate integer operation: integer operations and
     32x32-bit products 1, float32 arithmetic with vector operands 0.6,
     transcendentals 2.3.  A Philox4x32-10 block is ten rounds of two products
-    and four xors."""
+    and two three-input xors (v_bitop3_b32)."""
     assert (bench.SLOTS_INT, bench.SLOTS_F32, bench.SLOTS_TRANS) == (1.0, 0.6, 2.3)
     assert bench.slots(i=3, f=5, t=2) == pytest.approx(3 + 3.0 + 4.6)
-    assert bench.SLOTS_PHILOX == 60
+    assert bench.SLOTS_PHILOX == 40
     assert bench.SLOTS_DN_SWEEP == pytest.approx(9 * 0.6 + 2.3)
     assert bench.SLOTS_RT_INTERVAL == pytest.approx(13 + 33 * 0.6)
 
