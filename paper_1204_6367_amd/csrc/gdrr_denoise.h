@@ -114,45 +114,60 @@ __global__ __launch_bounds__(kDnBlock) void denoise_inside_kernel(DnParams D) {
 // column comes from the neighbouring lane by a DPP whole-wavefront shift (at
 // the image's left/right edge a lane keeps its own pixel); across wavefronts
 // the first/last row goes through LDS (at the top/bottom edge the pixel
-// itself).  One workgroup per image.
+// itself).  One workgroup per image.  The data Shat of the block's first R/2
+// rows waits in LDS (96 KiB a workgroup), the rest in registers: with all of
+// it in registers the 128 a lane has at 16 wavefronts per compute unit spilled.
+// With the edge rows' two buffers a workgroup takes up to the whole 160 KiB.
 template <int C, int R>
 __global__ __launch_bounds__(1024) void denoise_image_kernel(DnParams D) {
-    __shared__ float edge[2][16][64 * C];                 // first and last row of each wavefront's band
+    constexpr int RL = R / 2;                              // rows of Shat kept in LDS
+    // first and last row of each wavefront's band, in two buffers used by turns: the writes
+    // of sweep i + 2 come after the barrier of sweep i + 1, which every read of sweep i
+    // precedes, so one barrier a sweep suffices
+    __shared__ float edge[2][2][16][64 * C];
+    __shared__ float4 h_lds[RL][16][64 * C / 4];          // [row][wavefront][lane's C values]
+    static_assert(C == 4 || C == 2 || C == 1, "block width");
     const int img = blockIdx.x;
     const int waves = blockDim.x >> 6;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const size_t npix = (size_t)D.nv * D.nu;
     const int r0 = wave * R, c0 = lane * C;
     const double* H = D.shat + (size_t)img * D.shat_stride + (size_t)r0 * D.nu + c0;
-    float s[R][C], h[R][C];
+    float s[R][C], h[R - RL][C];
+    float* const hl = reinterpret_cast<float*>(&h_lds[0][wave][0]) + c0;   // row k at hl[k * 16 * 64 C]
 #pragma unroll
     for (int k = 0; k < R; ++k)
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            h[k][c] = (float)H[(size_t)k * D.nu + c];
-            s[k][c] = fmaxf(h[k][c], D.s_floor);
+            const float hv = (float)H[(size_t)k * D.nu + c];
+            if (k < RL) hl[(size_t)k * 16 * 64 * C + c] = hv;
+            else h[k - RL][c] = hv;
+            s[k][c] = fmaxf(hv, D.s_floor);
         }
     const float w1 = 1.0f - D.omega, qw = 0.25f * D.omega;
     for (int it = 0; it < D.iters; ++it) {
+        const int e = it & 1;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            edge[0][wave][c0 + c] = s[0][c];
-            edge[1][wave][c0 + c] = s[R - 1][c];
+            edge[e][0][wave][c0 + c] = s[0][c];
+            edge[e][1][wave][c0 + c] = s[R - 1][c];
         }
         __syncthreads();
         float above[C], below[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) {
-            above[c] = wave > 0 ? edge[1][wave - 1][c0 + c] : s[0][c];
-            below[c] = wave < waves - 1 ? edge[0][wave + 1][c0 + c] : s[R - 1][c];
+            above[c] = wave > 0 ? edge[e][1][wave - 1][c0 + c] : s[0][c];
+            below[c] = wave < waves - 1 ? edge[e][0][wave + 1][c0 + c] : s[R - 1][c];
         }
-        __syncthreads();
 #pragma unroll
         for (int k = 0; k < R; ++k) {
             // the row's old values and its neighbours outside this lane's block
-            float row[C];
+            float row[C], hrow[C];
 #pragma unroll
-            for (int c = 0; c < C; ++c) row[c] = s[k][c];
+            for (int c = 0; c < C; ++c) {
+                row[c] = s[k][c];
+                hrow[c] = k < RL ? hl[(size_t)k * 16 * 64 * C + c] : h[k < RL ? 0 : k - RL][c];
+            }
             const float left = __int_as_float(__builtin_amdgcn_update_dpp(
                 __float_as_int(row[0]), __float_as_int(row[C - 1]), 0x138, 0xf, 0xf, false));   // wave_shr:1
             const float right = __int_as_float(__builtin_amdgcn_update_dpp(
@@ -164,7 +179,7 @@ __global__ __launch_bounds__(1024) void denoise_image_kernel(DnParams D) {
                 const float dn = k + 1 < R ? s[k + 1][c] : below[c];
                 const float lf = c > 0 ? row[c - 1] : left;
                 const float rt = c + 1 < C ? row[c + 1] : right;
-                const float hk = h[k][c];
+                const float hk = hrow[c];
                 const float data = hk == 0.0f ? 1.0f : 1.0f - hk * __builtin_amdgcn_rcpf(sk);
                 const float v = w1 * sk + qw * ((up + dn + lf + rt) - data * D.inv_beta);
                 s[k][c] = fmaxf(v, D.s_floor);
