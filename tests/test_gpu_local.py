@@ -174,3 +174,24 @@ def test_bad_collision_deferral_rejected(gpu):
     for bad in (-1, 65):
         with pytest.raises(gpu._abi.GdrrError):
             b.project(seed=1, tune=dict(coll_defer=bad))
+
+
+def test_all_local_launch_shapes_give_the_same_bits(gpu):
+    """In the all-local instantiation the LDS holds as many rows of material
+    sets as the launch shape leaves room for (none to all; cubes of the other
+    sets take their bound from the mask in their global record): tallies are
+    bitwise the same for every shape."""
+    import torch
+    a = body_problem(1)
+    ph2 = W.ellipsoid_phantom((30, 36, 40), (4.0, 3.5, 3.0), 9, n_inner=10)
+    va, pa, sa = gpu.upload(a)
+    vb = gpu.DeviceVolume(ph2.density, ph2.material, ph2.spacing_mm)
+    va.local_majorants(5)
+    vb.local_majorants(4)
+    jobs = [gpu.JobSpec(a.geom.replace(phi_rad=0.4 * k), 60_000 + 531 * k, k, volume=k % 2) for k in range(6)]
+    bt = gpu.Batch([va, vb], pa, [sa], jobs)
+    ref = bt.project(seed=12)
+    for t in (dict(block=64, defer=2, chunk=64), dict(block=256), dict(block=512, coll_defer=20),
+              dict(block=1024, blocks_per_cu=1), dict(block=512, blocks_per_cu=3, chunk=128)):
+        log("launch shape", t)
+        assert torch.equal(bt.project(seed=12, tune=t), ref), t
