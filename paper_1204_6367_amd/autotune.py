@@ -25,9 +25,9 @@ DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "autotu
 # time from the best so far: chunk size, workgroups per CU.
 CANDIDATES: List[Dict[str, int]] = [
     dict(block=b, defer=d, coll_defer=c, chunk=0, blocks_per_cu=0)
-    for b in (256, 512) for d in (8, 16, 24, 32) for c in (0, 12, 20, 28)
+    for b in (256, 512, 1024) for d in (8, 16, 24, 32) for c in (0, 12, 20, 28)
 ]
-REFINE: List[Dict[str, int]] = [dict(chunk=c) for c in (128, 512, 2048)] + [dict(blocks_per_cu=n) for n in (1, 2)]
+REFINE: List[Dict[str, int]] = [dict(chunk=c) for c in (128, 512, 2048)] + [dict(blocks_per_cu=n) for n in (1, 2, 3, 4)]
 
 
 def kernel_sha() -> str:

@@ -701,7 +701,11 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
             if (w_next >= w_end) {
                 unsigned long long c = 0;
                 if (lane == 0) c = atomicAdd(P.counter, 1ull);
-                c = __shfl(c, 0);
+                // lane 0's value in scalar registers (every lane is active here): the branches on
+                // it, and so the wavefront's volume and job, stay wavefront-uniform to the compiler,
+                // which then reads the volume's fields with scalar loads
+                c = ((unsigned long long)(uint32_t)__builtin_amdgcn_readfirstlane((int)(c >> 32)) << 32) |
+                    (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)c);
                 if (c >= P.total_chunks) {
                     w_done = 1;
                 } else {
@@ -790,16 +794,16 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
     }
 }
 
-// The forward and trace transport: at most 80 VGPRs (6 wavefronts per SIMD).
+// The forward and trace transport: at most 80 VGPRs (6 wavefronts per SIMD;
+// the all-local instantiation takes 59, which allows 8).
 template <int MODE, int LOCAL>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void mc_kernel(KParams P) {
     mc_body<MODE, LOCAL>(P);
 }
 
 // The adjoint: at most 96 VGPRs (5 wavefronts per SIMD), where it would
-// otherwise take 97 and drop to 4; the all-local instantiation (85 VGPRs
-// unconstrained) at 80 and 6 wavefronts, measured faster despite 12 bytes of
-// spills.
+// otherwise take 97 and drop to 4; the all-local instantiation at most 80
+// (it takes 65).
 template <int LOCAL>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LOCAL == 3 ? 6 : 5))) void mc_adjoint_kernel(
     KParams P) {
