@@ -510,7 +510,14 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
     int macro_lds[GDRR_MAX_VOLUMES];
     int macro_lds_n = 0;
     for (int v = 0; v < GDRR_MAX_VOLUMES; ++v) macro_lds[v] = -1;
-    const size_t rec_bytes = lds_record_bytes(local && !any_single && interp ? 3 : 2);
+    // the all-local instantiation counts a flight's crossings in 9 bits per axis
+    bool small_grids = true;
+    for (int v = 0; v < B.n_vols; ++v)
+        if (B.vols[v].macro > 0 && batch_uses(B, v))
+            small_grids &= cubes(B.vols[v].nx, B.vols[v].macro) <= 512 && cubes(B.vols[v].ny, B.vols[v].macro) <= 512 &&
+                           cubes(B.vols[v].nz, B.vols[v].macro) <= 512;
+    const bool all_local = local && !any_single && interp && small_grids;
+    const size_t rec_bytes = lds_record_bytes(all_local ? 3 : 2);
     if (local) {
         size_t n = 0;
         for (int v = 0; v < B.n_vols; ++v)
@@ -525,7 +532,7 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
                                    cubes(B.vols[v].nz, B.vols[v].macro);
                 }
     }
-    const int local_kind = !local ? 0 : (macro_lds_n > 0 ? (any_single || !interp ? 2 : 3) : 1);
+    const int local_kind = !local ? 0 : (macro_lds_n > 0 ? (all_local ? 3 : 2) : 1);
     // Rows for the material sets of cubes (all-local launches, at most 8 materials): as many
     // as keep the workgroups per compute unit that the launch has without them (or the tuned
     // count), as the runtime's occupancy calculation has it.

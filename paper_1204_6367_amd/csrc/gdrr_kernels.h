@@ -441,6 +441,16 @@ __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, 
     // the cube index moves by one of these per crossing
     const int cix = sx, ciy = sy * V.mnx, ciz = sz * V.mnx * V.mny;
     int ci = (bz * V.mny + by) * V.mnx + bx;
+    // REC 2 (at most 512 cubes per axis): the crossings left along each axis's direction
+    // of travel before the line leaves the grid, in 10-bit fields whose top bit is a
+    // guard that the crossing past the last cube clears
+    uint32_t left = 0u;
+    if constexpr (REC == 2) {
+        const uint32_t kx = sx > 0 ? (uint32_t)(V.mnx - 1 - bx) : (sx < 0 ? (uint32_t)bx : 511u);
+        const uint32_t ky = sy > 0 ? (uint32_t)(V.mny - 1 - by) : (sy < 0 ? (uint32_t)by : 511u);
+        const uint32_t kz = sz > 0 ? (uint32_t)(V.mnz - 1 - bz) : (sz < 0 ? (uint32_t)bz : 511u);
+        left = (512u + kx) | ((512u + ky) << 10) | ((512u + kz) << 20);
+    }
     float mb = 0.0f, t = 0.0f;
     bool hit = false;
     // (selects instead of fminf/fmaxf below: no NaN can occur, and these need
@@ -477,15 +487,21 @@ __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, 
         t = tn > t ? tn : t;
         if (!(tn < tex)) break;                                        // left the box
         const bool ax = tmx <= tmy && tmx <= tmz, ay = !ax && tmy <= tmz, az = !ax && !ay;
-        bx += ax ? sx : 0;
-        by += ay ? sy : 0;
-        bz += az ? sz : 0;
         ci += ax ? cix : (ay ? ciy : ciz);
         tmx = ax ? tmx + dtx : tmx;
         tmy = ay ? tmy + dty : tmy;
         tmz = az ? tmz + dtz : tmz;
-        if ((unsigned)bx >= (unsigned)V.mnx || (unsigned)by >= (unsigned)V.mny || (unsigned)bz >= (unsigned)V.mnz)
-            break;
+        if constexpr (REC == 2) {
+            constexpr uint32_t kGuards = (1u << 9) | (1u << 19) | (1u << 29);
+            left -= ax ? 1u : (ay ? 1u << 10 : 1u << 20);
+            if ((left & kGuards) != kGuards) break;                   // left the grid
+        } else {
+            bx += ax ? sx : 0;
+            by += ay ? sy : 0;
+            bz += az ? sz : 0;
+            if ((unsigned)bx >= (unsigned)V.mnx || (unsigned)by >= (unsigned)V.mny || (unsigned)bz >= (unsigned)V.mnz)
+                break;
+        }
     }
     ph.px += t * ph.dx;
     ph.py += t * ph.dy;
@@ -638,9 +654,9 @@ __device__ __forceinline__ void stage_records_rows(const KParams& P, float2* s_t
 // LOCAL: 0 = every volume has one majorant per energy interval; 1 = some
 // volume tracks with local majorants, cube records read from global memory;
 // 2 = the same with every such volume's records staged in LDS; 3 = every
-// traced volume tracks with local majorants, records in LDS, and density is
-// interpolated (no single-majorant flight and no nearest-voxel lookup in the
-// code at all).  Separate instantiations, so that each loop keeps its
+// traced volume tracks with local majorants, records in LDS, at most 512 cubes
+// per axis, and density is interpolated (no single-majorant flight and no
+// nearest-voxel lookup in the code at all).  Separate instantiations, so that each loop keeps its
 // register budget.
 template <int MODE, int LOCAL>
 __device__ __forceinline__ void mc_body(const KParams& P) {
