@@ -441,16 +441,12 @@ __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, 
     // the cube index moves by one of these per crossing
     const int cix = sx, ciy = sy * V.mnx, ciz = sz * V.mnx * V.mny;
     int ci = (bz * V.mny + by) * V.mnx + bx;
-    // REC 2 (at most 512 cubes per axis): the crossings left along each axis's direction
-    // of travel before the line leaves the grid, in 10-bit fields whose top bit is a
-    // guard that the crossing past the last cube clears
+    // REC 2 (at most 512 cubes per axis): crossings left per axis, as in flight_pair_all_local
     uint32_t left = 0u;
-    if constexpr (REC == 2) {
-        const uint32_t kx = sx > 0 ? (uint32_t)(V.mnx - 1 - bx) : (sx < 0 ? (uint32_t)bx : 511u);
-        const uint32_t ky = sy > 0 ? (uint32_t)(V.mny - 1 - by) : (sy < 0 ? (uint32_t)by : 511u);
-        const uint32_t kz = sz > 0 ? (uint32_t)(V.mnz - 1 - bz) : (sz < 0 ? (uint32_t)bz : 511u);
-        left = (512u + kx) | ((512u + ky) << 10) | ((512u + kz) << 20);
-    }
+    if constexpr (REC == 2)
+        left = ((512u + (uint32_t)(sx > 0 ? V.mnx - 1 - bx : (sx < 0 ? bx : 511)))) |
+               ((512u + (uint32_t)(sy > 0 ? V.mny - 1 - by : (sy < 0 ? by : 511))) << 10) |
+               ((512u + (uint32_t)(sz > 0 ? V.mnz - 1 - bz : (sz < 0 ? bz : 511))) << 20);
     float mb = 0.0f, t = 0.0f;
     bool hit = false;
     // (selects instead of fminf/fmaxf below: no NaN can occur, and these need
@@ -527,6 +523,123 @@ __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, 
         return false;
     }
     return true;
+}
+
+// Both free flights of a pair (words x, y for the first, z, w for the second)
+// in the all-local instantiation.  The same flights as two calls of
+// flight_local, but the walk is set up once: after a null collision the
+// second flight goes on along the same line from the same cube, whose face
+// distances and crossings left stay valid (the distances re-based to the
+// null collision).  Cube records are the LDS words (density bound and table
+// row; a cube without a row takes its material mask from the global record).
+template <int MODE>
+__device__ __forceinline__ void flight_pair_all_local(const KParams& P, const Tables& T, const DVolume& V, int vo,
+                                                      Photon& ph, const Block& b, const uint32_t* lds_rec) {
+    const float p0x = ph.px, p0y = ph.py, p0z = ph.pz;     // (for the set-up only)
+    int bx = min(max((int)floorf((p0x - V.lox) * V.imx), 0), V.mnx - 1);
+    int by = min(max((int)floorf((p0y - V.loy) * V.imy), 0), V.mny - 1);
+    int bz = min(max((int)floorf((p0z - V.loz) * V.imz), 0), V.mnz - 1);
+    const float rx = ph.dx != 0.0f ? fast_rcp(ph.dx) : 0.0f;
+    const float ry = ph.dy != 0.0f ? fast_rcp(ph.dy) : 0.0f;
+    const float rz = ph.dz != 0.0f ? fast_rcp(ph.dz) : 0.0f;
+    const int sx = ph.dx > 0.0f ? 1 : (ph.dx < 0.0f ? -1 : 0);
+    const int sy = ph.dy > 0.0f ? 1 : (ph.dy < 0.0f ? -1 : 0);
+    const int sz = ph.dz > 0.0f ? 1 : (ph.dz < 0.0f ? -1 : 0);
+    // where the line leaves the box through a face on the positive side of an axis (the last
+    // cube there may reach past the face); leaving through a negative side is leaving the grid
+    float tex = fminf(sx > 0 ? (V.hix - p0x) * rx : INFINITY,
+                      fminf(sy > 0 ? (V.hiy - p0y) * ry : INFINITY, sz > 0 ? (V.hiz - p0z) * rz : INFINITY));
+    float tmx = sx > 0 ? (V.lox + (float)(bx + 1) * V.mex - p0x) * rx
+              : (sx < 0 ? (V.lox + (float)bx * V.mex - p0x) * rx : INFINITY);
+    float tmy = sy > 0 ? (V.loy + (float)(by + 1) * V.mey - p0y) * ry
+              : (sy < 0 ? (V.loy + (float)by * V.mey - p0y) * ry : INFINITY);
+    float tmz = sz > 0 ? (V.loz + (float)(bz + 1) * V.mez - p0z) * rz
+              : (sz < 0 ? (V.loz + (float)bz * V.mez - p0z) * rz : INFINITY);
+    const float dtx = V.mex * fabsf(rx), dty = V.mey * fabsf(ry), dtz = V.mez * fabsf(rz);
+    const float2* tot = T.tot + ph.ec.j * P.tot_rows;
+    const int cix = sx, ciy = sy * V.mnx, ciz = sz * V.mnx * V.mny;
+    int ci = (bz * V.mny + by) * V.mnx + bx;
+    // the crossings left along each axis's direction of travel before the line leaves the
+    // grid (at most 512 cubes per axis), in 10-bit fields whose top bit is a guard that the
+    // crossing past the last cube clears
+    uint32_t left = ((512u + (uint32_t)(sx > 0 ? V.mnx - 1 - bx : (sx < 0 ? bx : 511)))) |
+                    ((512u + (uint32_t)(sy > 0 ? V.mny - 1 - by : (sy < 0 ? by : 511))) << 10) |
+                    ((512u + (uint32_t)(sz > 0 ? V.mnz - 1 - bz : (sz < 0 ? bz : 511))) << 20);
+    constexpr uint32_t kGuards = (1u << 9) | (1u << 19) | (1u << 29);
+    float t = 0.0f;
+    for (int f = 0; f < 2; ++f) {
+        if (ph.step >= kMaxSteps) {
+            if (MODE == kModeTrace) trace_out<MODE>(P, ph, kLost, -1);
+            ph.st = kDead;
+            return;
+        }
+        ph.step += 1;
+        float tau = -fast_log(u24(f == 0 ? b.x : b.z));
+        float mb = 0.0f;
+        bool hit = false;
+        // (selects instead of fminf/fmaxf below: no NaN can occur, and these need
+        // no canonicalisation of their operands)
+        for (;;) {
+            const uint32_t w = lds_rec[ci];
+            const uint32_t row = w & 31u;
+            float tmax;
+            if (row != kNoRow) {
+                const float2 tt = tot[row];
+                tmax = tt.x + ph.ec.f * tt.y;
+            } else {
+                tmax = set_bound(tot, P.tot_rows, V.macro[ci].y, ph.ec.f);
+            }
+            mb = __uint_as_float(w & ~31u) * tmax;
+            const float tnext = fminf(tmx, fminf(tmy, tmz));
+            const float tn = tnext < tex ? tnext : tex;                    // the cube's exit, within the box
+            const float span = tn - t;
+            const float need = 0.1f * mb * (span > 0.0f ? span : 0.0f);   // mbar in 1/cm, lengths in mm
+            if (mb > 0.0f && tau < need) {
+                t += tau * fast_rcp(0.1f * mb);
+                hit = true;
+                break;
+            }
+            tau -= need;
+            t = tn > t ? tn : t;
+            if (!(tn < tex)) break;                                        // left the box
+            const bool ax = tmx <= tmy && tmx <= tmz, ay = !ax && tmy <= tmz, az = !ax && !ay;
+            ci += ax ? cix : (ay ? ciy : ciz);
+            tmx = ax ? tmx + dtx : tmx;
+            tmy = ay ? tmy + dty : tmy;
+            tmz = az ? tmz + dtz : tmz;
+            left -= ax ? 1u : (ay ? 1u << 10 : 1u << 20);
+            if ((left & kGuards) != kGuards) break;                       // left the grid
+        }
+        ph.px += t * ph.dx;
+        ph.py += t * ph.dy;
+        ph.pz += t * ph.dz;
+        if (!hit) {
+            int pixel;
+            const int cls = detector_pixel(P.jobs[ph.job], ph, pixel);
+            finish<MODE>(P, T, V, vo, ph, cls, pixel);
+            return;
+        }
+        int m;
+        const float rho = cell_density(V, true, ph.px, ph.py, ph.pz, m);
+        m = m < P.n_mat ? m : P.n_mat - 1;
+        const float2 tt = T.tot[ph.ec.j * P.tot_rows + m];
+        const float tot_m = tt.x + ph.ec.f * tt.y;
+        const float ladder = u24(f == 0 ? b.y : b.w) * mb;
+        const bool real = ladder < rho * tot_m;
+        if (MODE == kModeBackward && ph.passb) visit(P, V, true, ph, real, rho, tot_m, mb);
+        if (real) {
+            ph.st = kColl;
+            ph.sel = ladder * fast_rcp(rho);
+            ph.pm = m;
+            return;
+        }
+        // a null collision: the second flight starts here, the distances re-based to it
+        tmx -= t;
+        tmy -= t;
+        tmz -= t;
+        tex -= t;
+        t = 0.0f;
+    }
 }
 
 // A real collision (Sec. 2.4): the ladder value picks Rayleigh, Compton or
@@ -785,8 +898,14 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
             const Block b = philox(ph.pid, ph.jid, ph.pair, 0u, P.k0, P.k1);
             if constexpr (LOCAL == 3) {
                 const uint32_t* lr = reinterpret_cast<const uint32_t*>(lds_rec) + P.macro_lds[w_vol];
-                if (flight_local<MODE, 2>(P, T, V, vo, interp, ph, b.x, b.y, lr))
-                    flight_local<MODE, 2>(P, T, V, vo, interp, ph, b.z, b.w, lr);
+                // the adjoint keeps two walks a pair: the one walk's state across the
+                // collision test and its gradient visit would spill its registers
+                if constexpr (MODE == kModeBackward) {
+                    if (flight_local<MODE, 2>(P, T, V, vo, interp, ph, b.x, b.y, lr))
+                        flight_local<MODE, 2>(P, T, V, vo, interp, ph, b.z, b.w, lr);
+                } else {
+                    flight_pair_all_local<MODE>(P, T, V, vo, ph, b, lr);
+                }
             } else if (LOCAL == 2 && V.macro) {
                 const uint2* lr = reinterpret_cast<const uint2*>(lds_rec) + P.macro_lds[w_vol];
                 if (flight_local<MODE, 1>(P, T, V, vo, interp, ph, b.x, b.y, lr))
