@@ -69,8 +69,9 @@ SLOTS_SELECT = slots(i=2, f=4)                        # interaction type, at eve
 SLOTS_COLLISION = SLOTS_SELECT + slots(i=11, f=54, t=10)   # + sampler constants, rotation, energy cache
 SLOTS_BOX_EXIT = slots(i=6, f=28, t=3)                # single majorant only: distance to the box
 SLOTS_SOURCE = 2 * SLOTS_PHILOX + slots(i=50, f=55, t=4)   # two blocks, CDFs (fp64), aim point, box entry
-# local majorants: every flight first sets up its walk (cube coordinates, three
-# reciprocals, steps, exit-face distances), then visits cubes (its first, and
+# local majorants: every pair of flights first sets up its walk (cube coordinates,
+# three reciprocals, steps, exit-face distances; the second flight goes on along
+# the same walk), then each flight visits cubes (the one it starts in, and
 # one per face crossed): record word address and load, the bound from the row of
 # the material-set table it names, spend or stop, advance, step the cube index
 SLOTS_WALK = slots(i=30, f=42, t=3)
@@ -100,7 +101,7 @@ def work_per_history(stats, n):
     local = crossings > 0
     slots = (pairs * SLOTS_PHILOX + inbox * SLOTS_FLIGHT_IN + escapes * SLOTS_FLIGHT_OUT + tries * SLOTS_TRY
              + real * SLOTS_SELECT + scatter_events * (SLOTS_COLLISION - SLOTS_SELECT + (0 if local else SLOTS_BOX_EXIT))
-             + SLOTS_SOURCE + (flights * SLOTS_WALK + cubes * SLOTS_CUBE if local else 0.0))
+             + SLOTS_SOURCE + (pairs * SLOTS_WALK + cubes * SLOTS_CUBE if local else 0.0))
     nbytes = inbox * BYTES_FLIGHT_IN + BYTES_SOURCE + scored * BYTES_SCORE + cubes * BYTES_CUBE
     return dict(slots=slots, bytes=nbytes, flights=flights, inbox_flights=inbox, real=real, tries=tries,
                 cube_visits=cubes)

@@ -81,8 +81,8 @@ def test_work_model_composition():
     base = (pairs * bench.SLOTS_PHILOX + 6.6 * bench.SLOTS_FLIGHT_IN + 0.4 * bench.SLOTS_FLIGHT_OUT
             + 2.9 * bench.SLOTS_TRY + 2.5 * bench.SLOTS_SELECT + 2.1 * (bench.SLOTS_COLLISION - bench.SLOTS_SELECT)
             + bench.SLOTS_SOURCE)
-    # local majorants: a walk set-up per flight and the cube visits, no box exit after a collision
-    assert w["slots"] == pytest.approx(base + 7.0 * bench.SLOTS_WALK + 18.0 * bench.SLOTS_CUBE)
+    # local majorants: a walk set-up per pair of flights and the cube visits, no box exit after a collision
+    assert w["slots"] == pytest.approx(base + pairs * bench.SLOTS_WALK + 18.0 * bench.SLOTS_CUBE)
     nbytes = 6.6 * bench.BYTES_FLIGHT_IN + bench.BYTES_SOURCE + 0.005 * bench.BYTES_SCORE + 18.0 * bench.BYTES_CUBE
     assert w["bytes"] == pytest.approx(nbytes)
     # the single majorant: no cube walk, and every scattering recomputes the distance to the box
