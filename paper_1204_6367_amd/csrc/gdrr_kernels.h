@@ -929,18 +929,21 @@ __device__ __forceinline__ void mc_body(const KParams& P) {
     }
 }
 
-// The forward and trace transport: at most 80 VGPRs (6 wavefronts per SIMD;
-// the all-local instantiation takes 59, which allows 8).
+// The forward and trace transport: at most 80 VGPRs (6 wavefronts per SIMD);
+// the all-local forward at most 64 (8 wavefronts per SIMD, without spills),
+// which the 1024-thread workgroups, two per compute unit, then use.
 template <int MODE, int LOCAL>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(6))) void mc_kernel(KParams P) {
+__global__ __launch_bounds__(1024)
+__attribute__((amdgpu_waves_per_eu(MODE == kModeForward && LOCAL == 3 ? 8 : 6))) void mc_kernel(KParams P) {
     mc_body<MODE, LOCAL>(P);
 }
 
 // The adjoint: at most 96 VGPRs (5 wavefronts per SIMD), where it would
-// otherwise take 97 and drop to 4; the all-local instantiation at most 80
-// (it takes 65).
+// otherwise take 97 and drop to 4; the all-local instantiation at most 64 (8
+// wavefronts per SIMD; it would take 70, and the 44 bytes it spills cost less
+// than the occupancy: 5.38e9 against 5.11e9 histories/s at 6).
 template <int LOCAL>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LOCAL == 3 ? 6 : 5))) void mc_adjoint_kernel(
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(LOCAL == 3 ? 8 : 5))) void mc_adjoint_kernel(
     KParams P) {
     mc_body<kModeBackward, LOCAL>(P);
 }
