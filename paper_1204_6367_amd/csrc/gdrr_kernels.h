@@ -474,7 +474,7 @@ __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, 
         const float tn = tnext < tex ? tnext : tex;                    // the cube's exit, within the box
         const float span = tn - t;
         const float need = 0.1f * mb * (span > 0.0f ? span : 0.0f);   // mbar in 1/cm, lengths in mm
-        if (mb > 0.0f && tau < need) {
+        if (tau < need) {                                                // (need = 0 when mb = 0: tau > 0)
             t += tau * fast_rcp(0.1f * mb);
             hit = true;
             break;
@@ -482,7 +482,8 @@ __device__ __forceinline__ bool flight_local(const KParams& P, const Tables& T, 
         tau -= need;
         t = tn > t ? tn : t;
         if (!(tn < tex)) break;                                        // left the box
-        const bool ax = tmx <= tmy && tmx <= tmz, ay = !ax && tmy <= tmz, az = !ax && !ay;
+        // the axis of the nearest face (ties to x, then y)
+        const bool ax = tmx == tnext, ay = !ax && tmy == tnext, az = !ax && !ay;
         ci += ax ? cix : (ay ? ciy : ciz);
         tmx = ax ? tmx + dtx : tmx;
         tmy = ay ? tmy + dty : tmy;
@@ -594,7 +595,7 @@ __device__ __forceinline__ void flight_pair_all_local(const KParams& P, const Ta
             const float tn = tnext < tex ? tnext : tex;                    // the cube's exit, within the box
             const float span = tn - t;
             const float need = 0.1f * mb * (span > 0.0f ? span : 0.0f);   // mbar in 1/cm, lengths in mm
-            if (mb > 0.0f && tau < need) {
+            if (tau < need) {                                            // (need = 0 when mb = 0: tau > 0)
                 t += tau * fast_rcp(0.1f * mb);
                 hit = true;
                 break;
@@ -602,7 +603,8 @@ __device__ __forceinline__ void flight_pair_all_local(const KParams& P, const Ta
             tau -= need;
             t = tn > t ? tn : t;
             if (!(tn < tex)) break;                                        // left the box
-            const bool ax = tmx <= tmy && tmx <= tmz, ay = !ax && tmy <= tmz, az = !ax && !ay;
+            // the axis of the nearest face (ties to x, then y)
+            const bool ax = tmx == tnext, ay = !ax && tmy == tnext, az = !ax && !ay;
             ci += ax ? cix : (ay ? ciy : ciz);
             tmx = ax ? tmx + dtx : tmx;
             tmy = ay ? tmy + dty : tmy;
