@@ -681,8 +681,9 @@ int run_batch(const Batch& B, void* ws, size_t ws_bytes, hipStream_t st) {
                            cubes(V.ny, V.macro), cubes(V.nz, V.macro), phys->n_mat,
                            1.0 + (double)V.macro_margin, V.macro_rho_min, L.macro[v]};
             const size_t nm = (size_t)mp.mnx * mp.mny * mp.mnz;
+            // one workgroup of 256 per cube
             ls.push_back(make_launch((const void*)&macro_kernel,
-                                     dim3((unsigned)std::max<size_t>(1, std::min<size_t>((size_t)dev.cus * 8, (nm + 255) / 256))),
+                                     dim3((unsigned)std::max<size_t>(1, std::min<size_t>((size_t)dev.cus * 16, nm))),
                                      dim3(256), 0, mp));
         }
     }

@@ -1046,26 +1046,50 @@ struct MacroParams {
     uint2* out;
 };
 
+// One workgroup per cube (grid-stride over the cubes): the lanes stride over
+// the voxels of the cube grown by one voxel, x fastest (coalesced), then the
+// largest density and the union of the materials are reduced over the
+// workgroup.  Max and or are exact in any order, so the records are those of
+// a plain loop over the voxels.
 __global__ __launch_bounds__(256) void macro_kernel(MacroParams M) {
+    __shared__ float s_r[4];
+    __shared__ uint32_t s_m[4];
     const long long n = (long long)M.mnx * M.mny * M.mnz;
-    for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n; c += (long long)gridDim.x * blockDim.x) {
+    for (long long c = blockIdx.x; c < n; c += gridDim.x) {
         const int bx = (int)(c % M.mnx), by = (int)((c / M.mnx) % M.mny), bz = (int)(c / ((long long)M.mnx * M.mny));
         const int x0 = max(bx * M.mcube - 1, 0), x1 = min((bx + 1) * M.mcube, M.nx - 1);
         const int y0 = max(by * M.mcube - 1, 0), y1 = min((by + 1) * M.mcube, M.ny - 1);
         const int z0 = max(bz * M.mcube - 1, 0), z1 = min((bz + 1) * M.mcube, M.nz - 1);
+        const int nxc = x1 - x0 + 1, nyc = y1 - y0 + 1;
+        const int nv = nxc * nyc * (z1 - z0 + 1);
         float r = M.rho_min;
         uint32_t mask = 0u;
-        for (int z = z0; z <= z1; ++z)
-            for (int y = y0; y <= y1; ++y) {
-                const long long row = ((long long)z * M.ny + y) * M.nx;
-                for (int x = x0; x <= x1; ++x) {
-                    r = fmaxf(r, clean_density(M.density[row + x]));
-                    mask |= 1u << min((int)M.material[row + x], M.n_mat - 1);
-                }
+        for (int i = threadIdx.x; i < nv; i += blockDim.x) {
+            const int x = x0 + i % nxc, rest = i / nxc;
+            const int y = y0 + rest % nyc, z = z0 + rest / nyc;
+            const long long v = ((long long)z * M.ny + y) * M.nx + x;
+            r = fmaxf(r, clean_density(M.density[v]));
+            mask |= 1u << min((int)M.material[v], M.n_mat - 1);
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            r = fmaxf(r, __shfl_xor(r, o));
+            mask |= __shfl_xor(mask, o);
+        }
+        if ((threadIdx.x & 63) == 0) {
+            s_r[threadIdx.x >> 6] = r;
+            s_m[threadIdx.x >> 6] = mask;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+                r = fmaxf(r, s_r[w]);
+                mask |= s_m[w];
             }
-        // the density factor rounded up to 19 significant bits: the low 5 bits stay free
-        const uint32_t rb = __float_as_uint(__double2float_ru((double)r * M.scale));
-        M.out[c] = make_uint2((rb + 31u) & ~31u, mask);
+            // the density factor rounded up to 19 significant bits: the low 5 bits stay free
+            const uint32_t rb = __float_as_uint(__double2float_ru((double)r * M.scale));
+            M.out[c] = make_uint2((rb + 31u) & ~31u, mask);
+        }
+        __syncthreads();
     }
 }
 
